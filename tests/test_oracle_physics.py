@@ -1,0 +1,328 @@
+"""Pins of the oracle solver against closed forms and exact discrete invariants.
+
+The paper gives no traces to compare with (it makes no accuracy comparison,
+Sec. VII), so every pin here is fixed by the mathematics of eq. 2-4 and the
+staggered leapfrog scheme (Sec. II-A):
+ * exact periodic plane P and S waves (dispersion relation and impedances);
+ * exact conservation of the discrete energy with the PML off;
+ * exact reciprocity of explosive source / pressure receiver pairs;
+ * linearity and time-translation of the response (Sec. IV);
+ * the whole-space pressure of an explosive point source (textbook);
+ * far-field P radiation patterns of DC and CLVD sources (Sec. V);
+ * the CFL guard (eq. 5), checkpoint / resume.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1705_04874_amd import inputs
+from tests import physics
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("wave", ["P", "S"])
+@pytest.mark.parametrize("kspace", [0, 1])
+def test_plane_wave_is_exact(wave, kspace):
+    shape = (10, 12, 16)                   # [z][y][x]
+    h = (10.0, 12.5, 8.0)
+    vp, vs, rho = 3000.0, 1700.0, 2300.0
+    dt = 0.4e-3
+    m = (3, 2, 1)
+    c_ref = 3000.0
+    s = oracle.Solver(np.full(shape, vp), np.full(shape, vs), np.full(shape, rho), h, dt, pml=0,
+                      kspace=kspace, c_ref=c_ref)
+    s.set_sources(np.zeros((0, 3)), np.zeros((0, 6)), np.zeros((0, 1)))
+    s.set_state(physics.plane_wave_state(shape, h, dt, m, wave, vp, vs, rho, 0, kspace, c_ref))
+    s.run(40)
+    want = physics.plane_wave_state(shape, h, dt, m, wave, vp, vs, rho, 40, kspace, c_ref)
+    got = physics.summed(s.get_state())
+    want = physics.summed(want)
+    vscale = max(np.abs(b).max() for b in want[:3])
+    sscale = max(np.abs(b).max() for b in want[3:])
+    for i, (a, b) in enumerate(zip(got, want)):
+        scale = vscale if i < 3 else sscale
+        assert np.abs(a - b).max() < 1e-10 * scale, i
+
+
+def test_plane_wave_wrong_speed_fails():
+    """Control: the same comparison against a wave with a 1 % slower speed fails,
+    so the plane-wave pin has the resolution to see a wrong material constant."""
+    shape = (10, 12, 16)
+    h = (10.0, 12.5, 8.0)
+    vp, vs, rho, dt = 3000.0, 1700.0, 2300.0, 0.4e-3
+    s = oracle.Solver(np.full(shape, vp), np.full(shape, vs), np.full(shape, rho), h, dt, pml=0,
+                      kspace=1, c_ref=vp)
+    s.set_sources(np.zeros((0, 3)), np.zeros((0, 6)), np.zeros((0, 1)))
+    s.set_state(physics.plane_wave_state(shape, h, dt, (3, 2, 1), "P", vp, vs, rho, 0, 1, vp))
+    s.run(40)
+    wrong = physics.plane_wave_state(shape, h, dt, (3, 2, 1), "P", 0.99 * vp, vs, rho, 40, 1, vp)
+    assert rel(physics.summed(s.get_state())[0], physics.summed(wrong)[0]) > 1e-3
+
+
+# ---------------------------------------------------------------------------
+def hetero_model(shape, seed, fluid_top=0):
+    rng = np.random.default_rng(seed)
+    nz = shape[0]
+    vp = 2500 + 800 * rng.random(shape)
+    vs = vp / (1.7 + 0.2 * rng.random(shape))
+    rho = 1800 + 700 * rng.random(shape)
+    if fluid_top:
+        vp[:fluid_top] = 1500
+        vs[:fluid_top] = 0
+        rho[:fluid_top] = 1000
+    return vp, vs, rho
+
+
+@pytest.mark.parametrize("kspace", [0, 1])
+def test_energy_conserved_without_pml(kspace):
+    shape = (12, 10, 14)
+    h = (10.0, 10.0, 10.0)
+    vp, vs, rho = hetero_model(shape, 7, fluid_top=4)
+    dt = 0.25 * h[0] / vp.max()
+    s = oracle.Solver(vp, vs, rho, h, dt, pml=0, kspace=kspace, c_ref=vp.max())
+    s.set_sources(np.zeros((0, 3)), np.zeros((0, 6)), np.zeros((0, 1)))
+    rng = np.random.default_rng(11)
+    st = np.zeros((24,) + shape)
+    st[0] = rng.standard_normal(shape) * 1e-3
+    st[4] = rng.standard_normal(shape) * 1e-3
+    st[8] = rng.standard_normal(shape) * 1e-3
+    s.set_state(st)
+    energies = []
+    before = s.get_state()
+    for n in range(30):
+        s.run(1)
+        after = s.get_state()
+        energies.append(physics.discrete_energy(before, after, vp, vs, rho))
+        before = after
+    e = np.array(energies)
+    assert e[0] > 0
+    assert np.abs(e / e[0] - 1).max() < 1e-11
+
+
+def test_energy_decays_with_pml():
+    shape = (24, 24, 24)
+    h = (10.0, 10.0, 10.0)
+    vp, vs, rho = [np.full(shape, v) for v in (3000.0, 1700.0, 2300.0)]
+    dt = 1e-3
+    s = oracle.Solver(vp, vs, rho, h, dt, pml=6, kspace=1)
+    s.set_sources(np.array([[12, 12, 12]]), inputs.explosive(1000.0)[None],
+                  inputs.ricker(40.0, dt, 60)[None])
+    e = []
+    before = s.get_state()
+    for n in range(160):
+        s.run(1)
+        after = s.get_state()
+        if n >= 60:
+            e.append(physics.discrete_energy(before, after, vp, vs, rho))
+        before = after
+    e = np.array(e)
+    assert e[-1] < 0.05 * e[0]
+
+
+# ---------------------------------------------------------------------------
+def test_reciprocity_explosive_pressure():
+    shape = (14, 12, 16)
+    h = (10.0, 10.0, 10.0)
+    vp, vs, rho = hetero_model(shape, 3, fluid_top=3)
+    dt = 0.8e-3
+    a = np.array([4, 3, 9])
+    b = np.array([11, 8, 5])
+    nt = 120
+    w = inputs.ricker(35.0, dt, nt)
+    outs = []
+    for src, rec in [(a, b), (b, a)]:
+        s = oracle.Solver(vp, vs, rho, h, dt, pml=0, kspace=1, rec=rec[None])
+        s.set_sources(src[None], inputs.explosive(1000.0)[None], w[None])
+        outs.append(s.run(nt)[0, 0])
+    mu = rho * vs * vs
+    K = rho * vp * vp - 4.0 / 3.0 * mu
+    Ka = K[a[2], a[1], a[0]]
+    Kb = K[b[2], b[1], b[0]]
+    lhs = Ka * outs[0]
+    rhs = Kb * outs[1]
+    assert np.abs(lhs).max() > 0
+    assert np.abs(lhs - rhs).max() < 1e-10 * np.abs(lhs).max()
+
+
+# ---------------------------------------------------------------------------
+def small_setup(seed=1, nt=80):
+    shape = (16, 14, 18)
+    h = (10.0, 10.0, 10.0)
+    vp, vs, rho = hetero_model(shape, seed, fluid_top=4)
+    dt = 0.8e-3
+    rec = inputs.receiver_block(3, 15, 4, 10, 4)
+    return shape, h, vp, vs, rho, dt, rec
+
+
+def test_linearity_and_scaling():
+    shape, h, vp, vs, rho, dt, rec = small_setup()
+    nt = 80
+    w = inputs.ricker(30.0, dt, nt)
+    A = (np.array([[8, 7, 10]]), inputs.double_couple(0.3, 0.7, 1.1, 1000.0)[None])
+    B = (np.array([[5, 9, 12]]), inputs.clvd(500.0)[None])
+
+    def run(ijk, m6):
+        s = oracle.Solver(vp, vs, rho, h, dt, pml=4, kspace=1, rec=rec)
+        s.set_sources(ijk, m6, np.repeat(w[None], len(ijk), 0))
+        return s.run(nt)
+
+    ta = run(*A)
+    tb = run(*B)
+    tab = run(np.concatenate([A[0], B[0]]), np.concatenate([A[1], B[1]]))
+    assert rel(ta + tb, tab) < 1e-12
+    t2 = run(A[0], 2.5 * A[1])
+    assert rel(2.5 * ta, t2) < 1e-12
+
+
+def test_time_shift():
+    shape, h, vp, vs, rho, dt, rec = small_setup()
+    nt, lag = 90, 17
+    w = inputs.ricker(30.0, dt, nt)
+    wl = np.concatenate([np.zeros(lag), w[:nt - lag]])
+    src = np.array([[8, 7, 10]])
+    m6 = inputs.double_couple(1.0, 0.4, -0.5, 1000.0)[None]
+    outs = []
+    for ww in (w, wl):
+        s = oracle.Solver(vp, vs, rho, h, dt, pml=4, kspace=1, rec=rec)
+        s.set_sources(src, m6, ww[None])
+        outs.append(s.run(nt))
+    a, b = outs
+    assert np.abs(b[..., :lag]).max() == 0.0
+    assert rel(b[..., lag:], a[..., :nt - lag]) < 1e-12
+
+
+def test_checkpoint_resume():
+    shape, h, vp, vs, rho, dt, rec = small_setup()
+    nt = 60
+    w = inputs.ricker(30.0, dt, nt)
+    src = np.array([[8, 7, 10]])
+    m6 = inputs.double_couple(1.0, 0.4, -0.5, 1000.0)[None]
+    s = oracle.Solver(vp, vs, rho, h, dt, pml=4, kspace=1, rec=rec)
+    s.set_sources(src, m6, w[None])
+    full = s.run(nt)
+    s1 = oracle.Solver(vp, vs, rho, h, dt, pml=4, kspace=1, rec=rec)
+    s1.set_sources(src, m6, w[None])
+    first = s1.run(25)
+    st = s1.get_state()
+    s2 = oracle.Solver(vp, vs, rho, h, dt, pml=4, kspace=1, rec=rec)
+    s2.set_sources(src, m6, w[None])
+    s2.set_state(st)
+    s2.step = 25
+    second = s2.run(nt - 25)
+    np.testing.assert_array_equal(np.concatenate([first, second], axis=2), full)
+
+
+# ---------------------------------------------------------------------------
+def test_cfl_guard_and_bad_inputs():
+    shape = (8, 8, 8)
+    vp, vs, rho = [np.full(shape, v) for v in (3000.0, 1700.0, 2300.0)]
+    h = (10.0, 10.0, 10.0)
+    # kspace off: c dt sqrt(3)/h must stay below 2/pi
+    limit = 2 / math.pi * h[0] / (3000.0 * math.sqrt(3))
+    oracle.Solver(vp, vs, rho, h, 0.99 * limit, kspace=0)
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.Solver(vp, vs, rho, h, 1.01 * limit, kspace=0)
+    assert e.value.code == oracle.ORC_EUNSTABLE
+    # kspace on with c_ref >= max vp: any dt is stable
+    oracle.Solver(vp, vs, rho, h, 5 * limit, kspace=1)
+    bad = vp.copy()
+    bad[1, 2, 3] = np.nan
+    with pytest.raises(oracle.OracleError) as e:
+        oracle.Solver(bad, vs, rho, h, 1e-3)
+    assert e.value.code == oracle.ORC_EINVAL
+    with pytest.raises(oracle.OracleError):
+        oracle.Solver(vp, vs, rho, h, 1e-3, rec=np.array([[0, 0, 8]]))
+
+
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def homogeneous_runs():
+    """Explosive, DC and CLVD sources at the centre of a homogeneous 48^3 grid."""
+    n = 48
+    vp, vs, rho = 3000.0, 1700.0, 2400.0
+    h = (10.0, 10.0, 10.0)
+    dt = 1e-3
+    f0 = 20.0
+    nt = 150
+    c = n // 2
+    offs = [(12, 0, 0), (0, 12, 0), (-12, 0, 0), (0, -12, 0), (0, 0, 12), (0, 0, -12),
+            (9, 9, 0), (9, -9, 0), (-9, 9, 0), (-9, -9, 0), (16, 0, 0), (0, 0, 16)]
+    rec = np.array([[c + o[0], c + o[1], c + o[2]] for o in offs], np.int32)
+    m = inputs.homogeneous(n, n, n, vp, vs, rho)
+    w = inputs.ricker(f0, dt, nt)
+    out = {}
+    for name, m6 in [("exp", inputs.explosive(1000.0)), ("dc", inputs.dc_xy(1000.0)),
+                     ("clvd", inputs.clvd(1000.0))]:
+        s = oracle.Solver(m.vp, m.vs, m.rho, h, dt, pml=10, kspace=1, rec=rec)
+        s.set_sources(np.array([[c, c, c]]), m6[None], w[None])
+        out[name] = s.run(nt)
+    return dict(out=out, offs=offs, vp=vp, vs=vs, rho=rho, dt=dt, f0=f0, nt=nt, h=h)
+
+
+def test_explosion_matches_whole_space_green_function(homogeneous_runs):
+    R = homogeneous_runs
+    p = R["out"]["exp"][0]
+    t = (np.arange(R["nt"]) + 1) * R["dt"]
+    for i, o in enumerate(R["offs"]):
+        r = math.sqrt(sum(q * q for q in o)) * R["h"][0]
+        ana = physics.explosion_pressure(t, r, 1000.0, R["vp"], R["vs"], R["rho"], R["f0"])
+        win = (t > r / R["vp"]) & (t < r / R["vp"] + 3.0 / R["f0"])
+        win |= t < r / R["vp"]   # quiet before the arrival
+        assert rel(p[i][win], ana[win]) < 0.02, (o, rel(p[i][win], ana[win]))
+
+
+def test_radiation_patterns(homogeneous_runs):
+    """Far-field P polarity follows gamma.M.gamma: DC tau_xy ~ sin(2 phi) in the
+    xy-plane (opposite signs on the two diagonals), nodal on the axes; CLVD
+    diag(1,1,-2) is reversed overhead with twice the amplitude (Sec. V)."""
+    R = homogeneous_runs
+    offs = R["offs"]
+    t = (np.arange(R["nt"]) + 1) * R["dt"]
+
+    def peak(tr, o=(12, 0, 0)):
+        # signed amplitude: projection on the explosion's pressure waveform at
+        # the same distance (p of any trace-free tensor has the same time
+        # function times gamma.M.gamma)
+        r = math.sqrt(sum(q * q for q in o)) * R["h"][0]
+        ref = physics.explosion_pressure(t, r, 1000.0, R["vp"], R["vs"], R["rho"], R["f0"])
+        return float(np.dot(tr, ref) / np.dot(ref, ref))
+
+    dc = R["out"]["dc"][0]
+    diag = {o: peak(dc[offs.index(o)], o) for o in [(9, 9, 0), (9, -9, 0), (-9, 9, 0), (-9, -9, 0)]}
+    assert diag[(9, 9, 0)] > 0 and diag[(-9, -9, 0)] > 0
+    assert diag[(9, -9, 0)] < 0 and diag[(-9, 9, 0)] < 0
+    amp = abs(diag[(9, 9, 0)])
+    for o in [(12, 0, 0), (0, 12, 0), (-12, 0, 0), (0, -12, 0)]:
+        assert abs(peak(dc[offs.index(o)])) < 0.05 * amp
+    for o in [(9, -9, 0), (-9, 9, 0), (-9, -9, 0)]:
+        assert abs(abs(diag[o]) / amp - 1) < 1e-6
+    cl = R["out"]["clvd"][0]
+    up = peak(cl[offs.index((0, 0, -12))], (0, 0, -12))
+    side = peak(cl[offs.index((12, 0, 0))], (12, 0, 0))
+    assert side > 0 > up
+    assert abs(up / side + 2.0) < 0.05
+    ex = R["out"]["exp"][0]
+    vals = [peak(ex[offs.index(o)], o) for o in [(12, 0, 0), (0, 12, 0), (0, 0, 12), (0, 0, -12)]]
+    assert min(vals) > 0.98 and max(vals) / min(vals) < 1 + 1e-4
+
+
+def test_shear_dominates_for_dc(homogeneous_runs):
+    """DC sources radiate most energy as S waves, explosions as P waves (Sec. V-B)."""
+    R = homogeneous_runs
+    i = R["offs"].index((16, 0, 0))
+    r = 160.0
+    t = (np.arange(R["nt"]) + 0.5) * R["dt"]
+    ts = r / R["vs"]
+    tp = r / R["vp"]
+    sw = (t > ts) & (t < ts + 2.5 / R["f0"])
+    pw = (t > tp) & (t < tp + 2.5 / R["f0"])
+    vy_dc = R["out"]["dc"][2][i]
+    vx_ex = R["out"]["exp"][1][i]
+    assert np.abs(vy_dc[sw]).max() > 5 * np.abs(vy_dc[pw & ~sw]).max()
+    assert np.abs(vx_ex[pw]).max() > 20 * np.abs(R["out"]["exp"][2][i]).max()
