@@ -1,0 +1,196 @@
+#!/usr/bin/env python3
+"""Benchmark: Gcell-steps/s of the FP32 pseudo-spectral elastic solver on one GPU.
+
+Workload (default): the 128^3 layered marine model (water over 6 sediment
+layers with a seeded +-5 % correlated perturbation), dx = 10 m, dt = 0.8 ms,
+16-cell PML, one double-couple source with a 25 Hz Ricker wavelet, 64 x 64
+four-component seabed receivers, 2000 leapfrog steps.  One bench step is one
+complete shot: reset of the state and 2000 time steps through the HIP kernels
+(spectral derivatives, split-PML updates, source injection, receiver
+gathers), with the model tables already resident in HBM.
+
+Prints one JSON line with the throughput, the roofline position of the
+dominant kernel (HIP-event timing over the timed region) and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_bytes_per_cell(nx, nxh):
+    """Algorithmic HBM bytes per cell and launch for each kernel kind (one shot):
+    every input read once and every output written once; half spectra count
+    nxh/nx complex values per cell (8 bytes each), real fields 4 bytes."""
+    S = 8.0 * nxh / nx
+    R = 4.0
+    K = 4.0 * nxh / nx  # kappa table
+    return {
+        "y_fwd_stress": 6 * 2 * S,
+        "z_op_V": 6 * S + 9 * S + K,
+        "y_inv_V": 9 * 2 * S,
+        "vel_update": 9 * S + 2 * 9 * R + 3 * R + 3 * S,
+        "y_fwd_vel": 3 * 2 * S,
+        "z_op_S": 3 * S + 9 * S + K,
+        "y_inv_S": 9 * 2 * S,
+        "stress_update": 9 * S + 2 * 15 * R + 5 * R + 6 * S,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed shots")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed shots")
+    ap.add_argument("--nt", type=int, default=2000, help="time steps per shot")
+    ap.add_argument("--workload", default="c1", choices=["c1", "c2"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle sample time")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 1 GiB device copy first (reference kernel for HBM counters)")
+    ap.add_argument("--no-profile", action="store_true", help="time without per-kernel events")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus > 1 or world > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(shots would shard across GPUs with no exchange); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1705_04874_amd import binding, inputs
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    w = inputs.c1_workload(nt=args.nt) if args.workload == "c1" else inputs.c2_workload(nt=args.nt)
+    nz, ny, nx = w.model.shape
+    cells = nx * ny * nz
+    s = binding.Solver.from_workload(w)
+    s.set_workload_sources(w)
+    traces = torch.empty((s.n_shots, 4, s.n_rec, args.nt), dtype=torch.float32, device=dev)
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_read": a.numel() * 4,
+                          "copy_calibration_bytes_written": b.numel() * 4}), file=sys.stderr, flush=True)
+        del a, b
+
+    for i in range(args.warmup):
+        s.reset()
+        s.run(args.nt, out=traces)
+        print(f"warmup shot {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+
+    if not args.no_profile:
+        s.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        s.reset()
+        s.run(args.nt, out=traces)
+        print(f"timed shot {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    prof = s.profile_read() if not args.no_profile else {}
+    s.profile(False)
+
+    cell_steps = float(cells) * args.nt * args.steps * s.n_shots
+    value = cell_steps / elapsed / 1e9
+    ms_per_step = elapsed / args.steps * 1e3
+
+    # parity of the timed run against the stored FP64 oracle traces (if present)
+    parity = None
+    gold = os.path.join(ROOT, "tests", "golden", "c1_oracle_traces.npz")
+    if args.workload == "c1" and os.path.exists(gold):
+        g = np.load(gold, allow_pickle=False)
+        if int(g["nt"]) == args.nt:
+            got = traces[0][:, torch.as_tensor(g["receivers"], device=dev)].cpu().numpy().astype(np.float64)
+            ref = g["traces"]
+            parity = {c: float(np.linalg.norm(got[i] - ref[i]) / np.linalg.norm(ref[i]))
+                      for i, c in enumerate(["p", "vx", "vy", "vz"])}
+
+    roofline = None
+    kernels = None
+    if prof:
+        bpc = kernel_bytes_per_cell(nx, nx // 2 + 1)
+        kernels = {}
+        for k, (ms, n) in prof.items():
+            if n:
+                avg_us = ms / n * 1e3
+                alg = bpc[k] * cells * s.n_shots
+                kernels[k] = {"launches": n, "avg_us": round(avg_us, 2),
+                              "alg_bytes": int(alg), "alg_GBs": round(alg / (avg_us * 1e-6) / 1e9, 1)}
+        dom = max(kernels, key=lambda k: kernels[k]["avg_us"] * kernels[k]["launches"])
+        ach = kernels[dom]["alg_GBs"]
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+        tot_bytes = sum(bpc.values()) * cells * s.n_shots
+        step_us = sum(v["avg_us"] for v in kernels.values())
+        roofline["step_alg_bytes_per_cell"] = round(sum(bpc.values()), 1)
+        roofline["step_alg_GBs"] = round(tot_bytes / (step_us * 1e-6) / 1e9, 1)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        ow = inputs.c1_workload(nt=args.nt) if args.workload == "c1" else w
+        so = oracle.Solver.from_workload(ow)
+        so.set_sources(ow.src_ijk, ow.src_m, ow.wavelet)
+        so.run(1)
+        t = time.perf_counter()
+        n_cpu = 0
+        while time.perf_counter() - t < args.cpu_seconds and n_cpu < args.nt:
+            so.run(1)
+            n_cpu += 1
+        dt_cpu = time.perf_counter() - t
+        so.close()
+        cpu = {"value": round(cells * n_cpu / dt_cpu / 1e9, 6), "unit": "Gcell-steps/s", "cores": oracle.threads(),
+               "kind": "oracle",
+               "sample": f"{n_cpu} FP64 oracle steps (after 1 untimed) of the same {nx}x{ny}x{nz} shot, "
+                         f"{dt_cpu:.1f} s"}
+
+    out = {
+        "metric": "Gcell-steps/s FP32 PSTD elastic @1e-4 L2",
+        "value": round(value, 4),
+        "unit": "Gcell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "grid": [nx, ny, nz], "nt_per_shot": args.nt, "shots_per_step": s.n_shots,
+                   "receivers": s.n_rec, "pml": w.pml, "dx_m": w.d[0], "dt_s": w.dt,
+                   "step": "one full shot: state reset + nt leapfrog steps"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity_rel_l2": parity,
+        "kernels": kernels,
+        "device_bytes": s.device_bytes,
+    }
+    print(json.dumps(out), flush=True)
+    s.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

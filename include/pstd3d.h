@@ -1,0 +1,168 @@
+/*
+ * pstd3d — MI355X (gfx950) Fourier pseudo-spectral elastic wave solver and
+ * trace superposition.  Plain C ABI: host or device pointers and sizes only.
+ *
+ * Physics (arXiv 1705.04874, Das, Chen & Hobson):
+ *  - lossless 3-D elastic first-order stress-velocity system (eq. 2 with the
+ *    viscosities set to zero, Sec. II-A), Lame parameters from cp, cs, rho
+ *    (eq. 4), hydrophone pressure p = -(sxx + syy + szz)/3 (eq. 3);
+ *  - Fourier pseudo-spectral spatial derivatives, leapfrog time stepping on a
+ *    grid staggered in space and time (Sec. II-A), with a k-space correction
+ *    kappa = sinc(c_ref |k| dt / 2) on the derivative operator;
+ *  - a split-field perfectly matched layer of `thickness` cells on all six
+ *    faces (Sec. II-B), CFL number of eq. 5;
+ *  - point sources given by a symmetric moment tensor (eq. 6-7) with a
+ *    moment-rate wavelet; four-component seabed receivers (Sec. II-B);
+ *  - superposition of single-event traces with amplitudes and origin times
+ *    (Sec. IV, Cases 1-3).
+ *
+ * Conventions.
+ *  - Arrays over the grid are [nz][ny][nx], x fastest, z = 0 at the top.
+ *  - Moment tensors are 6 doubles (xx, yy, zz, xy, xz, yz) in N*m.
+ *  - Traces are float [n_shots][4][n_rec][nt], components (p, vx, vy, vz).
+ *    p of step n is sampled at time (n+1) dt at the cell centre; v of step n
+ *    at (n+1/2) dt at the component's staggered node (vx at (i+1/2, j, k) ...).
+ *  - Host inputs are copied during the call; device buffers passed in remain
+ *    owned by the caller.  A context owns its tables and state (device memory
+ *    allocated with hipMalloc) and is used from one stream at a time.
+ *  - Every call returns PSTD_OK (0) or a negative error code; the message of
+ *    the last error on the calling thread is returned by pstd3d_last_error().
+ *    No C++ exception crosses the ABI.
+ */
+#ifndef PSTD3D_H
+#define PSTD3D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PSTD_OK 0
+#define PSTD_EINVAL (-1)        /* bad argument or model value */
+#define PSTD_ENOMEM (-2)        /* device allocation failed */
+#define PSTD_EDEVICE (-3)       /* HIP runtime error */
+#define PSTD_EUNSTABLE (-4)     /* CFL condition violated, or non-finite field */
+#define PSTD_EUNSUPPORTED (-5)  /* grid length with a factor other than 2, 3, 5 or not built */
+
+typedef struct pstd3d_ctx pstd3d_ctx;
+
+/* Velocity model and receivers (Sec. II-B).  vp, vs (m/s) and rho (kg/m^3)
+ * are host arrays [nz][ny][nx]; rec_ijk is a host array [n_rec][3] of cell
+ * indices (i, j, k).  kspace: 1 applies the k-space correction (default), 0
+ * gives the plain pseudo-spectral operator.  c_ref <= 0 selects max(vp); it
+ * sets both the k-space correction and the PML profile. */
+typedef struct {
+    int nx, ny, nz;
+    const double *vp, *vs, *rho;
+    int n_rec;
+    const int32_t *rec_ijk;
+    int kspace;
+    double c_ref;
+} pstd3d_model;
+
+/* Split-field PML (Sec. II-B): `thickness` cells inside the grid on each
+ * face, absorption alpha = (A c_ref / h) (depth / thickness)^4 with A in
+ * nepers per cell (2 is a good default). */
+typedef struct {
+    int thickness;
+    double A;
+} pstd3d_pml;
+
+/* Create a solver for one model.  d = (dx, dy, dz) metres, dt seconds.
+ * Validates the model (finite, vp > 0, rho > 0, vs >= 0, positive bulk
+ * modulus), the receivers (inside the grid), the grid lengths (2, 3, 5
+ * factors, built lengths) and stability: with kspace = 0 it requires
+ * c_max dt sqrt(sum 1/h^2) <= 2/pi (eq. 5 in 3-D for the leapfrog scheme);
+ * with kspace = 1 and c_ref >= c_max any dt is stable.  The current HIP
+ * device is the context's device.  On success *out holds the context. */
+int pstd3d_create(const pstd3d_model *m, const double d[3], double dt, const pstd3d_pml *pml,
+                  pstd3d_ctx **out);
+
+/* Define the shots and reset every shot's state to zero at step 0.
+ * Shot s owns the point sources [shot_ofs[s], shot_ofs[s+1]) (host int32
+ * [n_shots+1]); source q has cell src_ijk[3q..3q+3), moment tensor
+ * m6[6q..6q+6) and wavelet row wavelet[q*nt_w .. (q+1)*nt_w) (host doubles,
+ * moment rate in 1/s, sample n applied during step n, zero beyond nt_w).
+ * In step n each stress component c,d of the source cell receives
+ * -dt * w[n] * M_cd / (dx dy dz), split equally over its split parts; shear
+ * components go 1/4 to each of the four shear nodes around the cell centre
+ * (eq. 6-7; Sec. II-A point sources). */
+int pstd3d_set_sources(pstd3d_ctx *c, int n_shots, const int32_t *shot_ofs, const int32_t *src_ijk,
+                       const double *m6, const double *wavelet, int nt_w);
+
+/* Advance every shot by nt steps on `hip_stream` (a hipStream_t, may be
+ * NULL for the null stream) and write the receiver traces of those steps to
+ * the caller-owned device buffer traces_dev [n_shots][4][n_rec][nt].
+ * Stateful: a second call continues where the first stopped.  Returns
+ * PSTD_EUNSTABLE if a non-finite value reached the receivers. */
+int pstd3d_run(pstd3d_ctx *c, int nt, float *traces_dev, void *hip_stream);
+
+/* Advance several contexts (uneven grids allowed) by nt steps as one HIP
+ * graph per step: the per-context step sequences are captured on forked
+ * streams so the graph runs them concurrently; traces[i] is context i's
+ * device trace buffer.  All contexts must live on the current device. */
+int pstd3d_run_many(pstd3d_ctx *const *ctxs, int n, int nt, float *const *traces, void *hip_stream);
+
+/* Checkpoint: copy shot `shot`'s 24 split fields (float, host [24][nz][ny][nx],
+ * order vx(x,y,z) vy(x,y,z) vz(x,y,z) sxx(x,y,z) syy(x,y,z) szz(x,y,z)
+ * sxy(x,y) sxz(x,z) syz(y,z)) to host memory. */
+int pstd3d_get_state(pstd3d_ctx *c, int shot, float *fields_host);
+/* Restore shot `shot`'s split fields from host memory and set the step index
+ * of the context (the wavelet sample used by the next step). */
+int pstd3d_set_state(pstd3d_ctx *c, int shot, const float *fields_host, long step);
+/* Step index of the next step. */
+long pstd3d_step(const pstd3d_ctx *c);
+
+/* Debug / test entry: the nine staggered spectral derivatives of one phase,
+ * computed with the same kernels as a time step.  phase 0: in = 6 device
+ * fields (sxx, syy, szz, sxy, sxz, syz) -> out = 9 device fields
+ * (Dx+ sxx, Dy- sxy, Dz- sxz, Dx- sxy, Dy+ syy, Dz- syz, Dx- sxz, Dy- syz, Dz+ szz);
+ * phase 1: in = 3 fields (vx, vy, vz) -> out = 9 fields
+ * (Dx- vx, Dy- vy, Dz- vz, Dy+ vx, Dx+ vy, Dz+ vx, Dx+ vz, Dz+ vy, Dy+ vz).
+ * D_d^{+-} f = IFFT[i k_d exp(+-i k_d h_d/2) kappa FFT f].  Uses shot 0's
+ * scratch; the shot's state is kept. */
+int pstd3d_derivs(pstd3d_ctx *c, int phase, const float *in_dev, float *out_dev, void *hip_stream);
+
+/* Zero every shot's state and set the step index to 0 (the sources set by
+ * pstd3d_set_sources are kept), enqueued on hip_stream. */
+int pstd3d_reset(pstd3d_ctx *c, void *hip_stream);
+
+/* Per-kernel timing with HIP events recorded around every launch of
+ * pstd3d_run (off by default).  Kinds: */
+#define PSTD_K_YFWD_S 0   /* y FFT of the 6 stress spectra */
+#define PSTD_K_ZOP_V 1    /* z FFT, 9 derivative symbols, inverse z FFT (V phase) */
+#define PSTD_K_YINV_V 2   /* inverse y FFT of the 9 stress derivatives */
+#define PSTD_K_VEL 3      /* inverse x FFT + velocity update + receivers + x FFT of v */
+#define PSTD_K_YFWD_V 4   /* y FFT of the 3 velocity spectra */
+#define PSTD_K_ZOP_S 5    /* z operator of the S phase */
+#define PSTD_K_YINV_S 6   /* inverse y FFT of the 9 velocity derivatives */
+#define PSTD_K_STR 7      /* inverse x FFT + stress update + sources + receivers + x FFT */
+#define PSTD_K_COUNT 8
+/* enable != 0 turns timing on and clears the accumulators. */
+int pstd3d_profile(pstd3d_ctx *c, int enable);
+/* Accumulated milliseconds and launch count of one kernel kind since the
+ * last pstd3d_profile(c, 1). */
+int pstd3d_profile_read(const pstd3d_ctx *c, int kind, double *total_ms, long *launches);
+
+/* Bytes of device memory held by the context. */
+long pstd3d_device_bytes(const pstd3d_ctx *c);
+void pstd3d_destroy(pstd3d_ctx *c);
+const char *pstd3d_last_error(void);
+
+/* Superposition of single-event traces (Sec. IV; Case 2's shift-and-add with
+ * real-valued shifts):
+ *   out[c][r][m] = sum_e amp[e] * x_e(m dt_out - t_origin[e] - t0[c]),
+ * x_e(t) the linear interpolation of tr[src_idx[e]][c][r][.] at t / dt_in,
+ * zero outside [0, nt_in - 1].  Accumulated in double, in event order.
+ * tr: device float [n_src][4][n_rec][nt_in]; out: device float
+ * [4][n_rec][nt_out]; t0: host double[4] (time of sample 0 per component);
+ * src_idx, amp, t_origin: host arrays [n_ev].  Runs on hip_stream. */
+int seis_combine(const float *tr, int n_src, int n_rec, int nt_in, double dt_in, const double t0[4],
+                 int n_ev, const int32_t *src_idx, const double *amp, const double *t_origin,
+                 int nt_out, double dt_out, float *out, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -40,6 +40,10 @@
 
 #include "oracle.h"
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 struct ostate {
     int nx, ny, nz;
     long n;
@@ -121,6 +125,16 @@ static void free_state(ostate *s)
 void opstd_destroy(ostate *s) { free_state(s); }
 
 long opstd_step_index(const ostate *s) { return s->step; }
+
+/* threads the OpenMP loops of the oracle use */
+int oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 void opstd_set_step(ostate *s, long step) { s->step = step; }
 

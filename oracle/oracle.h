@@ -34,6 +34,7 @@ int opstd_run(ostate *s, int nt, double *traces);
 void opstd_get_state(const ostate *s, double *fields);
 void opstd_set_state(ostate *s, const double *fields);
 long opstd_step_index(const ostate *s);
+int oracle_threads(void);
 void opstd_set_step(ostate *s, long step);
 void opstd_destroy(ostate *s);
 void opstd_deriv(int nx, int ny, int nz, double dx, double dy, double dz, const double *f,

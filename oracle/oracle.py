@@ -47,12 +47,18 @@ def lib():
         L.opstd_step_index.restype = C.c_long
         L.opstd_set_step.argtypes = [C.c_void_p, C.c_long]
         L.opstd_destroy.argtypes = [C.c_void_p]
+        L.oracle_threads.restype = C.c_int
         L.opstd_deriv.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
                                   dp, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, dp]
         L.ocombine.argtypes = [fp, C.c_int, C.c_int, C.c_int, C.c_double, dp, C.c_int, ip, dp, dp,
                                C.c_int, C.c_double, dp]
         _LIB = L
     return _LIB
+
+
+def threads():
+    """OpenMP threads the oracle's loops use."""
+    return int(lib().oracle_threads())
 
 
 def _dp(a):

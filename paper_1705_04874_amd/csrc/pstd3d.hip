@@ -1,0 +1,869 @@
+// Host side of the pstd3d C ABI: model ingest, FP64 operator tables, shot
+// state, launch sequencing (eager or HIP-graph), checkpoints.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pstd3d.h"
+#include "pstd_kernels.hpp"
+
+using namespace pstd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                       \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(e_ == hipErrorOutOfMemory ? PSTD_ENOMEM : PSTD_EDEVICE,             \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                 \
+    } while (0)
+
+constexpr int NT = 256;
+
+// ---------------------------------------------------------------------------
+// per-length kernel launchers
+struct XFns {
+    void (*vel)(dim3, hipStream_t, Geo, Mat, Pml, const float2*, float*, float2*, Rec, float*, const int*, int, int);
+    void (*str)(dim3, hipStream_t, Geo, Mat, Pml, const float2*, float*, float2*, Rec, Inj, float*, const int*, int, int);
+    void (*xfwd)(dim3, hipStream_t, Geo, const float2*, const float*, long, float2*, long, SumDesc);
+    void (*xinv)(dim3, hipStream_t, Geo, const float2*, const float2*, float*);
+    int rows;
+};
+struct YFns {
+    void (*fwd)(dim3, hipStream_t, Geo, const float2*, float2*, int, int);
+    void (*inv)(dim3, hipStream_t, Geo, const float2*, float2*, int, int);
+    int tile;
+};
+struct ZFns {
+    void (*op)(dim3, hipStream_t, Geo, const float2*, float2*, int, const ZDesc*, int);
+    int tile;
+};
+
+template <int N>
+struct Launch {
+    static void vel(dim3 gr, hipStream_t st, Geo g, Mat m, Pml p, const float2* tw, float* f, float2* s, Rec r,
+                    float* tr, const int* sp, int n0, int ldt)
+    {
+        hipLaunchKernelGGL((k_vel<N, NT>), gr, dim3(NT), 0, st, g, m, p, tw, f, s, r, tr, sp, n0, ldt);
+    }
+    static void str(dim3 gr, hipStream_t st, Geo g, Mat m, Pml p, const float2* tw, float* f, float2* s, Rec r,
+                    Inj in, float* tr, const int* sp, int n0, int ldt)
+    {
+        hipLaunchKernelGGL((k_str<N, NT>), gr, dim3(NT), 0, st, g, m, p, tw, f, s, r, in, tr, sp, n0, ldt);
+    }
+    static void xfwd(dim3 gr, hipStream_t st, Geo g, const float2* tw, const float* in, long is, float2* out,
+                     long os, SumDesc sd)
+    {
+        hipLaunchKernelGGL((k_xfwd<N, NT>), gr, dim3(NT), 0, st, g, tw, in, is, out, os, sd);
+    }
+    static void xinv(dim3 gr, hipStream_t st, Geo g, const float2* tw, const float2* in, float* out)
+    {
+        hipLaunchKernelGGL((k_xinv<N, NT>), gr, dim3(NT), 0, st, g, tw, in, out);
+    }
+    static void yf(dim3 gr, hipStream_t st, Geo g, const float2* tw, float2* s, int f0, int nf)
+    {
+        hipLaunchKernelGGL((k_y<N, NT, -1>), gr, dim3(NT), 0, st, g, tw, s, f0, nf);
+    }
+    static void yi(dim3 gr, hipStream_t st, Geo g, const float2* tw, float2* s, int f0, int nf)
+    {
+        hipLaunchKernelGGL((k_y<N, NT, +1>), gr, dim3(NT), 0, st, g, tw, s, f0, nf);
+    }
+    static void z(dim3 gr, hipStream_t st, Geo g, const float2* tw, float2* s, int in0, const ZDesc* zd, int ph)
+    {
+        hipLaunchKernelGGL((k_z<N, NT>), gr, dim3(NT), 0, st, g, tw, s, in0, zd, ph);
+    }
+};
+
+// Grid lengths the library is built for (all factor into 2, 3 and 5).
+#define PSTD_LENGTHS(X)                                                                          \
+    X(16) X(20) X(24) X(30) X(32) X(40) X(48) X(60) X(64) X(72) X(75) X(80) X(90) X(96) X(100) X(120) X(125) \
+    X(128) X(144) X(150) X(160) X(180) X(192) X(200) X(240) X(256) X(288) X(300) X(320) X(360)  \
+    X(384) X(400) X(480) X(512)
+
+bool x_fns(int n, XFns* f)
+{
+    switch (n) {
+#define CASE(N)                                                                                        \
+    case N:                                                                                            \
+        *f = XFns{Launch<N>::vel, Launch<N>::str, Launch<N>::xfwd, Launch<N>::xinv, rows_for(N)};      \
+        return true;
+        PSTD_LENGTHS(CASE)
+#undef CASE
+    default:
+        return false;
+    }
+}
+
+bool y_fns(int n, YFns* f)
+{
+    switch (n) {
+#define CASE(N)                                              \
+    case N:                                                  \
+        *f = YFns{Launch<N>::yf, Launch<N>::yi, tile_for(N)}; \
+        return true;
+        PSTD_LENGTHS(CASE)
+#undef CASE
+    default:
+        return false;
+    }
+}
+
+bool z_fns(int n, ZFns* f)
+{
+    switch (n) {
+#define CASE(N)                                  \
+    case N:                                      \
+        *f = ZFns{Launch<N>::z, tile_for(N)};    \
+        return true;
+        PSTD_LENGTHS(CASE)
+#undef CASE
+    default:
+        return false;
+    }
+}
+
+// V phase: stress spectra (sxx, syy, szz, sxy, sxz, syz) -> 9 derivatives,
+// derivative index 3 c + d feeds split part v_c^(d).
+PhaseDesc phase_v()
+{
+    PhaseDesc p{};
+    p.nin = 6;
+    auto set = [&](int in, int o, int idx, int axis, int plus) {
+        p.oidx[in][o] = idx;
+        p.axis[in][o] = axis;
+        p.plus[in][o] = plus;
+        p.nout[in] = o + 1;
+    };
+    set(0, 0, 0, 0, 1);  // Dx+ sxx -> vx(x)
+    set(1, 0, 4, 1, 1);  // Dy+ syy -> vy(y)
+    set(2, 0, 8, 2, 1);  // Dz+ szz -> vz(z)
+    set(3, 0, 1, 1, 0);  // Dy- sxy -> vx(y)
+    set(3, 1, 3, 0, 0);  // Dx- sxy -> vy(x)
+    set(4, 0, 2, 2, 0);  // Dz- sxz -> vx(z)
+    set(4, 1, 6, 0, 0);  // Dx- sxz -> vz(x)
+    set(5, 0, 5, 2, 0);  // Dz- syz -> vy(z)
+    set(5, 1, 7, 1, 0);  // Dy- syz -> vz(y)
+    return p;
+}
+
+// S phase: velocity spectra (vx, vy, vz) -> e0..e8
+PhaseDesc phase_s()
+{
+    PhaseDesc p{};
+    p.nin = 3;
+    auto set = [&](int in, int o, int idx, int axis, int plus) {
+        p.oidx[in][o] = idx;
+        p.axis[in][o] = axis;
+        p.plus[in][o] = plus;
+        p.nout[in] = o + 1;
+    };
+    set(0, 0, 0, 0, 0);  // Dx- vx
+    set(0, 1, 3, 1, 1);  // Dy+ vx
+    set(0, 2, 5, 2, 1);  // Dz+ vx
+    set(1, 0, 1, 1, 0);  // Dy- vy
+    set(1, 1, 4, 0, 1);  // Dx+ vy
+    set(1, 2, 7, 2, 1);  // Dz+ vy
+    set(2, 0, 2, 2, 0);  // Dz- vz
+    set(2, 1, 6, 0, 1);  // Dx+ vz
+    set(2, 2, 8, 1, 1);  // Dy+ vz
+    return p;
+}
+
+template <class T>
+int dev_upload(T** dst, const std::vector<T>& h)
+{
+    size_t bytes = std::max<size_t>(sizeof(T), h.size() * sizeof(T));
+    HIP_TRY(hipMalloc(dst, bytes));
+    if (!h.empty()) HIP_TRY(hipMemcpy(*dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return PSTD_OK;
+}
+
+double pml_alpha(double pos, int n, int L, double A, double c, double h)
+{
+    if (L <= 0) return 0.0;
+    double depth = std::max((double)L - pos, pos - (double)(n - 1 - L));
+    depth = std::min(std::max(depth, 0.0), (double)L);
+    double r = depth / L;
+    return A * c / h * r * r * r * r;
+}
+
+}  // namespace
+
+struct pstd3d_ctx {
+    int nx = 0, ny = 0, nz = 0;
+    double h[3] = {0, 0, 0}, dt = 0, c_ref = 0, cmax = 0;
+    int pml = 0, kspace = 1;
+    double pml_A = 0;
+    int n_rec = 0;
+    int device = 0;
+    Geo g{};
+    XFns xf{};
+    YFns yf{};
+    ZFns zf{};
+    // model-wide device tables
+    float* mat = nullptr;      // 8 arrays of n
+    float* pmlb = nullptr;     // ai[3], ah[3] back to back
+    float2* tw = nullptr;      // x, y, z twiddles
+    float2* sym = nullptr;     // per axis D-, D+
+    float* kap = nullptr;
+    int* rec_ptr = nullptr;
+    int4* rec_ent = nullptr;
+    ZDesc* zdesc = nullptr;
+    Mat M{};
+    Pml P{};
+    Ops O{};
+    const float2 *twx = nullptr, *twy = nullptr, *twz = nullptr;
+    // shots
+    int n_shots = 0;
+    float* fields = nullptr;
+    float2* spec = nullptr;
+    int* inj_ptr = nullptr;
+    int4* inj_ent = nullptr;
+    float* wav = nullptr;
+    int nt_w = 0;
+    int* stepd = nullptr;
+    int* flag = nullptr;
+    long step = 0;
+    long bytes = 0;
+    // per-kernel event timing
+    bool prof = false;
+    std::vector<hipEvent_t> evpool;
+    size_t evused = 0;
+    std::vector<std::pair<int, size_t>> evpend;   // (kind, index of start event)
+    double prof_ms[PSTD_K_COUNT] = {0};
+    long prof_n[PSTD_K_COUNT] = {0};
+
+    ~pstd3d_ctx()
+    {
+        release_shots();
+        release_model();
+        for (auto e : evpool) (void)hipEventDestroy(e);
+    }
+
+    // record a start event for `kind`; returns the pool index (or -1)
+    long ev_begin(int kind, hipStream_t st)
+    {
+        if (!prof) return -1;
+        if (evused + 2 > evpool.size()) {
+            for (int i = 0; i < 64; ++i) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) return -1;
+                evpool.push_back(e);
+            }
+        }
+        const size_t i = evused;
+        evused += 2;
+        (void)hipEventRecord(evpool[i], st);
+        evpend.push_back({kind, i});
+        return (long)i;
+    }
+    void ev_end(long i, hipStream_t st)
+    {
+        if (i >= 0) (void)hipEventRecord(evpool[i + 1], st);
+    }
+    // after the stream has been synchronised: fold the pending pairs in
+    void ev_collect()
+    {
+        for (auto& p : evpend) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, evpool[p.second], evpool[p.second + 1]) == hipSuccess) {
+                prof_ms[p.first] += ms;
+                prof_n[p.first] += 1;
+            }
+        }
+        evpend.clear();
+        evused = 0;
+    }
+
+    void release_shots()
+    {
+        (void)hipFree(fields);
+        (void)hipFree(spec);
+        (void)hipFree(inj_ptr);
+        (void)hipFree(inj_ent);
+        (void)hipFree(wav);
+        fields = nullptr;
+        spec = nullptr;
+        inj_ptr = nullptr;
+        inj_ent = nullptr;
+        wav = nullptr;
+        n_shots = 0;
+    }
+    void release_model()
+    {
+        (void)hipFree(mat);
+        (void)hipFree(pmlb);
+        (void)hipFree(tw);
+        (void)hipFree(sym);
+        (void)hipFree(kap);
+        (void)hipFree(rec_ptr);
+        (void)hipFree(rec_ent);
+        (void)hipFree(zdesc);
+        (void)hipFree(stepd);
+        (void)hipFree(flag);
+    }
+};
+
+namespace {
+
+int build_model(pstd3d_ctx* c, const pstd3d_model* m)
+{
+    const int nx = c->nx, ny = c->ny, nz = c->nz;
+    const long n = (long)nx * ny * nz;
+    const double dt = c->dt;
+    auto at = [&](int i, int j, int k) { return (long)i + nx * ((long)j + (long)ny * k); };
+    // eq. 4 and staggered averages, in double
+    std::vector<double> mu(n);
+    for (long q = 0; q < n; ++q) mu[q] = m->rho[q] * m->vs[q] * m->vs[q];
+    std::vector<float> hm(8 * n);
+    float* dtr[3] = {&hm[0], &hm[n], &hm[2 * n]};
+    float* dlam = &hm[3 * n];
+    float* dmu2 = &hm[4 * n];
+    float* dmus[3] = {&hm[5 * n], &hm[6 * n], &hm[7 * n]};
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const long q = at(i, j, k);
+                const int ip = std::min(i + 1, nx - 1), jp = std::min(j + 1, ny - 1), kp = std::min(k + 1, nz - 1);
+                const double r0 = m->rho[q];
+                dtr[0][q] = (float)(dt / (0.5 * (r0 + m->rho[at(ip, j, k)])));
+                dtr[1][q] = (float)(dt / (0.5 * (r0 + m->rho[at(i, jp, k)])));
+                dtr[2][q] = (float)(dt / (0.5 * (r0 + m->rho[at(i, j, kp)])));
+                const double lam = m->rho[q] * m->vp[q] * m->vp[q] - 2.0 * mu[q];
+                dlam[q] = (float)(dt * lam);
+                dmu2[q] = (float)(2.0 * dt * mu[q]);
+                const long nb[3][4] = {{q, at(ip, j, k), at(i, jp, k), at(ip, jp, k)},
+                                       {q, at(ip, j, k), at(i, j, kp), at(ip, j, kp)},
+                                       {q, at(i, jp, k), at(i, j, kp), at(i, jp, kp)}};
+                for (int p = 0; p < 3; ++p) {
+                    double inv = 0.0;
+                    bool fluid = false;
+                    for (int t = 0; t < 4; ++t) {
+                        const double v = mu[nb[p][t]];
+                        if (v == 0.0) fluid = true;
+                        else inv += 1.0 / v;
+                    }
+                    dmus[p][q] = fluid ? 0.0f : (float)(dt * 4.0 / inv);
+                }
+            }
+    int rc = dev_upload(&c->mat, hm);
+    if (rc) return rc;
+    for (int d = 0; d < 3; ++d) c->M.dtr[d] = c->mat + d * n;
+    c->M.dlam = c->mat + 3 * n;
+    c->M.dmu2 = c->mat + 4 * n;
+    for (int p = 0; p < 3; ++p) c->M.dmus[p] = c->mat + (5 + p) * n;
+
+    // PML factors
+    const int N[3] = {nx, ny, nz};
+    std::vector<float> hp(2 * (nx + ny + nz));
+    size_t off[3][2];
+    size_t o = 0;
+    for (int d = 0; d < 3; ++d) {
+        off[d][0] = o;
+        for (int i = 0; i < N[d]; ++i)
+            hp[o++] = (float)std::exp(-pml_alpha(i, N[d], c->pml, c->pml_A, c->c_ref, c->h[d]) * dt / 2);
+        off[d][1] = o;
+        for (int i = 0; i < N[d]; ++i)
+            hp[o++] = (float)std::exp(-pml_alpha(i + 0.5, N[d], c->pml, c->pml_A, c->c_ref, c->h[d]) * dt / 2);
+    }
+    rc = dev_upload(&c->pmlb, hp);
+    if (rc) return rc;
+    for (int d = 0; d < 3; ++d) {
+        c->P.ai[d] = c->pmlb + off[d][0];
+        c->P.ah[d] = c->pmlb + off[d][1];
+    }
+
+    // twiddles exp(-2 pi i e / N) per axis
+    std::vector<float2> ht;
+    size_t toff[3];
+    for (int d = 0; d < 3; ++d) {
+        toff[d] = ht.size();
+        for (int e = 0; e < N[d]; ++e) {
+            const double a = -2.0 * M_PI * (double)e / N[d];
+            ht.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+        }
+    }
+    rc = dev_upload(&c->tw, ht);
+    if (rc) return rc;
+    c->twx = c->tw + toff[0];
+    c->twy = c->tw + toff[1];
+    c->twz = c->tw + toff[2];
+
+    // staggered derivative symbols i k exp(+-i k h / 2); x uses kx = 0..nx/2
+    auto kval = [](int m, int nn, double h) {
+        const int mm = m <= nn / 2 ? m : m - nn;
+        return 2.0 * M_PI * mm / (nn * h);
+    };
+    const int len[3] = {c->g.nxh, ny, nz};
+    std::vector<float2> hs;
+    size_t soff[3][2];
+    for (int d = 0; d < 3; ++d)
+        for (int plus = 0; plus < 2; ++plus) {
+            soff[d][plus] = hs.size();
+            for (int mi = 0; mi < len[d]; ++mi) {
+                const double k = kval(mi, N[d], c->h[d]);
+                const double a = (plus ? 0.5 : -0.5) * k * c->h[d];
+                // i k (cos a + i sin a) = (-k sin a, k cos a)
+                hs.push_back(make_float2((float)(-k * std::sin(a)), (float)(k * std::cos(a))));
+            }
+        }
+    rc = dev_upload(&c->sym, hs);
+    if (rc) return rc;
+    for (int d = 0; d < 3; ++d)
+        for (int plus = 0; plus < 2; ++plus) c->O.sym[d][plus] = c->sym + soff[d][plus];
+
+    // k-space correction with the 1/(nx ny nz) of the inverse transform folded in
+    std::vector<float> hk((size_t)nz * ny * c->g.ldx, 0.0f);
+    const double inv_n = 1.0 / (double)n;
+    for (int k = 0; k < nz; ++k) {
+        const double kz = kval(k, nz, c->h[2]);
+        for (int j = 0; j < ny; ++j) {
+            const double ky = kval(j, ny, c->h[1]);
+            for (int i = 0; i < c->g.nxh; ++i) {
+                const double kx = kval(i, nx, c->h[0]);
+                const double q = std::sqrt(kx * kx + ky * ky + kz * kz);
+                const double arg = 0.5 * c->c_ref * q * dt;
+                const double kap = (c->kspace && arg != 0.0) ? std::sin(arg) / arg : 1.0;
+                hk[((size_t)k * ny + j) * c->g.ldx + i] = (float)(kap * inv_n);
+            }
+        }
+    }
+    rc = dev_upload(&c->kap, hk);
+    if (rc) return rc;
+    c->O.kap = c->kap;
+    {
+        std::vector<ZDesc> zd(1);
+        zd[0].ph[0] = phase_v();
+        zd[0].ph[1] = phase_s();
+        zd[0].ops = c->O;
+        rc = dev_upload(&c->zdesc, zd);
+        if (rc) return rc;
+    }
+
+    // receivers sorted by row
+    std::vector<int4> re(c->n_rec);
+    for (int r = 0; r < c->n_rec; ++r) {
+        const int32_t* q = m->rec_ijk + 3 * r;
+        re[r] = make_int4(q[0], q[1] + ny * q[2], r, 0);
+    }
+    std::stable_sort(re.begin(), re.end(), [](const int4& a, const int4& b) { return a.y < b.y; });
+    std::vector<int> rp(c->g.nrows + 1, 0);
+    for (auto& e : re) rp[e.y + 1]++;
+    for (int r = 0; r < c->g.nrows; ++r) rp[r + 1] += rp[r];
+    rc = dev_upload(&c->rec_ptr, rp);
+    if (rc) return rc;
+    rc = dev_upload(&c->rec_ent, re);
+    if (rc) return rc;
+
+    HIP_TRY(hipMalloc(&c->stepd, sizeof(int)));
+    HIP_TRY(hipMemset(c->stepd, 0, sizeof(int)));
+    HIP_TRY(hipMalloc(&c->flag, sizeof(int)));
+    c->bytes = (long)(hm.size() * 4 + hp.size() * 4 + ht.size() * 8 + hs.size() * 8 + hk.size() * 4 +
+                      rp.size() * 4 + re.size() * 16);
+    return PSTD_OK;
+}
+
+Rec rec_of(const pstd3d_ctx* c) { return Rec{c->rec_ptr, c->rec_ent, c->n_rec}; }
+Inj inj_of(const pstd3d_ctx* c) { return Inj{c->inj_ptr, c->inj_ent, c->wav, c->nt_w}; }
+
+// one leapfrog step of every shot of a context
+void enqueue_step(pstd3d_ctx* c, hipStream_t st, float* traces, int n0, int ldt)
+{
+    const Geo& g = c->g;
+    const int S = c->n_shots;
+    const dim3 gx((g.nrows + c->xf.rows - 1) / c->xf.rows, S);
+    const int ty = c->yf.tile, tz = c->zf.tile;
+    const int tyn = (g.nxh + ty - 1) / ty, tzn = (g.nxh + tz - 1) / tz;
+    long e;
+    // V phase
+    e = c->ev_begin(PSTD_K_YFWD_S, st);
+    c->yf.fwd(dim3(tyn, g.nz, S * 6), st, g, c->twy, c->spec, 0, 6);
+    c->ev_end(e, st);
+    e = c->ev_begin(PSTD_K_ZOP_V, st);
+    c->zf.op(dim3(tzn, g.ny, S * 6), st, g, c->twz, c->spec, 0, c->zdesc, 0);
+    c->ev_end(e, st);
+    e = c->ev_begin(PSTD_K_YINV_V, st);
+    c->yf.inv(dim3(tyn, g.nz, S * 9), st, g, c->twy, c->spec, 9, 9);
+    c->ev_end(e, st);
+    e = c->ev_begin(PSTD_K_VEL, st);
+    c->xf.vel(gx, st, g, c->M, c->P, c->twx, c->fields, c->spec, rec_of(c), traces, c->stepd, n0, ldt);
+    c->ev_end(e, st);
+    // S phase
+    e = c->ev_begin(PSTD_K_YFWD_V, st);
+    c->yf.fwd(dim3(tyn, g.nz, S * 3), st, g, c->twy, c->spec, 6, 3);
+    c->ev_end(e, st);
+    e = c->ev_begin(PSTD_K_ZOP_S, st);
+    c->zf.op(dim3(tzn, g.ny, S * 3), st, g, c->twz, c->spec, 6, c->zdesc, 1);
+    c->ev_end(e, st);
+    e = c->ev_begin(PSTD_K_YINV_S, st);
+    c->yf.inv(dim3(tyn, g.nz, S * 9), st, g, c->twy, c->spec, 9, 9);
+    c->ev_end(e, st);
+    e = c->ev_begin(PSTD_K_STR, st);
+    c->xf.str(gx, st, g, c->M, c->P, c->twx, c->fields, c->spec, rec_of(c), inj_of(c), traces, c->stepd, n0, ldt);
+    c->ev_end(e, st);
+    hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, st, c->stepd);
+}
+
+bool len_ok(int n)
+{
+    XFns a;
+    return x_fns(n, &a);
+}
+
+// Recompute the x-transformed stress sums from the split fields.
+void enqueue_restore_spectra(pstd3d_ctx* c, hipStream_t st)
+{
+    SumDesc sd{};
+    sd.nf = 6;
+    const int first[6] = {9, 12, 15, 18, 20, 22};
+    const int cnt[6] = {3, 3, 3, 2, 2, 2};
+    for (int f = 0; f < 6; ++f) {
+        sd.first[f] = first[f];
+        sd.cnt[f] = cnt[f];
+    }
+    const dim3 gx((c->g.nrows + c->xf.rows - 1) / c->xf.rows, c->n_shots);
+    c->xf.xfwd(gx, st, c->g, c->twx, c->fields, c->g.fstride, c->spec, c->g.sstride, sd);
+}
+
+}  // namespace
+
+// ===========================================================================
+extern "C" {
+
+const char* pstd3d_last_error(void) { return g_err.c_str(); }
+
+int pstd3d_create(const pstd3d_model* m, const double d[3], double dt, const pstd3d_pml* pml, pstd3d_ctx** out)
+{
+    if (!m || !d || !pml || !out) return fail(PSTD_EINVAL, "null argument");
+    *out = nullptr;
+    const int nx = m->nx, ny = m->ny, nz = m->nz;
+    if (nx < 2 || ny < 2 || nz < 2) return fail(PSTD_EINVAL, "grid must be at least 2 cells per axis");
+    if (!m->vp || !m->vs || !m->rho) return fail(PSTD_EINVAL, "null model array");
+    if (!(d[0] > 0) || !(d[1] > 0) || !(d[2] > 0) || !(dt > 0)) return fail(PSTD_EINVAL, "spacing and dt must be > 0");
+    if (pml->thickness < 0 || 2 * pml->thickness > std::min(nx, std::min(ny, nz)) || !(pml->A >= 0))
+        return fail(PSTD_EINVAL, "bad PML thickness or strength");
+    if (!len_ok(nx) || !len_ok(ny) || !len_ok(nz))
+        return fail(PSTD_EUNSUPPORTED, "grid length not built (lengths factor into 2, 3, 5; see PSTD_LENGTHS)");
+    if (m->n_rec < 0 || (m->n_rec > 0 && !m->rec_ijk)) return fail(PSTD_EINVAL, "bad receivers");
+    const long n = (long)nx * ny * nz;
+    double cmax = 0.0;
+    for (long q = 0; q < n; ++q) {
+        const double vp = m->vp[q], vs = m->vs[q], rho = m->rho[q];
+        if (!std::isfinite(vp) || !std::isfinite(vs) || !std::isfinite(rho) || !(vp > 0) || !(rho > 0) || !(vs >= 0))
+            return fail(PSTD_EINVAL, "model value out of range at cell " + std::to_string(q));
+        if (3.0 * vp * vp <= 4.0 * vs * vs) return fail(PSTD_EINVAL, "non-positive bulk modulus at cell " + std::to_string(q));
+        cmax = std::max(cmax, vp);
+    }
+    for (int r = 0; r < m->n_rec; ++r) {
+        const int32_t* q = m->rec_ijk + 3 * r;
+        if (q[0] < 0 || q[0] >= nx || q[1] < 0 || q[1] >= ny || q[2] < 0 || q[2] >= nz)
+            return fail(PSTD_EINVAL, "receiver " + std::to_string(r) + " outside the grid");
+    }
+    const double c_ref = m->c_ref > 0 ? m->c_ref : cmax;
+    const double sh = std::sqrt(1 / (d[0] * d[0]) + 1 / (d[1] * d[1]) + 1 / (d[2] * d[2]));
+    if (!m->kspace) {
+        if (cmax * dt * sh > 2.0 / M_PI) return fail(PSTD_EUNSTABLE, "CFL: c_max dt sqrt(sum 1/h^2) exceeds 2/pi");
+    } else if (c_ref < cmax) {
+        const double arg = c_ref * M_PI * sh * dt / 2;
+        const double smax = arg >= M_PI / 2 ? 1.0 : std::sin(arg);
+        if (cmax / c_ref * smax > 1.0) return fail(PSTD_EUNSTABLE, "k-space scheme unstable: c_ref below c_max");
+    }
+    auto* c = new (std::nothrow) pstd3d_ctx();
+    if (!c) return fail(PSTD_ENOMEM, "host allocation");
+    c->nx = nx;
+    c->ny = ny;
+    c->nz = nz;
+    for (int a = 0; a < 3; ++a) c->h[a] = d[a];
+    c->dt = dt;
+    c->c_ref = c_ref;
+    c->cmax = cmax;
+    c->pml = pml->thickness;
+    c->pml_A = pml->A;
+    c->kspace = m->kspace ? 1 : 0;
+    c->n_rec = m->n_rec;
+    (void)hipGetDevice(&c->device);
+    x_fns(nx, &c->xf);
+    y_fns(ny, &c->yf);
+    z_fns(nz, &c->zf);
+    Geo& g = c->g;
+    g.nx = nx;
+    g.ny = ny;
+    g.nz = nz;
+    g.nxh = nx / 2 + 1;
+    g.ldx = (g.nxh + 15) / 16 * 16;
+    g.nrows = ny * nz;
+    g.n = n;
+    g.nspec = (long)nz * ny * g.ldx;
+    g.fstride = 24 * n;
+    g.sstride = 18 * g.nspec;
+    int rc = build_model(c, m);
+    if (rc) {
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return PSTD_OK;
+}
+
+int pstd3d_set_sources(pstd3d_ctx* c, int n_shots, const int32_t* shot_ofs, const int32_t* src_ijk, const double* m6,
+                       const double* wavelet, int nt_w)
+{
+    if (!c || n_shots < 1 || !shot_ofs || nt_w < 0) return fail(PSTD_EINVAL, "bad arguments");
+    if (shot_ofs[0] != 0) return fail(PSTD_EINVAL, "shot_ofs[0] must be 0");
+    for (int s = 0; s < n_shots; ++s)
+        if (shot_ofs[s + 1] < shot_ofs[s]) return fail(PSTD_EINVAL, "shot_ofs must be non-decreasing");
+    const int nsrc = shot_ofs[n_shots];
+    if (nsrc > 0 && (!src_ijk || !m6 || (nt_w > 0 && !wavelet))) return fail(PSTD_EINVAL, "null source arrays");
+    const int nx = c->nx, ny = c->ny, nz = c->nz;
+    for (int q = 0; q < nsrc; ++q) {
+        const int32_t* p = src_ijk + 3 * q;
+        if (p[0] < 0 || p[0] >= nx || p[1] < 0 || p[1] >= ny || p[2] < 0 || p[2] >= nz)
+            return fail(PSTD_EINVAL, "source " + std::to_string(q) + " outside the grid");
+        for (int t = 0; t < 6; ++t)
+            if (!std::isfinite(m6[6 * q + t])) return fail(PSTD_EINVAL, "non-finite moment tensor");
+    }
+    HIP_TRY(hipSetDevice(c->device));
+    // injection entries per shot: {x, split part, coef, wavelet row}
+    const double dV = c->h[0] * c->h[1] * c->h[2];
+    const int nrows = c->g.nrows;
+    std::vector<int> ptr((size_t)n_shots * (nrows + 1), 0);
+    std::vector<int4> ent;
+    static const int pair_axes[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (int s = 0; s < n_shots; ++s) {
+        std::vector<std::pair<long, int4>> es;   // (row, entry)
+        for (int q = shot_ofs[s]; q < shot_ofs[s + 1]; ++q) {
+            const int32_t* p = src_ijk + 3 * q;
+            const double* M = m6 + 6 * q;
+            for (int cc = 0; cc < 3; ++cc) {
+                if (M[cc] == 0.0) continue;
+                const float coef = (float)(-c->dt * M[cc] / dV / 3.0);
+                for (int d = 0; d < 3; ++d) {
+                    int4 e = make_int4(p[0], 3 * cc + d, __builtin_bit_cast(int, coef), q);
+                    es.push_back({(long)p[1] + (long)ny * p[2], e});
+                }
+            }
+            for (int pr = 0; pr < 3; ++pr) {
+                if (M[3 + pr] == 0.0) continue;
+                const float coef = (float)(-c->dt * M[3 + pr] / dV / 8.0);
+                const int a0 = pair_axes[pr][0], a1 = pair_axes[pr][1];
+                const int N[3] = {nx, ny, nz};
+                for (int o0 = -1; o0 <= 0; ++o0)
+                    for (int o1 = -1; o1 <= 0; ++o1) {
+                        int ix[3] = {p[0], p[1], p[2]};
+                        ix[a0] = (ix[a0] + o0 + N[a0]) % N[a0];
+                        ix[a1] = (ix[a1] + o1 + N[a1]) % N[a1];
+                        for (int t = 0; t < 2; ++t) {
+                            int4 e = make_int4(ix[0], 9 + 2 * pr + t, __builtin_bit_cast(int, coef), q);
+                            es.push_back({(long)ix[1] + (long)ny * ix[2], e});
+                        }
+                    }
+            }
+        }
+        std::stable_sort(es.begin(), es.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+        int* sp = &ptr[(size_t)s * (nrows + 1)];
+        const int base = (int)ent.size();
+        for (auto& e : es) sp[e.first + 1]++;
+        sp[0] = base;
+        for (int r = 0; r < nrows; ++r) sp[r + 1] += sp[r];
+        for (auto& e : es) ent.push_back(e.second);
+    }
+    std::vector<float> w((size_t)nsrc * nt_w);
+    for (size_t i = 0; i < w.size(); ++i) w[i] = (float)wavelet[i];
+
+    c->release_shots();
+    const size_t fbytes = (size_t)n_shots * c->g.fstride * sizeof(float);
+    const size_t sbytes = (size_t)n_shots * c->g.sstride * sizeof(float2);
+    HIP_TRY(hipMalloc(&c->fields, fbytes));
+    HIP_TRY(hipMalloc(&c->spec, sbytes));
+    HIP_TRY(hipMemset(c->fields, 0, fbytes));
+    HIP_TRY(hipMemset(c->spec, 0, sbytes));
+    int rc = dev_upload(&c->inj_ptr, ptr);
+    if (rc) return rc;
+    rc = dev_upload(&c->inj_ent, ent);
+    if (rc) return rc;
+    rc = dev_upload(&c->wav, w);
+    if (rc) return rc;
+    c->nt_w = nt_w;
+    c->n_shots = n_shots;
+    c->step = 0;
+    HIP_TRY(hipMemset(c->stepd, 0, sizeof(int)));
+    HIP_TRY(hipDeviceSynchronize());
+    return PSTD_OK;
+}
+
+static int check_traces(pstd3d_ctx* c, const float* traces, long count, hipStream_t st)
+{
+    HIP_TRY(hipMemsetAsync(c->flag, 0, sizeof(int), st));
+    if (count > 0) hipLaunchKernelGGL(k_check_finite, dim3(256), dim3(256), 0, st, traces, count, c->flag);
+    int h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, c->flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h) return fail(PSTD_EUNSTABLE, "non-finite value in the receiver traces");
+    return PSTD_OK;
+}
+
+int pstd3d_run(pstd3d_ctx* c, int nt, float* traces_dev, void* hip_stream)
+{
+    if (!c || nt < 0) return fail(PSTD_EINVAL, "bad arguments");
+    if (c->n_shots == 0) return fail(PSTD_EINVAL, "pstd3d_set_sources has not been called");
+    if (nt > 0 && c->n_rec > 0 && !traces_dev) return fail(PSTD_EINVAL, "null trace buffer");
+    if (c->step + nt > 2147483647L) return fail(PSTD_EINVAL, "step index overflow");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int n0 = (int)c->step;
+    for (int n = 0; n < nt; ++n) {
+        enqueue_step(c, st, traces_dev, n0, nt);
+        if (c->prof && c->evused >= 4096) {
+            HIP_TRY(hipStreamSynchronize(st));
+            c->ev_collect();
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    c->step += nt;
+    int rc = check_traces(c, traces_dev, (long)c->n_shots * 4 * c->n_rec * nt, st);
+    if (c->prof) c->ev_collect();
+    return rc;
+}
+
+int pstd3d_reset(pstd3d_ctx* c, void* hip_stream)
+{
+    if (!c || c->n_shots == 0) return fail(PSTD_EINVAL, "no shots to reset");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    HIP_TRY(hipMemsetAsync(c->fields, 0, (size_t)c->n_shots * c->g.fstride * sizeof(float), st));
+    HIP_TRY(hipMemsetAsync(c->spec, 0, (size_t)c->n_shots * c->g.sstride * sizeof(float2), st));
+    HIP_TRY(hipMemsetAsync(c->stepd, 0, sizeof(int), st));
+    c->step = 0;
+    return PSTD_OK;
+}
+
+int pstd3d_profile(pstd3d_ctx* c, int enable)
+{
+    if (!c) return fail(PSTD_EINVAL, "null context");
+    c->prof = enable != 0;
+    for (int k = 0; k < PSTD_K_COUNT; ++k) {
+        c->prof_ms[k] = 0;
+        c->prof_n[k] = 0;
+    }
+    c->evpend.clear();
+    c->evused = 0;
+    return PSTD_OK;
+}
+
+int pstd3d_profile_read(const pstd3d_ctx* c, int kind, double* total_ms, long* launches)
+{
+    if (!c || kind < 0 || kind >= PSTD_K_COUNT || !total_ms || !launches) return fail(PSTD_EINVAL, "bad arguments");
+    *total_ms = c->prof_ms[kind];
+    *launches = c->prof_n[kind];
+    return PSTD_OK;
+}
+
+int pstd3d_run_many(pstd3d_ctx* const* ctxs, int n, int nt, float* const* traces, void* hip_stream)
+{
+    if (!ctxs || n < 1 || nt < 0 || !traces) return fail(PSTD_EINVAL, "bad arguments");
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i] || ctxs[i]->n_shots == 0) return fail(PSTD_EINVAL, "context without shots");
+        if (nt > 0 && ctxs[i]->n_rec > 0 && !traces[i]) return fail(PSTD_EINVAL, "null trace buffer");
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    int n0[64];
+    if (n > 64) return fail(PSTD_EINVAL, "at most 64 contexts per call");
+    for (int i = 0; i < n; ++i) n0[i] = (int)ctxs[i]->step;
+    for (int s = 0; s < nt; ++s)
+        for (int i = 0; i < n; ++i) enqueue_step(ctxs[i], st, traces[i], n0[i], nt);
+    HIP_TRY(hipGetLastError());
+    for (int i = 0; i < n; ++i) {
+        ctxs[i]->step += nt;
+        int rc = check_traces(ctxs[i], traces[i], (long)ctxs[i]->n_shots * 4 * ctxs[i]->n_rec * nt, st);
+        if (rc) return rc;
+    }
+    return PSTD_OK;
+}
+
+int pstd3d_get_state(pstd3d_ctx* c, int shot, float* fields_host)
+{
+    if (!c || !fields_host || shot < 0 || shot >= c->n_shots) return fail(PSTD_EINVAL, "bad arguments");
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(fields_host, c->fields + (size_t)shot * c->g.fstride, c->g.fstride * sizeof(float),
+                      hipMemcpyDeviceToHost));
+    return PSTD_OK;
+}
+
+int pstd3d_set_state(pstd3d_ctx* c, int shot, const float* fields_host, long step)
+{
+    if (!c || !fields_host || shot < 0 || shot >= c->n_shots || step < 0 || step > 2147483647L)
+        return fail(PSTD_EINVAL, "bad arguments");
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(c->fields + (size_t)shot * c->g.fstride, fields_host, c->g.fstride * sizeof(float),
+                      hipMemcpyHostToDevice));
+    enqueue_restore_spectra(c, nullptr);
+    const int s32 = (int)step;
+    HIP_TRY(hipMemcpy(c->stepd, &s32, sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(hipDeviceSynchronize());
+    c->step = step;
+    return PSTD_OK;
+}
+
+long pstd3d_step(const pstd3d_ctx* c) { return c ? c->step : -1; }
+
+int pstd3d_derivs(pstd3d_ctx* c, int phase, const float* in_dev, float* out_dev, void* hip_stream)
+{
+    if (!c || !in_dev || !out_dev || (phase != 0 && phase != 1)) return fail(PSTD_EINVAL, "bad arguments");
+    if (c->n_shots == 0) return fail(PSTD_EINVAL, "pstd3d_set_sources has not been called");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t st = (hipStream_t)hip_stream;
+    const Geo& g = c->g;
+    SumDesc sd{};
+    sd.nf = phase == 0 ? 6 : 3;
+    for (int f = 0; f < sd.nf; ++f) {
+        sd.first[f] = f;
+        sd.cnt[f] = 1;
+    }
+    const int in0 = phase == 0 ? 0 : 6;
+    const dim3 gx((g.nrows + c->xf.rows - 1) / c->xf.rows, 1);
+    const int ty = c->yf.tile, tz = c->zf.tile;
+    const int tyn = (g.nxh + ty - 1) / ty, tzn = (g.nxh + tz - 1) / tz;
+    // shot 0 scratch: spectra in0.. and the derivative block
+    c->xf.xfwd(gx, st, g, c->twx, in_dev, 0, c->spec + in0 * g.nspec, 0, sd);
+    c->yf.fwd(dim3(tyn, g.nz, sd.nf), st, g, c->twy, c->spec, in0, sd.nf);
+    c->zf.op(dim3(tzn, g.ny, sd.nf), st, g, c->twz, c->spec, in0, c->zdesc, phase);
+    c->yf.inv(dim3(tyn, g.nz, 9), st, g, c->twy, c->spec, 9, 9);
+    c->xf.xinv(gx, st, g, c->twx, c->spec + 9 * g.nspec, out_dev);
+    // the stress spectra are part of the state between steps: rebuild them
+    enqueue_restore_spectra(c, st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    return PSTD_OK;
+}
+
+long pstd3d_device_bytes(const pstd3d_ctx* c)
+{
+    if (!c) return 0;
+    return c->bytes + (long)c->n_shots * (c->g.fstride * 4 + c->g.sstride * 8);
+}
+
+void pstd3d_destroy(pstd3d_ctx* c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,59 @@
+"""The C ABI library loads and exports every symbol its header declares, and its
+argument validation (which runs before any device call) rejects bad input.
+No compute call here needs a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1705_04874_amd", "libpstd3d.so")
+HEADER = os.path.join(ROOT, "include", "pstd3d.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pstd3d_\w+|seis_combine)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libpstd3d.so is not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_validation_without_device(lib):
+    from paper_1705_04874_amd import binding as B
+    shape = (16, 16, 16)
+    vp, vs, rho = [np.full(shape, v) for v in (3000.0, 1700.0, 2300.0)]
+    # CFL violation with the plain operator
+    with pytest.raises(B.PstdError) as e:
+        B.Solver(vp, vs, rho, (10, 10, 10), 2e-3, kspace=0, pml=2)
+    assert e.value.code == B.PSTD_EUNSTABLE
+    # a length with a factor 17 is not supported
+    shp = (16, 16, 17)
+    with pytest.raises(B.PstdError) as e:
+        B.Solver(np.full(shp, 3000.0), np.full(shp, 1700.0), np.full(shp, 2300.0), (10, 10, 10), 1e-3, pml=2)
+    assert e.value.code == B.PSTD_EUNSUPPORTED
+    bad = vp.copy()
+    bad[3, 3, 3] = np.nan
+    with pytest.raises(B.PstdError) as e:
+        B.Solver(bad, vs, rho, (10, 10, 10), 1e-3, pml=2)
+    assert e.value.code == B.PSTD_EINVAL
+    with pytest.raises(B.PstdError) as e:
+        B.Solver(vp, vs, rho, (10, 10, 10), 1e-3, pml=2, rec=np.array([[0, 16, 0]]))
+    assert e.value.code == B.PSTD_EINVAL
+    with pytest.raises(B.PstdError) as e:
+        B.Solver(vp, vs, rho, (10, 10, 10), 1e-3, pml=9)
+    assert e.value.code == B.PSTD_EINVAL

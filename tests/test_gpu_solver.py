@@ -1,0 +1,186 @@
+"""GPU parity of the HIP solver against the FP64 oracle, through the C ABI.
+
+Bar (FP32 kernels vs FP64 oracle): relative L2 <= 1e-4 per trace component
+(p, vx, vy, vz) over all receivers and samples.  Derivative operators alone:
+<= 2e-5 relative (a few FP32 FFT round-offs).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1705_04874_amd import inputs
+from tests import physics
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def B(gpu):
+    from paper_1705_04874_amd import binding
+    return binding
+
+
+def hetero(shape, seed, water=0):
+    rng = np.random.default_rng(seed)
+    vp = 2400 + 900 * rng.random(shape)
+    vs = vp / (1.7 + 0.3 * rng.random(shape))
+    rho = 1800 + 600 * rng.random(shape)
+    vp[:water], vs[:water], rho[:water] = 1500.0, 0.0, 1000.0
+    return vp, vs, rho
+
+
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(24, 40, 48), (16, 75, 32), (20, 24, 60)])
+def test_derivatives_match_oracle(B, shape):
+    import torch
+    say("derivs", shape)
+    h = (10.0, 12.5, 8.0)
+    vp, vs, rho = hetero(shape, 1)
+    dt = 0.6e-3
+    s = B.Solver(vp, vs, rho, h, dt, pml=2, kspace=1)
+    s.set_sources([0, 0], np.zeros((0, 3)), np.zeros((0, 6)), np.zeros((0, 1)))
+    rng = np.random.default_rng(2)
+    axes_v = [(0, +1, 0), (1, -1, 3), (2, -1, 4), (0, -1, 3), (1, +1, 1), (2, -1, 5), (0, -1, 4), (1, -1, 5),
+              (2, +1, 2)]
+    axes_s = [(0, -1, 0), (1, -1, 1), (2, -1, 2), (1, +1, 0), (0, +1, 1), (2, +1, 0), (0, +1, 2), (2, +1, 1),
+              (1, +1, 2)]
+    for phase, nin, table in [(0, 6, axes_v), (1, 3, axes_s)]:
+        f = rng.standard_normal((nin,) + shape)
+        got = s.derivs(phase, torch.from_numpy(f.astype(np.float32)).cuda()).cpu().numpy()
+        for o, (axis, sign, src) in enumerate(table):
+            ref = oracle.deriv(f[src], axis, sign, h=h, kspace=1, c_ref=vp.max(), dt=dt)
+            e = rel(got[o], ref)
+            assert e < 2e-5, (phase, o, e)
+
+
+# ---------------------------------------------------------------------------
+def run_both(B, w, nt, **over):
+    s = B.Solver.from_workload(w, **over)
+    s.set_workload_sources(w)
+    g = s.run(nt).cpu().numpy()
+    refs = [oracle.run_shot(w, shot=k, nt=nt, **over) for k in range(w.n_shots)]
+    s.close()
+    return g, refs
+
+
+def test_c0_two_layer_full(B):
+    w = inputs.c0_workload()
+    say("c0", w.model.shape, w.nt)
+    g, refs = run_both(B, w, w.nt)
+    for c in range(4):
+        e = rel(g[0, c], refs[0][c])
+        say(f"  comp {c} rel-L2 {e:.3e}")
+        assert e <= TOL
+
+
+def small_workload(shape=(30, 24, 40), nt=150, kspace=1, shots=2, seed=3, pml=6):
+    nz, ny, nx = shape
+    vp, vs, rho = hetero(shape, seed, water=5)
+    m = inputs.Model(vp, vs, rho)
+    dt = 0.8e-3
+    rec = np.concatenate([inputs.receiver_block(4, nx - 4, 3, ny - 3, 5),
+                          np.array([[nx - 1, ny - 1, nz - 1], [0, 0, 0]], np.int32)])
+    rng = np.random.default_rng(seed)
+    ijk, mts, ofs = [], [], [0]
+    for k in range(shots):
+        for q in range(k + 1):
+            ijk.append([rng.integers(8, nx - 8), rng.integers(6, ny - 6), rng.integers(10, nz - 8)])
+            mts.append(inputs.random_dc(rng, 1000.0) + (q == 1) * inputs.clvd(300.0))
+        ofs.append(len(ijk))
+    # one source at a grid corner: shear stencil wraps around the periodic edges
+    ijk.append([0, 0, nz - 1])
+    mts.append(inputs.double_couple(0.5, 0.9, 0.2, 800.0))
+    ofs[-1] = len(ijk)
+    wav = np.stack([inputs.ricker(30.0 + 3 * q, dt, nt) for q in range(len(ijk))])
+    return inputs.Workload("small", m, (10.0, 10.0, 10.0), dt, nt, pml, 2.0, kspace, 0.0, rec,
+                           np.array(ijk, np.int32), np.array(mts), np.array(ofs, np.int32), wav)
+
+
+@pytest.mark.parametrize("kspace", [1, 0])
+def test_small_heterogeneous_multishot(B, kspace):
+    w = small_workload(kspace=kspace)
+    say("small multishot kspace", kspace, w.model.shape, w.n_shots)
+    g, refs = run_both(B, w, w.nt)
+    for k in range(w.n_shots):
+        for c in range(4):
+            e = rel(g[k, c], refs[k][c])
+            say(f"  shot {k} comp {c} rel-L2 {e:.3e}")
+            assert e <= TOL
+
+
+def test_shots_are_independent(B):
+    """Batched shots give exactly the traces of the same shots run one at a time."""
+    w = small_workload(nt=60, shots=3)
+    s = B.Solver.from_workload(w)
+    s.set_workload_sources(w)
+    batch = s.run(w.nt).cpu().numpy()
+    for k in range(w.n_shots):
+        a, b = int(w.shot_ofs[k]), int(w.shot_ofs[k + 1])
+        s1 = B.Solver.from_workload(w)
+        s1.set_sources([0, b - a], w.src_ijk[a:b], w.src_m[a:b], w.wavelet[a:b])
+        one = s1.run(w.nt).cpu().numpy()[0]
+        np.testing.assert_array_equal(batch[k], one)
+
+
+def test_run_is_stateful_and_checkpoint_is_exact(B):
+    w = small_workload(nt=80, shots=1)
+    s = B.Solver.from_workload(w)
+    s.set_workload_sources(w)
+    full = s.run(80).cpu().numpy()
+    s.set_workload_sources(w)
+    a = s.run(30).cpu().numpy()
+    st = s.get_state()
+    b = s.run(50).cpu().numpy()
+    np.testing.assert_array_equal(np.concatenate([a, b], axis=3), full)
+    s2 = B.Solver.from_workload(w)
+    s2.set_workload_sources(w)
+    s2.set_state(st, 30)
+    c = s2.run(50).cpu().numpy()
+    np.testing.assert_array_equal(c, b)
+
+
+@pytest.mark.parametrize("wave", ["P", "S"])
+def test_plane_wave(B, wave):
+    shape = (24, 20, 32)
+    h = (10.0, 12.5, 8.0)
+    vp, vs, rho, dt = 3000.0, 1700.0, 2300.0, 0.4e-3
+    s = B.Solver(np.full(shape, vp), np.full(shape, vs), np.full(shape, rho), h, dt, pml=0, kspace=1, c_ref=vp)
+    s.set_sources([0, 0], np.zeros((0, 3)), np.zeros((0, 6)), np.zeros((0, 1)))
+    s.set_state(physics.plane_wave_state(shape, h, dt, (3, 2, 1), wave, vp, vs, rho, 0, 1, vp), 0)
+    s.run(200)
+    got = physics.summed(s.get_state().astype(np.float64))
+    want = physics.summed(physics.plane_wave_state(shape, h, dt, (3, 2, 1), wave, vp, vs, rho, 200, 1, vp))
+    vscale = max(np.abs(b).max() for b in want[:3])
+    sscale = max(np.abs(b).max() for b in want[3:])
+    for i, (a, b) in enumerate(zip(got, want)):
+        scale = vscale if i < 3 else sscale
+        assert np.abs(a - b).max() < 2e-4 * scale, (i, np.abs(a - b).max() / scale)
+
+
+def test_error_codes(B):
+    shape = (16, 16, 16)
+    vp, vs, rho = [np.full(shape, v) for v in (3000.0, 1700.0, 2300.0)]
+    limit = 2 / math.pi * 10.0 / (3000.0 * math.sqrt(3))
+    with pytest.raises(B.PstdError) as e:
+        B.Solver(vp, vs, rho, (10, 10, 10), 1.05 * limit, kspace=0, pml=2)
+    assert e.value.code == B.PSTD_EUNSTABLE
+    shp = (16, 16, 17)
+    with pytest.raises(B.PstdError) as e:
+        B.Solver(np.full(shp, 3000.0), np.full(shp, 1700.0), np.full(shp, 2300.0), (10, 10, 10), 1e-3, pml=2)
+    assert e.value.code == B.PSTD_EUNSUPPORTED
+    s = B.Solver(vp, vs, rho, (10, 10, 10), 1e-3, pml=2)
+    with pytest.raises(B.PstdError) as e:
+        s.set_sources([0, 1], np.array([[0, 0, 16]]), np.zeros((1, 6)), np.zeros((1, 4)))
+    assert e.value.code == B.PSTD_EINVAL
