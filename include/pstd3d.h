@@ -62,11 +62,14 @@ typedef struct {
 } pstd3d_model;
 
 /* Split-field PML (Sec. II-B): `thickness` cells inside the grid on each
- * face, absorption alpha = (A c_ref / h) (depth / thickness)^4 with A in
- * nepers per cell (2 is a good default). */
+ * face, absorption alpha_d = (A c_ref / h_d) (depth / thickness)^4 with A in
+ * nepers per cell (2 is a good default).  mratio = p >= 0 makes it
+ * multi-axial: the split part along axis d is damped by alpha_d + p times the
+ * profiles of the two other axes (p = 0: the classical split PML). */
 typedef struct {
     int thickness;
     double A;
+    double mratio;
 } pstd3d_pml;
 
 /* Create a solver for one model.  d = (dx, dy, dz) metres, dt seconds.

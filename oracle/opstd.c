@@ -24,6 +24,9 @@
  *    the four surrounding centres (clamped), 0 if any of them is 0;
  *  - split-field PML on all six faces, profile alpha = (A c_ref / h)(depth/L)^4,
  *    factor a = exp(-alpha dt / 2) applied before and after adding the update;
+ *    multi-axial (M-PML): the split part along axis d is damped by alpha_d plus
+ *    p times the profiles of the two other axes, all evaluated at the field's
+ *    own node (p = 0 is the classical split PML);
  *  - a source adds -dt w[n] M_cd / dV to each stress component, split equally
  *    over the split parts; shear parts are spread 1/4 to each of the 4 shear
  *    nodes around the cell centre;
@@ -52,8 +55,9 @@ struct ostate {
     double c_ref;
     /* materials */
     double *lam, *mu, *rinv[3], *mu_s[3]; /* mu_s: xy, xz, yz */
-    /* PML factors a_d at integer / half nodes */
+    /* PML factors a_d at integer / half nodes; b = a^p for the other axes */
     double *a_int[3], *a_half[3];
+    double *b_int[3], *b_half[3];
     /* wavenumbers per axis, 1-D operator symbols i k exp(+-i k h/2), kappa(|k|) */
     double *k[3];
     double complex *sym[3][2];
@@ -101,6 +105,8 @@ static void free_state(ostate *s)
         free(s->mu_s[d]);
         free(s->a_int[d]);
         free(s->a_half[d]);
+        free(s->b_int[d]);
+        free(s->b_half[d]);
         free(s->k[d]);
         free(s->sym[d][0]);
         free(s->sym[d][1]);
@@ -140,10 +146,11 @@ void opstd_set_step(ostate *s, long step) { s->step = step; }
 
 ostate *opstd_create(int nx, int ny, int nz, const double *vp, const double *vs,
                      const double *rho, double dx, double dy, double dz, double dt, int pml_n,
-                     double pml_A, int kspace, double c_ref, int n_rec, const int *rec_ijk,
-                     int *err)
+                     double pml_A, double pml_p, int kspace, double c_ref, int n_rec,
+                     const int *rec_ijk, int *err)
 {
     *err = ORC_EINVAL;
+    if (!(pml_p >= 0 && pml_p <= 1)) return NULL;
     if (nx < 2 || ny < 2 || nz < 2 || !(dx > 0) || !(dy > 0) || !(dz > 0) || !(dt > 0)) return NULL;
     if (pml_n < 0 || 2 * pml_n > nx || 2 * pml_n > ny || 2 * pml_n > nz || pml_A < 0) return NULL;
     long n = (long)nx * ny * nz;
@@ -198,6 +205,8 @@ ostate *opstd_create(int nx, int ny, int nz, const double *vp, const double *vs,
         s->mu_s[d] = malloc(sizeof(double) * n);
         s->a_int[d] = malloc(sizeof(double) * N[d]);
         s->a_half[d] = malloc(sizeof(double) * N[d]);
+        s->b_int[d] = malloc(sizeof(double) * N[d]);
+        s->b_half[d] = malloc(sizeof(double) * N[d]);
         for (int c = 0; c < 3; ++c) {
             s->v[c][d] = calloc(n, sizeof(double));
             s->sn[c][d] = calloc(n, sizeof(double));
@@ -251,8 +260,12 @@ ostate *opstd_create(int nx, int ny, int nz, const double *vp, const double *vs,
     /* PML factors */
     for (int d = 0; d < 3; ++d)
         for (int i = 0; i < N[d]; ++i) {
-            s->a_int[d][i] = exp(-pml_alpha(i, N[d], pml_n, pml_A, c_ref, s->h[d]) * dt / 2);
-            s->a_half[d][i] = exp(-pml_alpha(i + 0.5, N[d], pml_n, pml_A, c_ref, s->h[d]) * dt / 2);
+            double ai = pml_alpha(i, N[d], pml_n, pml_A, c_ref, s->h[d]);
+            double ah = pml_alpha(i + 0.5, N[d], pml_n, pml_A, c_ref, s->h[d]);
+            s->a_int[d][i] = exp(-ai * dt / 2);
+            s->a_half[d][i] = exp(-ah * dt / 2);
+            s->b_int[d][i] = exp(-pml_p * ai * dt / 2);
+            s->b_half[d][i] = exp(-pml_p * ah * dt / 2);
         }
     if (build_operator(s) != ORC_OK) {
         free_state(s);
@@ -389,10 +402,15 @@ static void sum2(const ostate *s, double *const p[2], double *out)
     for (long c = 0; c < s->n; ++c) out[c] = p[0][c] + p[1][c];
 }
 
-/* a_d for a field staggered by half a cell along axis d or not */
-static inline double afac(const ostate *s, int d, int idx, int half)
+/* Damping factor of the split part along axis d of a field whose node is
+ * half a cell up along the axes flagged in half[]: a_d times b_e of the two
+ * other axes (multi-axial PML). */
+static inline double afac(const ostate *s, int d, const int pos[3], const int half[3])
 {
-    return half ? s->a_half[d][idx] : s->a_int[d][idx];
+    double a = half[d] ? s->a_half[d][pos[d]] : s->a_int[d][pos[d]];
+    for (int e = 0; e < 3; ++e)
+        if (e != d) a *= half[e] ? s->b_half[e][pos[e]] : s->b_int[e][pos[e]];
+    return a;
 }
 
 static void velocity_step(ostate *s)
@@ -443,7 +461,8 @@ static void velocity_step(ostate *s)
                 int pos[3] = {i, j, kk};
                 for (int comp = 0; comp < 3; ++comp)
                     for (int d = 0; d < 3; ++d) {
-                        double a = afac(s, d, pos[d], comp == d);
+                        int half[3] = {comp == 0, comp == 1, comp == 2};
+                        double a = afac(s, d, pos, half);
                         double *f = s->v[comp][d];
                         f[c] = a * (a * f[c] + dt * s->rinv[comp][c] * dv[comp][d][c]);
                     }
@@ -486,9 +505,10 @@ static void stress_step(ostate *s)
                 long c = IDX(s, i, j, kk);
                 int pos[3] = {i, j, kk};
                 double lam = s->lam[c], mu = s->mu[c];
+                static const int centre[3] = {0, 0, 0};
                 for (int comp = 0; comp < 3; ++comp)
                     for (int d = 0; d < 3; ++d) {
-                        double a = afac(s, d, pos[d], 0);
+                        double a = afac(s, d, pos, centre);
                         double coef = lam + (comp == d ? 2.0 * mu : 0.0);
                         double *f = s->sn[comp][d];
                         f[c] = a * (a * f[c] + dt * coef * e[d][c]);
@@ -496,7 +516,10 @@ static void stress_step(ostate *s)
                 for (int p = 0; p < 3; ++p)
                     for (int t = 0; t < 2; ++t) {
                         int d = pair_axes[p][t];
-                        double a = afac(s, d, pos[d], 1);
+                        int half[3] = {0, 0, 0};
+                        half[pair_axes[p][0]] = 1;
+                        half[pair_axes[p][1]] = 1;
+                        double a = afac(s, d, pos, half);
                         double *f = s->ss[p][t];
                         f[c] = a * (a * f[c] + dt * s->mu_s[p][c] * g[p][t][c]);
                     }

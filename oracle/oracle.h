@@ -26,8 +26,8 @@ typedef struct ostate ostate;
 
 ostate *opstd_create(int nx, int ny, int nz, const double *vp, const double *vs,
                      const double *rho, double dx, double dy, double dz, double dt, int pml_n,
-                     double pml_A, int kspace, double c_ref, int n_rec, const int *rec_ijk,
-                     int *err);
+                     double pml_A, double pml_p, int kspace, double c_ref, int n_rec,
+                     const int *rec_ijk, int *err);
 int opstd_set_sources(ostate *s, int n_src, const int *src_ijk, const double *m6,
                       const double *wavelet, int nt_w);
 int opstd_run(ostate *s, int nt, double *traces);

@@ -37,7 +37,7 @@ def lib():
         L.offt_3d.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int]
         L.opstd_create.restype = C.c_void_p
         L.opstd_create.argtypes = [C.c_int, C.c_int, C.c_int, dp, dp, dp, C.c_double, C.c_double,
-                                   C.c_double, C.c_double, C.c_int, C.c_double, C.c_int,
+                                   C.c_double, C.c_double, C.c_int, C.c_double, C.c_double, C.c_int,
                                    C.c_double, C.c_int, ip, ip]
         L.opstd_set_sources.argtypes = [C.c_void_p, C.c_int, ip, dp, dp, C.c_int]
         L.opstd_run.argtypes = [C.c_void_p, C.c_int, dp]
@@ -110,7 +110,7 @@ class Solver:
 
     N_STATE = 24
 
-    def __init__(self, vp, vs, rho, d, dt, pml=0, pml_A=2.0, kspace=1, c_ref=0.0, rec=None):
+    def __init__(self, vp, vs, rho, d, dt, pml=0, pml_A=2.0, kspace=1, c_ref=0.0, rec=None, pml_p=0.1):
         self.vp, self.vs, self.rho = _f64(vp), _f64(vs), _f64(rho)
         self.shape = self.vp.shape
         nz, ny, nx = self.shape
@@ -118,7 +118,7 @@ class Solver:
         err = C.c_int(0)
         self._h = lib().opstd_create(nx, ny, nz, _dp(self.vp), _dp(self.vs), _dp(self.rho),
                                      float(d[0]), float(d[1]), float(d[2]), float(dt), int(pml),
-                                     float(pml_A), int(kspace), float(c_ref), self.rec.shape[0],
+                                     float(pml_A), float(pml_p), int(kspace), float(c_ref), self.rec.shape[0],
                                      _ip(self.rec), C.byref(err))
         if not self._h:
             raise OracleError(err.value, "create")
@@ -126,7 +126,8 @@ class Solver:
 
     @classmethod
     def from_workload(cls, w, **over):
-        kw = dict(d=w.d, dt=w.dt, pml=w.pml, pml_A=w.pml_A, kspace=w.kspace, c_ref=w.c_ref, rec=w.rec)
+        kw = dict(d=w.d, dt=w.dt, pml=w.pml, pml_A=w.pml_A, pml_p=w.pml_p, kspace=w.kspace, c_ref=w.c_ref,
+                  rec=w.rec)
         kw.update(over)
         return cls(w.model.vp, w.model.vs, w.model.rho, **kw)
 

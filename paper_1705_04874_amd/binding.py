@@ -32,7 +32,7 @@ class PstdModel(C.Structure):
 
 
 class PstdPml(C.Structure):
-    _fields_ = [("thickness", C.c_int), ("A", C.c_double)]
+    _fields_ = [("thickness", C.c_int), ("A", C.c_double), ("mratio", C.c_double)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -87,7 +87,7 @@ def _i32(a):
 class Solver:
     """One velocity model on the current GPU; shots are batched inside."""
 
-    def __init__(self, vp, vs, rho, d, dt, pml=16, pml_A=2.0, kspace=1, c_ref=0.0, rec=None):
+    def __init__(self, vp, vs, rho, d, dt, pml=16, pml_A=2.0, kspace=1, c_ref=0.0, rec=None, pml_p=0.1):
         self.vp, self.vs, self.rho = _f64(vp), _f64(vs), _f64(rho)
         nz, ny, nx = self.vp.shape
         self.shape = (nz, ny, nx)
@@ -96,7 +96,7 @@ class Solver:
                       self.rho.ctypes.data_as(_dp), self.rec.shape[0], self.rec.ctypes.data_as(_ip),
                       int(kspace), float(c_ref))
         dd = (C.c_double * 3)(*[float(x) for x in d])
-        p = PstdPml(int(pml), float(pml_A))
+        p = PstdPml(int(pml), float(pml_A), float(pml_p))
         h = C.c_void_p()
         _check(_L.pstd3d_create(C.byref(m), dd, float(dt), C.byref(p), C.byref(h)), "pstd3d_create")
         self._h = h
@@ -105,7 +105,8 @@ class Solver:
 
     @classmethod
     def from_workload(cls, w, **over):
-        kw = dict(d=w.d, dt=w.dt, pml=w.pml, pml_A=w.pml_A, kspace=w.kspace, c_ref=w.c_ref, rec=w.rec)
+        kw = dict(d=w.d, dt=w.dt, pml=w.pml, pml_A=w.pml_A, pml_p=w.pml_p, kspace=w.kspace, c_ref=w.c_ref,
+                  rec=w.rec)
         kw.update(over)
         return cls(w.model.vp, w.model.vs, w.model.rho, **kw)
 

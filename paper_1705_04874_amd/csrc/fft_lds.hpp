@@ -82,6 +82,51 @@ template <int DIR> struct Dft<8, DIR> {
     }
 };
 
+// 16-point DFT as 4 x 4 with constant inner twiddles W16^(n2 k1)
+template <int DIR> struct Dft<16, DIR> {
+    template <int M>
+    static __device__ __forceinline__ float2 w16(float2 a)
+    {
+        // multiply by exp(DIR * 2 pi i M / 16)
+        constexpr float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f, h = 0.70710678118654752440f;
+        constexpr float cs[8] = {1.f, c1, h, s1, 0.f, -s1, -h, -c1};
+        constexpr float sn[8] = {0.f, s1, h, c1, 1.f, c1, h, s1};
+        constexpr float c = cs[M % 8] * ((M / 8) % 2 ? -1.f : 1.f);
+        constexpr float s = sn[M % 8] * ((M / 8) % 2 ? -1.f : 1.f) * (DIR < 0 ? -1.f : 1.f);
+        return make_float2(a.x * c - a.y * s, a.x * s + a.y * c);
+    }
+    static __device__ __forceinline__ void run(float2* a)
+    {
+        float2 y[4][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+            y[n2][0] = a[n2];
+            y[n2][1] = a[4 + n2];
+            y[n2][2] = a[8 + n2];
+            y[n2][3] = a[12 + n2];
+            Dft<4, DIR>::run(y[n2]);
+        }
+        y[1][1] = w16<1>(y[1][1]);
+        y[1][2] = w16<2>(y[1][2]);
+        y[1][3] = w16<3>(y[1][3]);
+        y[2][1] = w16<2>(y[2][1]);
+        y[2][2] = w16<4>(y[2][2]);
+        y[2][3] = w16<6>(y[2][3]);
+        y[3][1] = w16<3>(y[3][1]);
+        y[3][2] = w16<6>(y[3][2]);
+        y[3][3] = w16<9>(y[3][3]);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            float2 t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+            Dft<4, DIR>::run(t);
+            a[k1] = t[0];
+            a[k1 + 4] = t[1];
+            a[k1 + 8] = t[2];
+            a[k1 + 12] = t[3];
+        }
+    }
+};
+
 template <int DIR> struct Dft<3, DIR> {
     static __device__ __forceinline__ void run(float2* a)
     {
@@ -117,11 +162,26 @@ template <int DIR> struct Dft<5, DIR> {
     }
 };
 
+// LDS element offset of position i in a pencil: with PAD the row layout gets
+// one spare slot every 16 elements, which spreads power-of-two strides over
+// all LDS banks.
+template <bool PAD>
+__device__ __forceinline__ constexpr int lidx(int i)
+{
+    return PAD ? i + (i >> 4) : i;
+}
+__host__ __device__ constexpr int padded_len(int n) { return n + (n >> 4) + 1; }
+
 // ---------------------------------------------------------------------------
-// radix plan: as many 8s as possible, then 4, 2, 3, 5
+// radix plan: as many 16s as possible, then 8, 4, 2, 3, 5
 __host__ __device__ constexpr int plan_radix(int n, int p)
 {
     int idx = 0;
+    while (n % 16 == 0 && n > 1) {
+        if (idx == p) return 16;
+        n /= 16;
+        ++idx;
+    }
     while (n % 8 == 0 && n > 1) {
         if (idx == p) return 8;
         n /= 8;
@@ -166,11 +226,28 @@ __host__ __device__ constexpr int plan_ns(int n, int p)
 
 __host__ __device__ constexpr bool plan_ok(int n) { return n >= 2 && plan_ns(n, plan_passes(n)) == n; }
 
+// the same radices in reverse order (used by inverse transforms that start
+// from the register-resident output of a forward transform)
+__host__ __device__ constexpr int plan_radix_rev(int n, int p) { return plan_radix(n, plan_passes(n) - 1 - p); }
+__host__ __device__ constexpr int plan_ns_rev(int n, int p)
+{
+    int ns = 1;
+    for (int i = 0; i < p; ++i) ns *= plan_radix_rev(n, i);
+    return ns;
+}
+
 // Element (pencil, i) of the LDS batch lives at s[pencil * PS + i * IS].
 // COLMAJOR: consecutive threads take consecutive pencils (use when PS == 1,
 // i.e. pencils interleaved column-wise); otherwise consecutive elements.
-template <int N, int R, int NS, int NPEN, int NT, int DIR, int PS, int IS, bool COLMAJOR>
-__device__ __forceinline__ void fft_pass(float2* s, const float2* __restrict__ tw)
+//
+// FROM_G: the pass reads its inputs through the loader ld(pencil, i) instead
+// of LDS; TO_G: it hands its outputs to the storer st(pencil, i, value)
+// instead of LDS.  The first pass of a transform can so read global memory
+// straight into registers and the last pass write registers straight out.
+// Twiddles tw[e] = exp(-2 pi i e / N) may live in LDS or global memory.
+template <int N, int R, int NS, int NPEN, int NT, int DIR, int PS, int IS, bool COLMAJOR, bool FROM_G, bool TO_G,
+          class Ld, class St, bool PAD = false>
+__device__ __forceinline__ void fft_pass(float2* s, const float2* tw, const Ld& ld, const St& st)
 {
     constexpr int M = N / R;
     constexpr int NB = NPEN * M;
@@ -186,7 +263,10 @@ __device__ __forceinline__ void fft_pass(float2* s, const float2* __restrict__ t
             const int j = COLMAJOR ? b / NPEN : b - pen * M;
             const int k = j % NS;
 #pragma unroll
-            for (int r = 0; r < R; ++r) a[q][r] = s[pen * PS + (j + r * M) * IS];
+            for (int r = 0; r < R; ++r) {
+                if constexpr (FROM_G) a[q][r] = ld(pen, j + r * M);
+                else a[q][r] = s[pen * PS + lidx<PAD>(j + r * M) * IS];
+            }
             if (NS > 1) {
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
@@ -198,7 +278,7 @@ __device__ __forceinline__ void fft_pass(float2* s, const float2* __restrict__ t
             Dft<R, DIR>::run(a[q]);
         }
     }
-    __syncthreads();
+    if constexpr (!FROM_G && !TO_G) __syncthreads();
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const int b = t + q * NT;
@@ -208,30 +288,183 @@ __device__ __forceinline__ void fft_pass(float2* s, const float2* __restrict__ t
             const int k = j % NS;
             const int base = (j / NS) * NS * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) s[pen * PS + (base + r * NS) * IS] = a[q][r];
+            for (int r = 0; r < R; ++r) {
+                if constexpr (TO_G) st(pen, base + r * NS, a[q][r]);
+                else s[pen * PS + lidx<PAD>(base + r * NS) * IS] = a[q][r];
+            }
         }
     }
-    __syncthreads();
+    if constexpr (!TO_G) __syncthreads();
 }
 
-template <int N, int P, int NPEN, int NT, int DIR, int PS, int IS, bool COLMAJOR>
+struct NoLd {
+    __device__ float2 operator()(int, int) const { return make_float2(0.f, 0.f); }
+};
+struct NoSt {
+    __device__ void operator()(int, int, float2) const {}
+};
+
+template <int N, int P, int NPEN, int NT, int DIR, int PS, int IS, bool COLMAJOR, bool LDG, bool STG, class Ld,
+          class St, bool PAD = false>
 struct FftPasses {
-    static __device__ __forceinline__ void run(float2* s, const float2* __restrict__ tw)
+    static __device__ __forceinline__ void run(float2* s, const float2* tw, const Ld& ld, const St& st)
     {
-        if constexpr (P < plan_passes(N)) {
-            fft_pass<N, plan_radix(N, P), plan_ns(N, P), NPEN, NT, DIR, PS, IS, COLMAJOR>(s, tw);
-            FftPasses<N, P + 1, NPEN, NT, DIR, PS, IS, COLMAJOR>::run(s, tw);
+        constexpr int NP = plan_passes(N);
+        if constexpr (P < NP) {
+            constexpr bool first = P == 0, last = P == NP - 1;
+            fft_pass<N, plan_radix(N, P), plan_ns(N, P), NPEN, NT, DIR, PS, IS, COLMAJOR, LDG && first, STG && last,
+                     Ld, St, PAD>(s, tw, ld, st);
+            FftPasses<N, P + 1, NPEN, NT, DIR, PS, IS, COLMAJOR, LDG, STG, Ld, St, PAD>::run(s, tw, ld, st);
         }
     }
 };
 
-// Transform NPEN pencils of length N held in LDS. The caller must have
-// synchronised after staging the data; the routine ends with a barrier.
-template <int N, int NPEN, int NT, int DIR, int PS, int IS, bool COLMAJOR>
-__device__ __forceinline__ void lds_fft(float2* s, const float2* __restrict__ tw)
+// Transform NPEN pencils of length N held in LDS (in place).  The caller
+// synchronises after staging the data; the routine ends with a barrier.
+template <int N, int NPEN, int NT, int DIR, int PS, int IS, bool COLMAJOR, bool PAD = false>
+__device__ __forceinline__ void lds_fft(float2* s, const float2* tw)
 {
     static_assert(plan_ok(N), "length must factor into 2, 3 and 5");
-    FftPasses<N, 0, NPEN, NT, DIR, PS, IS, COLMAJOR>::run(s, tw);
+    FftPasses<N, 0, NPEN, NT, DIR, PS, IS, COLMAJOR, false, false, NoLd, NoSt, PAD>::run(s, tw, NoLd{}, NoSt{});
+}
+
+// Transform NPEN pencils whose inputs come from ld(pencil, i) (first pass
+// reads straight into registers).  With STG the outputs go to st(pencil, i, v)
+// and the routine ends WITHOUT a barrier (the caller synchronises before it
+// writes the LDS buffer again); otherwise the result is left in LDS followed
+// by a barrier.  The caller must make sure the LDS buffer is no longer read
+// before the call when the plan has more than one pass.
+template <int N, int NPEN, int NT, int DIR, int PS, int IS, bool COLMAJOR, bool STG, class Ld, class St,
+          bool PAD = false>
+__device__ __forceinline__ void fft_ld(float2* s, const float2* tw, const Ld& ld, const St& st)
+{
+    static_assert(plan_ok(N), "length must factor into 2, 3 and 5");
+    FftPasses<N, 0, NPEN, NT, DIR, PS, IS, COLMAJOR, true, STG, Ld, St, PAD>::run(s, tw, ld, st);
+}
+
+// ---------------------------------------------------------------------------
+// Register-resident ends.  For a Stockham plan whose last pass has radix RL,
+// thread t ends holding, for each of its butterflies b = t + q NT (pencil and
+// j from b as in fft_pass), the RL outputs j + r (N / RL).  An inverse run
+// with the reversed plan starts from exactly that set, so a forward transform,
+// a pointwise multiply and an inverse transform need no LDS round trip in
+// between.  reg_coords gives (pencil, element) of a[q][r].
+template <int N, int R, int NPEN, int NT, bool COLMAJOR>
+__device__ __forceinline__ bool reg_coords(int q, int r, int& pen, int& idx)
+{
+    constexpr int M = N / R;
+    constexpr int NB = NPEN * M;
+    const int b = threadIdx.x + q * NT;
+    pen = COLMAJOR ? b % NPEN : b / M;
+    const int j = COLMAJOR ? b / NPEN : b - pen * M;
+    idx = j + r * M;
+    return (NB % NT == 0) || b < NB;
+}
+
+// One pass of a plan (REV selects the reversed radix order) with the inputs
+// in registers (FROM_R) and/or the outputs left in registers (TO_R).
+template <int N, int P, bool REV, int NPEN, int NT, int DIR, int PS, int IS, bool COLMAJOR, bool FROM_G, bool FROM_R,
+          bool TO_G, bool TO_R, class Ld, class St, class RIn, class ROut>
+__device__ __forceinline__ void fft_pass_r(float2* s, const float2* tw, const Ld& ld, const St& st, RIn& rin,
+                                           ROut& rout)
+{
+    constexpr int R = REV ? plan_radix_rev(N, P) : plan_radix(N, P);
+    constexpr int NS = REV ? plan_ns_rev(N, P) : plan_ns(N, P);
+    constexpr int M = N / R;
+    constexpr int NB = NPEN * M;
+    constexpr int Q = (NB + NT - 1) / NT;
+    constexpr int TS = N / (NS * R);
+    float2 a[Q][R];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int b = t + q * NT;
+        if ((NB % NT == 0) || b < NB) {
+            const int pen = COLMAJOR ? b % NPEN : b / M;
+            const int j = COLMAJOR ? b / NPEN : b - pen * M;
+            const int k = j % NS;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if constexpr (FROM_R) a[q][r] = rin[q][r];
+                else if constexpr (FROM_G) a[q][r] = ld(pen, j + r * M);
+                else a[q][r] = s[pen * PS + (j + r * M) * IS];
+            }
+            if (NS > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    float2 w = tw[r * k * TS];
+                    if (DIR > 0) w.y = -w.y;
+                    a[q][r] = c_mul(a[q][r], w);
+                }
+            }
+            Dft<R, DIR>::run(a[q]);
+        }
+    }
+    if constexpr (!FROM_G && !FROM_R && !TO_G && !TO_R) __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int b = t + q * NT;
+        if ((NB % NT == 0) || b < NB) {
+            const int pen = COLMAJOR ? b % NPEN : b / M;
+            const int j = COLMAJOR ? b / NPEN : b - pen * M;
+            const int k = j % NS;
+            const int base = (j / NS) * NS * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if constexpr (TO_R) rout[q][r] = a[q][r];
+                else if constexpr (TO_G) st(pen, base + r * NS, a[q][r]);
+                else s[pen * PS + (base + r * NS) * IS] = a[q][r];
+            }
+        }
+    }
+    if constexpr (!TO_G && !TO_R) __syncthreads();
+}
+
+template <int N, int P, bool REV, int NPEN, int NT, int DIR, int PS, int IS, bool COLMAJOR, bool LDG, bool LDR,
+          bool STG, bool STR, class Ld, class St, class RIn, class ROut>
+struct FftPassesR {
+    static __device__ __forceinline__ void run(float2* s, const float2* tw, const Ld& ld, const St& st, RIn& rin,
+                                               ROut& rout)
+    {
+        constexpr int NP = plan_passes(N);
+        if constexpr (P < NP) {
+            constexpr bool first = P == 0, last = P == NP - 1;
+            fft_pass_r<N, P, REV, NPEN, NT, DIR, PS, IS, COLMAJOR, LDG && first, LDR && first, STG && last,
+                       STR && last, Ld, St, RIn, ROut>(s, tw, ld, st, rin, rout);
+            FftPassesR<N, P + 1, REV, NPEN, NT, DIR, PS, IS, COLMAJOR, LDG, LDR, STG, STR, Ld, St, RIn, ROut>::run(
+                s, tw, ld, st, rin, rout);
+        }
+    }
+};
+
+// register array shapes of the first / last pass
+template <int N, int NPEN, int NT>
+struct RegShape {
+    static constexpr int RL = plan_radix(N, plan_passes(N) - 1);   // forward last = reversed first
+    static constexpr int QL = (NPEN * (N / RL) + NT - 1) / NT;
+};
+
+// Forward-plan transform from ld(pencil, i) leaving the outputs in registers
+// (no trailing barrier: the caller synchronises before it writes s again).
+template <int N, int NPEN, int NT, int DIR, int PS, int IS, bool COLMAJOR, class Ld, class ROut>
+__device__ __forceinline__ void fft_g2r(float2* s, const float2* tw, const Ld& ld, ROut& rout)
+{
+    static_assert(plan_ok(N), "length must factor into 2, 3 and 5");
+    float2 dummy[1][1];
+    FftPassesR<N, 0, false, NPEN, NT, DIR, PS, IS, COLMAJOR, true, false, false, true, Ld, NoSt, float2[1][1],
+               ROut>::run(s, tw, ld, NoSt{}, dummy, rout);
+}
+
+// Reversed-plan transform from registers to st(pencil, i, v) (no trailing
+// barrier; the caller synchronises before the first pass writes s when s was
+// read just before).
+template <int N, int NPEN, int NT, int DIR, int PS, int IS, bool COLMAJOR, class RIn, class St>
+__device__ __forceinline__ void fft_r2g(float2* s, const float2* tw, RIn& rin, const St& st)
+{
+    static_assert(plan_ok(N), "length must factor into 2, 3 and 5");
+    float2 dummy[1][1];
+    FftPassesR<N, 0, true, NPEN, NT, DIR, PS, IS, COLMAJOR, false, true, true, false, NoLd, St, RIn,
+               float2[1][1]>::run(s, tw, NoLd{}, st, rin, dummy);
 }
 
 }  // namespace pstd

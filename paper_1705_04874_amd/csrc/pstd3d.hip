@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -37,7 +38,7 @@ constexpr int NT = 256;
 // ---------------------------------------------------------------------------
 // per-length kernel launchers
 struct XFns {
-    void (*vel)(dim3, hipStream_t, Geo, Mat, Pml, const float2*, float*, float2*, Rec, float*, const int*, int, int);
+    void (*vel)(dim3, hipStream_t, Geo, Mat, Pml, const float2*, float*, float2*, Rec, float*, const int*, int*, int, int);
     void (*str)(dim3, hipStream_t, Geo, Mat, Pml, const float2*, float*, float2*, Rec, Inj, float*, const int*, int, int);
     void (*xfwd)(dim3, hipStream_t, Geo, const float2*, const float*, long, float2*, long, SumDesc);
     void (*xinv)(dim3, hipStream_t, Geo, const float2*, const float2*, float*);
@@ -56,9 +57,9 @@ struct ZFns {
 template <int N>
 struct Launch {
     static void vel(dim3 gr, hipStream_t st, Geo g, Mat m, Pml p, const float2* tw, float* f, float2* s, Rec r,
-                    float* tr, const int* sp, int n0, int ldt)
+                    float* tr, const int* sp, int* sn, int n0, int ldt)
     {
-        hipLaunchKernelGGL((k_vel<N, NT>), gr, dim3(NT), 0, st, g, m, p, tw, f, s, r, tr, sp, n0, ldt);
+        hipLaunchKernelGGL((k_vel<N, NT>), gr, dim3(NT), 0, st, g, m, p, tw, f, s, r, tr, sp, sn, n0, ldt);
     }
     static void str(dim3 gr, hipStream_t st, Geo g, Mat m, Pml p, const float2* tw, float* f, float2* s, Rec r,
                     Inj in, float* tr, const int* sp, int n0, int ldt)
@@ -207,7 +208,7 @@ struct pstd3d_ctx {
     int nx = 0, ny = 0, nz = 0;
     double h[3] = {0, 0, 0}, dt = 0, c_ref = 0, cmax = 0;
     int pml = 0, kspace = 1;
-    double pml_A = 0;
+    double pml_A = 0, pml_p = 0;
     int n_rec = 0;
     int device = 0;
     Geo g{};
@@ -367,24 +368,26 @@ int build_model(pstd3d_ctx* c, const pstd3d_model* m)
     c->M.dmu2 = c->mat + 4 * n;
     for (int p = 0; p < 3; ++p) c->M.dmus[p] = c->mat + (5 + p) * n;
 
-    // PML factors
+    // PML factors a = exp(-alpha dt/2) and multi-axial factors b = a^p
     const int N[3] = {nx, ny, nz};
-    std::vector<float> hp(2 * (nx + ny + nz));
-    size_t off[3][2];
+    std::vector<float> hp(4 * (nx + ny + nz));
+    size_t off[3][4];
     size_t o = 0;
-    for (int d = 0; d < 3; ++d) {
-        off[d][0] = o;
-        for (int i = 0; i < N[d]; ++i)
-            hp[o++] = (float)std::exp(-pml_alpha(i, N[d], c->pml, c->pml_A, c->c_ref, c->h[d]) * dt / 2);
-        off[d][1] = o;
-        for (int i = 0; i < N[d]; ++i)
-            hp[o++] = (float)std::exp(-pml_alpha(i + 0.5, N[d], c->pml, c->pml_A, c->c_ref, c->h[d]) * dt / 2);
-    }
+    for (int d = 0; d < 3; ++d)
+        for (int kind = 0; kind < 4; ++kind) {
+            off[d][kind] = o;
+            const double shift = (kind & 1) ? 0.5 : 0.0;
+            const double pw = (kind & 2) ? c->pml_p : 1.0;
+            for (int i = 0; i < N[d]; ++i)
+                hp[o++] = (float)std::exp(-pw * pml_alpha(i + shift, N[d], c->pml, c->pml_A, c->c_ref, c->h[d]) * dt / 2);
+        }
     rc = dev_upload(&c->pmlb, hp);
     if (rc) return rc;
     for (int d = 0; d < 3; ++d) {
         c->P.ai[d] = c->pmlb + off[d][0];
         c->P.ah[d] = c->pmlb + off[d][1];
+        c->P.bi[d] = c->pmlb + off[d][2];
+        c->P.bh[d] = c->pmlb + off[d][3];
     }
 
     // twiddles exp(-2 pi i e / N) per axis
@@ -426,8 +429,10 @@ int build_model(pstd3d_ctx* c, const pstd3d_model* m)
     for (int d = 0; d < 3; ++d)
         for (int plus = 0; plus < 2; ++plus) c->O.sym[d][plus] = c->sym + soff[d][plus];
 
-    // k-space correction with the 1/(nx ny nz) of the inverse transform folded in
-    std::vector<float> hk((size_t)nz * ny * c->g.ldx, 0.0f);
+    // k-space correction with the 1/(nx ny nz) of the inverse transform folded
+    // in; main block [nz][ny][ldx] (kx < nxm) followed by the Nyquist plane
+    const size_t kmain = (size_t)nz * ny * c->g.ldx;
+    std::vector<float> hk(kmain + (size_t)nz * ny, 0.0f);
     const double inv_n = 1.0 / (double)n;
     for (int k = 0; k < nz; ++k) {
         const double kz = kval(k, nz, c->h[2]);
@@ -438,13 +443,15 @@ int build_model(pstd3d_ctx* c, const pstd3d_model* m)
                 const double q = std::sqrt(kx * kx + ky * ky + kz * kz);
                 const double arg = 0.5 * c->c_ref * q * dt;
                 const double kap = (c->kspace && arg != 0.0) ? std::sin(arg) / arg : 1.0;
-                hk[((size_t)k * ny + j) * c->g.ldx + i] = (float)(kap * inv_n);
+                const size_t at = i < c->g.nxm ? ((size_t)k * ny + j) * c->g.ldx + i : kmain + (size_t)k * ny + j;
+                hk[at] = (float)(kap * inv_n);
             }
         }
     }
     rc = dev_upload(&c->kap, hk);
     if (rc) return rc;
     c->O.kap = c->kap;
+    c->O.kapn = c->kap + kmain;
     {
         std::vector<ZDesc> zd(1);
         zd[0].ph[0] = phase_v();
@@ -469,8 +476,8 @@ int build_model(pstd3d_ctx* c, const pstd3d_model* m)
     rc = dev_upload(&c->rec_ent, re);
     if (rc) return rc;
 
-    HIP_TRY(hipMalloc(&c->stepd, sizeof(int)));
-    HIP_TRY(hipMemset(c->stepd, 0, sizeof(int)));
+    HIP_TRY(hipMalloc(&c->stepd, 2 * sizeof(int)));
+    HIP_TRY(hipMemset(c->stepd, 0, 2 * sizeof(int)));
     HIP_TRY(hipMalloc(&c->flag, sizeof(int)));
     c->bytes = (long)(hm.size() * 4 + hp.size() * 4 + ht.size() * 8 + hs.size() * 8 + hk.size() * 4 +
                       rp.size() * 4 + re.size() * 16);
@@ -481,13 +488,17 @@ Rec rec_of(const pstd3d_ctx* c) { return Rec{c->rec_ptr, c->rec_ent, c->n_rec}; 
 Inj inj_of(const pstd3d_ctx* c) { return Inj{c->inj_ptr, c->inj_ent, c->wav, c->nt_w}; }
 
 // one leapfrog step of every shot of a context
-void enqueue_step(pstd3d_ctx* c, hipStream_t st, float* traces, int n0, int ldt)
+// Step n reads the step counter word n & 1 and the velocity kernel writes n + 1
+// into the other word.
+void enqueue_step(pstd3d_ctx* c, hipStream_t st, float* traces, int n0, int ldt, int parity)
 {
+    const int* cur = c->stepd + parity;
+    int* nxt = c->stepd + (parity ^ 1);
     const Geo& g = c->g;
     const int S = c->n_shots;
     const dim3 gx((g.nrows + c->xf.rows - 1) / c->xf.rows, S);
-    const int ty = c->yf.tile, tz = c->zf.tile;
-    const int tyn = (g.nxh + ty - 1) / ty, tzn = (g.nxh + tz - 1) / tz;
+    const int tyn = (g.nxm + c->yf.tile - 1) / c->yf.tile + g.has_nyq;
+    const int tzn = (g.nxm + c->zf.tile - 1) / c->zf.tile + g.has_nyq;
     long e;
     // V phase
     e = c->ev_begin(PSTD_K_YFWD_S, st);
@@ -500,7 +511,7 @@ void enqueue_step(pstd3d_ctx* c, hipStream_t st, float* traces, int n0, int ldt)
     c->yf.inv(dim3(tyn, g.nz, S * 9), st, g, c->twy, c->spec, 9, 9);
     c->ev_end(e, st);
     e = c->ev_begin(PSTD_K_VEL, st);
-    c->xf.vel(gx, st, g, c->M, c->P, c->twx, c->fields, c->spec, rec_of(c), traces, c->stepd, n0, ldt);
+    c->xf.vel(gx, st, g, c->M, c->P, c->twx, c->fields, c->spec, rec_of(c), traces, cur, nxt, n0, ldt);
     c->ev_end(e, st);
     // S phase
     e = c->ev_begin(PSTD_K_YFWD_V, st);
@@ -513,9 +524,8 @@ void enqueue_step(pstd3d_ctx* c, hipStream_t st, float* traces, int n0, int ldt)
     c->yf.inv(dim3(tyn, g.nz, S * 9), st, g, c->twy, c->spec, 9, 9);
     c->ev_end(e, st);
     e = c->ev_begin(PSTD_K_STR, st);
-    c->xf.str(gx, st, g, c->M, c->P, c->twx, c->fields, c->spec, rec_of(c), inj_of(c), traces, c->stepd, n0, ldt);
+    c->xf.str(gx, st, g, c->M, c->P, c->twx, c->fields, c->spec, rec_of(c), inj_of(c), traces, cur, n0, ldt);
     c->ev_end(e, st);
-    hipLaunchKernelGGL(k_step_inc, dim3(1), dim3(64), 0, st, c->stepd);
 }
 
 bool len_ok(int n)
@@ -554,8 +564,9 @@ int pstd3d_create(const pstd3d_model* m, const double d[3], double dt, const pst
     if (nx < 2 || ny < 2 || nz < 2) return fail(PSTD_EINVAL, "grid must be at least 2 cells per axis");
     if (!m->vp || !m->vs || !m->rho) return fail(PSTD_EINVAL, "null model array");
     if (!(d[0] > 0) || !(d[1] > 0) || !(d[2] > 0) || !(dt > 0)) return fail(PSTD_EINVAL, "spacing and dt must be > 0");
-    if (pml->thickness < 0 || 2 * pml->thickness > std::min(nx, std::min(ny, nz)) || !(pml->A >= 0))
-        return fail(PSTD_EINVAL, "bad PML thickness or strength");
+    if (pml->thickness < 0 || 2 * pml->thickness > std::min(nx, std::min(ny, nz)) || !(pml->A >= 0) ||
+        !(pml->mratio >= 0 && pml->mratio <= 1))
+        return fail(PSTD_EINVAL, "bad PML thickness, strength or multi-axial ratio");
     if (!len_ok(nx) || !len_ok(ny) || !len_ok(nz))
         return fail(PSTD_EUNSUPPORTED, "grid length not built (lengths factor into 2, 3, 5; see PSTD_LENGTHS)");
     if (m->n_rec < 0 || (m->n_rec > 0 && !m->rec_ijk)) return fail(PSTD_EINVAL, "bad receivers");
@@ -593,6 +604,7 @@ int pstd3d_create(const pstd3d_model* m, const double d[3], double dt, const pst
     c->cmax = cmax;
     c->pml = pml->thickness;
     c->pml_A = pml->A;
+    c->pml_p = pml->mratio;
     c->kspace = m->kspace ? 1 : 0;
     c->n_rec = m->n_rec;
     (void)hipGetDevice(&c->device);
@@ -604,10 +616,14 @@ int pstd3d_create(const pstd3d_model* m, const double d[3], double dt, const pst
     g.ny = ny;
     g.nz = nz;
     g.nxh = nx / 2 + 1;
-    g.ldx = (g.nxh + 15) / 16 * 16;
+    g.has_nyq = nx % 2 == 0;
+    g.nxm = g.has_nyq ? nx / 2 : g.nxh;
+    g.ldx = (g.nxm + 15) / 16 * 16;
     g.nrows = ny * nz;
     g.n = n;
-    g.nspec = (long)nz * ny * g.ldx;
+    g.nqoff = (long)nz * ny * g.ldx;
+    // Nyquist plane after the main block; spectra start on 256-byte boundaries
+    g.nspec = (g.nqoff + (g.has_nyq ? (long)nz * ny : 0) + 31) / 32 * 32;
     g.fstride = 24 * n;
     g.sstride = 18 * g.nspec;
     int rc = build_model(c, m);
@@ -700,7 +716,7 @@ int pstd3d_set_sources(pstd3d_ctx* c, int n_shots, const int32_t* shot_ofs, cons
     c->nt_w = nt_w;
     c->n_shots = n_shots;
     c->step = 0;
-    HIP_TRY(hipMemset(c->stepd, 0, sizeof(int)));
+    HIP_TRY(hipMemset(c->stepd, 0, 2 * sizeof(int)));
     HIP_TRY(hipDeviceSynchronize());
     return PSTD_OK;
 }
@@ -716,6 +732,109 @@ static int check_traces(pstd3d_ctx* c, const float* traces, long count, hipStrea
     return PSTD_OK;
 }
 
+// HIP graph of two consecutive steps of several contexts: each context's two
+// steps are captured on its own stream branch (forked from and joined into a
+// private origin stream), so independent models run concurrently.
+static int capture_pair(pstd3d_ctx* const* ctxs, int n, float* const* traces, const int* n0, int ldt,
+                        hipGraphExec_t* out)
+{
+    hipStream_t origin = nullptr;
+    std::vector<hipStream_t> br(n, nullptr);
+    std::vector<hipEvent_t> join(n, nullptr);
+    hipEvent_t fork = nullptr;
+    hipGraph_t graph = nullptr;
+    int rc = PSTD_OK;
+    auto cleanup = [&]() {
+        if (graph) (void)hipGraphDestroy(graph);
+        for (auto e : join)
+            if (e) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
+        for (auto s : br)
+            if (s) (void)hipStreamDestroy(s);
+        if (origin) (void)hipStreamDestroy(origin);
+    };
+#define CAP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            rc = fail(PSTD_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+            cleanup();                                                                   \
+            return rc;                                                                   \
+        }                                                                                \
+    } while (0)
+    CAP_TRY(hipStreamCreateWithFlags(&origin, hipStreamNonBlocking));
+    CAP_TRY(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    for (int i = 0; i < n; ++i) {
+        CAP_TRY(hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking));
+        CAP_TRY(hipEventCreateWithFlags(&join[i], hipEventDisableTiming));
+    }
+    CAP_TRY(hipStreamBeginCapture(origin, hipStreamCaptureModeThreadLocal));
+    hipError_t ce = hipEventRecord(fork, origin);
+    for (int i = 0; i < n && ce == hipSuccess; ++i) {
+        ce = hipStreamWaitEvent(br[i], fork, 0);
+        for (int s = 0; s < 2 && ce == hipSuccess; ++s) enqueue_step(ctxs[i], br[i], traces[i], n0[i], ldt, (n0[i] + s) & 1);
+        if (ce == hipSuccess) ce = hipGetLastError();
+        if (ce == hipSuccess) ce = hipEventRecord(join[i], br[i]);
+        if (ce == hipSuccess) ce = hipStreamWaitEvent(origin, join[i], 0);
+    }
+    hipError_t ee = hipStreamEndCapture(origin, &graph);
+    if (ce != hipSuccess || ee != hipSuccess) {
+        rc = fail(PSTD_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce != hipSuccess ? ce : ee));
+        cleanup();
+        return rc;
+    }
+    CAP_TRY(hipGraphInstantiate(out, graph, nullptr, nullptr, 0));
+    cleanup();
+    return PSTD_OK;
+#undef CAP_TRY
+}
+
+static bool graphs_enabled()
+{
+    const char* e = std::getenv("PSTD_GRAPH");
+    return !(e && e[0] == '0');
+}
+
+// Advance contexts by nt steps: pairs of steps replay one captured graph,
+// an odd last step (and runs with event timing) go out eagerly.
+static int advance(pstd3d_ctx* const* ctxs, int n, int nt, float* const* traces, hipStream_t st)
+{
+    std::vector<int> n0(n);
+    bool prof = false;
+    for (int i = 0; i < n; ++i) {
+        n0[i] = (int)ctxs[i]->step;
+        prof = prof || ctxs[i]->prof;
+    }
+    int done = 0;
+    if (!prof && graphs_enabled() && nt >= 4) {
+        hipGraphExec_t ex = nullptr;
+        int rc = capture_pair(ctxs, n, traces, n0.data(), nt, &ex);
+        if (rc) return rc;
+        for (; done + 2 <= nt; done += 2) {
+            hipError_t e = hipGraphLaunch(ex, st);
+            if (e != hipSuccess) {
+                (void)hipGraphExecDestroy(ex);
+                return fail(PSTD_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+            }
+        }
+        HIP_TRY(hipStreamSynchronize(st));
+        (void)hipGraphExecDestroy(ex);
+    }
+    for (; done < nt; ++done) {
+        for (int i = 0; i < n; ++i) {
+            pstd3d_ctx* c = ctxs[i];
+            enqueue_step(c, st, traces[i], n0[i], nt, (n0[i] + done) & 1);
+            if (c->prof && c->evused >= 4096) {
+                HIP_TRY(hipStreamSynchronize(st));
+                c->ev_collect();
+            }
+        }
+    }
+    HIP_TRY(hipGetLastError());
+    for (int i = 0; i < n; ++i) ctxs[i]->step += nt;
+    return PSTD_OK;
+}
+
 int pstd3d_run(pstd3d_ctx* c, int nt, float* traces_dev, void* hip_stream)
 {
     if (!c || nt < 0) return fail(PSTD_EINVAL, "bad arguments");
@@ -724,19 +843,35 @@ int pstd3d_run(pstd3d_ctx* c, int nt, float* traces_dev, void* hip_stream)
     if (c->step + nt > 2147483647L) return fail(PSTD_EINVAL, "step index overflow");
     HIP_TRY(hipSetDevice(c->device));
     hipStream_t st = (hipStream_t)hip_stream;
-    const int n0 = (int)c->step;
-    for (int n = 0; n < nt; ++n) {
-        enqueue_step(c, st, traces_dev, n0, nt);
-        if (c->prof && c->evused >= 4096) {
-            HIP_TRY(hipStreamSynchronize(st));
-            c->ev_collect();
-        }
-    }
-    HIP_TRY(hipGetLastError());
-    c->step += nt;
-    int rc = check_traces(c, traces_dev, (long)c->n_shots * 4 * c->n_rec * nt, st);
+    int rc = advance(&c, 1, nt, &traces_dev, st);
+    if (rc) return rc;
+    rc = check_traces(c, traces_dev, (long)c->n_shots * 4 * c->n_rec * nt, st);
     if (c->prof) c->ev_collect();
     return rc;
+}
+
+int pstd3d_run_many(pstd3d_ctx* const* ctxs, int n, int nt, float* const* traces, void* hip_stream)
+{
+    if (!ctxs || n < 1 || nt < 0 || !traces) return fail(PSTD_EINVAL, "bad arguments");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i] || ctxs[i]->n_shots == 0) return fail(PSTD_EINVAL, "context without shots");
+        if (nt > 0 && ctxs[i]->n_rec > 0 && !traces[i]) return fail(PSTD_EINVAL, "null trace buffer");
+        if (ctxs[i]->device != dev) return fail(PSTD_EINVAL, "contexts must live on the current device");
+        if (ctxs[i]->step + nt > 2147483647L) return fail(PSTD_EINVAL, "step index overflow");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return fail(PSTD_EINVAL, "a context appears twice");
+    }
+    hipStream_t st = (hipStream_t)hip_stream;
+    int rc = advance(ctxs, n, nt, traces, st);
+    if (rc) return rc;
+    for (int i = 0; i < n; ++i) {
+        rc = check_traces(ctxs[i], traces[i], (long)ctxs[i]->n_shots * 4 * ctxs[i]->n_rec * nt, st);
+        if (ctxs[i]->prof) ctxs[i]->ev_collect();
+        if (rc) return rc;
+    }
+    return PSTD_OK;
 }
 
 int pstd3d_reset(pstd3d_ctx* c, void* hip_stream)
@@ -746,7 +881,7 @@ int pstd3d_reset(pstd3d_ctx* c, void* hip_stream)
     hipStream_t st = (hipStream_t)hip_stream;
     HIP_TRY(hipMemsetAsync(c->fields, 0, (size_t)c->n_shots * c->g.fstride * sizeof(float), st));
     HIP_TRY(hipMemsetAsync(c->spec, 0, (size_t)c->n_shots * c->g.sstride * sizeof(float2), st));
-    HIP_TRY(hipMemsetAsync(c->stepd, 0, sizeof(int), st));
+    HIP_TRY(hipMemsetAsync(c->stepd, 0, 2 * sizeof(int), st));
     c->step = 0;
     return PSTD_OK;
 }
@@ -772,28 +907,6 @@ int pstd3d_profile_read(const pstd3d_ctx* c, int kind, double* total_ms, long* l
     return PSTD_OK;
 }
 
-int pstd3d_run_many(pstd3d_ctx* const* ctxs, int n, int nt, float* const* traces, void* hip_stream)
-{
-    if (!ctxs || n < 1 || nt < 0 || !traces) return fail(PSTD_EINVAL, "bad arguments");
-    for (int i = 0; i < n; ++i) {
-        if (!ctxs[i] || ctxs[i]->n_shots == 0) return fail(PSTD_EINVAL, "context without shots");
-        if (nt > 0 && ctxs[i]->n_rec > 0 && !traces[i]) return fail(PSTD_EINVAL, "null trace buffer");
-    }
-    hipStream_t st = (hipStream_t)hip_stream;
-    int n0[64];
-    if (n > 64) return fail(PSTD_EINVAL, "at most 64 contexts per call");
-    for (int i = 0; i < n; ++i) n0[i] = (int)ctxs[i]->step;
-    for (int s = 0; s < nt; ++s)
-        for (int i = 0; i < n; ++i) enqueue_step(ctxs[i], st, traces[i], n0[i], nt);
-    HIP_TRY(hipGetLastError());
-    for (int i = 0; i < n; ++i) {
-        ctxs[i]->step += nt;
-        int rc = check_traces(ctxs[i], traces[i], (long)ctxs[i]->n_shots * 4 * ctxs[i]->n_rec * nt, st);
-        if (rc) return rc;
-    }
-    return PSTD_OK;
-}
-
 int pstd3d_get_state(pstd3d_ctx* c, int shot, float* fields_host)
 {
     if (!c || !fields_host || shot < 0 || shot >= c->n_shots) return fail(PSTD_EINVAL, "bad arguments");
@@ -814,7 +927,7 @@ int pstd3d_set_state(pstd3d_ctx* c, int shot, const float* fields_host, long ste
                       hipMemcpyHostToDevice));
     enqueue_restore_spectra(c, nullptr);
     const int s32 = (int)step;
-    HIP_TRY(hipMemcpy(c->stepd, &s32, sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->stepd + (s32 & 1), &s32, sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(hipDeviceSynchronize());
     c->step = step;
     return PSTD_OK;
@@ -837,8 +950,8 @@ int pstd3d_derivs(pstd3d_ctx* c, int phase, const float* in_dev, float* out_dev,
     }
     const int in0 = phase == 0 ? 0 : 6;
     const dim3 gx((g.nrows + c->xf.rows - 1) / c->xf.rows, 1);
-    const int ty = c->yf.tile, tz = c->zf.tile;
-    const int tyn = (g.nxh + ty - 1) / ty, tzn = (g.nxh + tz - 1) / tz;
+    const int tyn = (g.nxm + c->yf.tile - 1) / c->yf.tile + g.has_nyq;
+    const int tzn = (g.nxm + c->zf.tile - 1) / c->zf.tile + g.has_nyq;
     // shot 0 scratch: spectra in0.. and the derivative block
     c->xf.xfwd(gx, st, g, c->twx, in_dev, 0, c->spec + in0 * g.nspec, 0, sd);
     c->yf.fwd(dim3(tyn, g.nz, sd.nf), st, g, c->twy, c->spec, in0, sd.nf);

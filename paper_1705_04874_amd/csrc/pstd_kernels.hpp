@@ -8,16 +8,22 @@
 //   S phase: y FFT --> z operator --> inverse y FFT --> [inverse x FFT +
 //            stress update + source injection + receivers + x FFT of the 6
 //            summed stresses]
-// Real fields are [nz][ny][nx]; x-transformed spectra are [nz][ny][ldx]
-// complex with kx = 0 .. nx/2 (ldx >= nx/2 + 1, padded to 128-byte rows).
+// Real fields are [nz][ny][nx].  An x-transformed spectrum (kx = 0 .. nx/2)
+// is stored as a main block [nz][ny][ldx] holding kx < nxm (nxm = nx/2 for
+// even nx, (nx+1)/2 for odd nx; ldx = nxm rounded up to 16, i.e. 128-byte
+// rows) followed, for even nx, by the Nyquist plane kx = nx/2 as [nz][ny].
+// The y and z transforms work on 16-column tiles of the main block plus
+// tiles of 16 Nyquist pencils, so no tile is left almost empty.
 #pragma once
 #include "fft_lds.hpp"
 
 namespace pstd {
 
 struct Geo {
-    int nx, ny, nz, nxh, ldx, nrows;   // nrows = ny * nz
+    int nx, ny, nz, nxh, ldx, nrows;   // nrows = ny * nz; nxh = nx/2 + 1
+    int nxm, has_nyq;                  // main columns, Nyquist plane present
     long n;                            // cells
+    long nqoff;                        // offset of the Nyquist plane in a spectrum
     long nspec;                        // complex values per spectrum
     long fstride;                      // floats per shot of split fields (24 n)
     long sstride;                      // complex values per shot of spectra (18 nspec)
@@ -31,10 +37,14 @@ struct Mat {
     const float* dmus[3];  // dt * mu at xy, xz, yz shear nodes
 };
 
-// PML factors a = exp(-alpha dt / 2) per axis, at integer and half nodes
+// PML factors a = exp(-alpha dt / 2) per axis, at integer and half nodes, and
+// the multi-axial factors b = a^p: a split part along axis d is damped by
+// a_d times b_e of the two other axes e.
 struct Pml {
     const float* ai[3];
     const float* ah[3];
+    const float* bi[3];
+    const float* bh[3];
 };
 
 struct Rec {
@@ -61,7 +71,8 @@ struct PhaseDesc {
 
 struct Ops {
     const float2* sym[3][2];   // per axis, [0] = D-, [1] = D+ : i k exp(-+ i k h/2)
-    const float* kap;          // kappa(|k|) / (nx ny nz), [nz][ny][ldx]
+    const float* kap;          // kappa(|k|) / (nx ny nz), main block [nz][ny][ldx]
+    const float* kapn;         // the same on the Nyquist plane [nz][ny]
 };
 
 // device-resident descriptor of the two derivative phases (read with uniform
@@ -74,34 +85,41 @@ struct ZDesc {
 constexpr int rows_for(int nx) { return nx <= 32 ? 16 : nx <= 64 ? 8 : nx <= 160 ? 4 : 2; }
 constexpr int tile_for(int n) { return n >= 384 ? 8 : 16; }
 
-// value of real pencil p (= field * ROWS + local row) of a staged spectrum row
+// index of spectrum element (row, kx) within one field's spectrum
+__device__ __forceinline__ long spec_idx(const Geo& g, int row, int k)
+{
+    return k < g.nxm ? (long)row * g.ldx + k : g.nqoff + row;
+}
+
+// value of real pencil p (= field * ROWS + local row) of a spectrum row
 __device__ __forceinline__ float2 spec_at(const float2* __restrict__ base, const Geo& g, int rows,
                                           int row0, int p, int k)
 {
     const int f = p / rows, r = p - f * rows;
     const int row = row0 + r;
     if (row >= g.nrows) return make_float2(0.f, 0.f);
-    return base[f * g.nspec + (long)row * g.ldx + k];
+    return base[f * g.nspec + spec_idx(g, row, k)];
 }
 
-// Stage NPI complex pencils, each the Hermitian extension of two half spectra
-// (real pencils 2q and 2q+1), so one complex inverse FFT gives both real rows.
-template <int NX, int ROWS, int NT, int NPI, int PS>
-__device__ __forceinline__ void stage_c2r(float2* s, const float2* __restrict__ src, const Geo& g, int row0)
-{
-    constexpr int NXH = NX / 2 + 1;
-    for (int e = threadIdx.x; e < NPI * NXH; e += NT) {
-        const int q = e / NXH, k = e - q * NXH;
-        float2 a = spec_at(src, g, ROWS, row0, 2 * q, k);
-        float2 b = spec_at(src, g, ROWS, row0, 2 * q + 1, k);
-        if (k == 0 || 2 * k == NX) {
-            s[q * PS + k] = make_float2(a.x, b.x);
-        } else {
-            s[q * PS + k] = make_float2(a.x - b.y, a.y + b.x);
-            s[q * PS + NX - k] = make_float2(a.x + b.y, b.x - a.y);
-        }
+// Loader for an inverse x transform: complex pencil q is the Hermitian
+// extension of the half spectra of real pencils 2q and 2q+1 (Z = A + i B), so
+// one complex inverse FFT gives both real rows (as real and imaginary parts).
+// DC and Nyquist keep only their real parts.
+template <int NX, int ROWS>
+struct HermLoader {
+    const float2* __restrict__ src;
+    Geo g;
+    int row0;
+    __device__ float2 operator()(int q, int i) const
+    {
+        const bool hi = 2 * i > NX;
+        const int k = hi ? NX - i : i;
+        const float2 a = spec_at(src, g, ROWS, row0, 2 * q, k);
+        const float2 b = spec_at(src, g, ROWS, row0, 2 * q + 1, k);
+        if (k == 0 || 2 * k == NX) return make_float2(a.x, b.x);
+        return hi ? make_float2(a.x + b.y, b.x - a.y) : make_float2(a.x - b.y, a.y + b.x);
     }
-}
+};
 
 // Unpack NPO complex forward transforms of paired real rows into half spectra.
 template <int NX, int ROWS, int NT, int NPO, int PS>
@@ -110,8 +128,8 @@ __device__ __forceinline__ void unstage_r2c(const float2* s, float2* __restrict_
     constexpr int NXH = NX / 2 + 1;
     for (int e = threadIdx.x; e < NPO * NXH; e += NT) {
         const int q = e / NXH, k = e - q * NXH;
-        const float2 z = s[q * PS + k];
-        const float2 zm = s[q * PS + (k == 0 ? 0 : NX - k)];
+        const float2 z = s[q * PS + lidx<true>(k)];
+        const float2 zm = s[q * PS + lidx<true>(k == 0 ? 0 : NX - k)];
         const float2 A = make_float2(0.5f * (z.x + zm.x), 0.5f * (z.y - zm.y));
         const float2 B = make_float2(0.5f * (z.y + zm.y), -0.5f * (z.x - zm.x));
 #pragma unroll
@@ -119,7 +137,7 @@ __device__ __forceinline__ void unstage_r2c(const float2* s, float2* __restrict_
             const int p = 2 * q + h;
             const int f = p / ROWS, r = p - f * ROWS;
             const int row = row0 + r;
-            if (row < g.nrows) dst[f * g.nspec + (long)row * g.ldx + k] = h ? B : A;
+            if (row < g.nrows) dst[f * g.nspec + spec_idx(g, row, k)] = h ? B : A;
         }
     }
 }
@@ -128,14 +146,14 @@ __device__ __forceinline__ void unstage_r2c(const float2* s, float2* __restrict_
 template <int PS>
 __device__ __forceinline__ float pencil_val(const float2* s, int p, int x)
 {
-    const float2 v = s[(p >> 1) * PS + x];
+    const float2 v = s[(p >> 1) * PS + lidx<true>(x)];
     return (p & 1) ? v.y : v.x;
 }
 
 template <int PS>
 __device__ __forceinline__ void pencil_set(float2* s, int p, int x, float v)
 {
-    float* f = reinterpret_cast<float*>(s + (p >> 1) * PS + x);
+    float* f = reinterpret_cast<float*>(s + (p >> 1) * PS + lidx<true>(x));
     f[p & 1] = v;
 }
 
@@ -146,14 +164,21 @@ template <int NX, int NT>
 __global__ __launch_bounds__(NT) void k_vel(Geo g, Mat m, Pml pm, const float2* __restrict__ twx,
                                             float* __restrict__ fields, float2* __restrict__ spec,
                                             Rec rc, float* __restrict__ traces,
-                                            const int* __restrict__ stepp, int n0, int ldt)
+                                            const int* __restrict__ stepp, int* __restrict__ stepn, int n0,
+                                            int ldt)
 {
     constexpr int ROWS = rows_for(NX);
-    constexpr int PS = NX + 1;
+    constexpr int PS = padded_len(NX);
     constexpr int NPI = 9 * ROWS / 2;
     constexpr int NPO = 3 * ROWS / 2;
     constexpr int CPT = (ROWS * NX + NT - 1) / NT;
     __shared__ float2 s[NPI * PS];
+    __shared__ float2 tw[NX];
+    // step counters alternate between two words: this step reads one and
+    // publishes the next step's index in the other (read by no kernel of
+    // this step)
+    const int step = *stepp;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *stepn = step + 1;
 
     const int shot = blockIdx.y;
     const int row0 = blockIdx.x * ROWS;
@@ -161,41 +186,61 @@ __global__ __launch_bounds__(NT) void k_vel(Geo g, Mat m, Pml pm, const float2* 
     const float2* __restrict__ D9 = spec + (long)shot * g.sstride + 9 * g.nspec;
     float2* __restrict__ S3 = spec + (long)shot * g.sstride + 6 * g.nspec;
 
-    stage_c2r<NX, ROWS, NT, NPI, PS>(s, D9, g, row0);
-    __syncthreads();
-    lds_fft<NX, NPI, NT, +1, PS, 1, false>(s, twx);
+    for (int i = threadIdx.x; i < NX; i += NT) tw[i] = twx[i];
+    fft_ld<NX, NPI, NT, +1, PS, 1, false, false, HermLoader<NX, ROWS>, NoSt, true>(s, tw, HermLoader<NX, ROWS>{D9, g, row0}, NoSt{});
+
+    // all loads of the update before any store: the split parts share one
+    // base pointer, so interleaved stores would serialise later loads
+    float vp[CPT][9], dtr[CPT][3], a[CPT][3][3];
+    bool ok[CPT];
+    long cell[CPT];
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+        const int c = threadIdx.x + i * NT;
+        const int r = c / NX, x = c - r * NX;
+        const int row = row0 + r;
+        ok[i] = c < ROWS * NX && row < g.nrows;
+        const int rr = ok[i] ? row : row0;
+        const int y = rr % g.ny, z = rr / g.ny;
+        cell[i] = (long)rr * NX + x;
+        const float axi = pm.ai[0][x], axh = pm.ah[0][x];
+        const float ayi = pm.ai[1][y], ayh = pm.ah[1][y];
+        const float azi = pm.ai[2][z], azh = pm.ah[2][z];
+        const float bxi = pm.bi[0][x], bxh = pm.bh[0][x];
+        const float byi = pm.bi[1][y], byh = pm.bh[1][y];
+        const float bzi = pm.bi[2][z], bzh = pm.bh[2][z];
+        // component c sits half a cell up along axis c; split part d is damped
+        // by a_d and by b of the two other axes, all at the component's node
+        a[i][0][0] = axh * byi * bzi; a[i][0][1] = ayi * bxh * bzi; a[i][0][2] = azi * bxh * byi;
+        a[i][1][0] = axi * byh * bzi; a[i][1][1] = ayh * bxi * bzi; a[i][1][2] = azi * bxi * byh;
+        a[i][2][0] = axi * byi * bzh; a[i][2][1] = ayi * bxi * bzh; a[i][2][2] = azh * bxi * byi;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) vp[i][q] = ok[i] ? F[(long)q * g.n + cell[i]] : 0.f;
+#pragma unroll
+        for (int comp = 0; comp < 3; ++comp) dtr[i][comp] = ok[i] ? m.dtr[comp][cell[i]] : 0.f;
+    }
 
     float vsum[CPT][3];
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
         const int c = threadIdx.x + i * NT;
-        vsum[i][0] = vsum[i][1] = vsum[i][2] = 0.f;
-        if (c >= ROWS * NX) continue;
         const int r = c / NX, x = c - r * NX;
-        const int row = row0 + r;
-        if (row >= g.nrows) continue;
-        const int y = row % g.ny, z = row / g.ny;
-        const long cell = (long)row * NX + x;
-        const float axi = pm.ai[0][x], axh = pm.ah[0][x];
-        const float ayi = pm.ai[1][y], ayh = pm.ah[1][y];
-        const float azi = pm.ai[2][z], azh = pm.ah[2][z];
-        // a_d for component c along axis d: half node when c == d
-        const float a[3][3] = {{axh, ayi, azi}, {axi, ayh, azi}, {axi, ayi, azh}};
 #pragma unroll
         for (int comp = 0; comp < 3; ++comp) {
-            const float dtr = m.dtr[comp][cell];
             float acc = 0.f;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                const int p = (3 * comp + d) * ROWS + r;
-                const float dv = pencil_val<PS>(s, p, x);
-                float* f = F + (long)(3 * comp + d) * g.n + cell;
-                const float ad = a[comp][d];
-                const float v = ad * (ad * (*f) + dtr * dv);
-                *f = v;
-                acc += v;
+                const int q = 3 * comp + d;
+                const float dv = ok[i] ? pencil_val<PS>(s, q * ROWS + r, x) : 0.f;
+                const float ad = a[i][comp][d];
+                vp[i][q] = ad * (ad * vp[i][q] + dtr[i][comp] * dv);
+                acc += vp[i][q];
             }
             vsum[i][comp] = acc;
+        }
+        if (ok[i]) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) F[(long)q * g.n + cell[i]] = vp[i][q];
         }
     }
     __syncthreads();
@@ -205,14 +250,14 @@ __global__ __launch_bounds__(NT) void k_vel(Geo g, Mat m, Pml pm, const float2* 
         if (c >= ROWS * NX) continue;
         const int r = c / NX, x = c - r * NX;
 #pragma unroll
-        for (int comp = 0; comp < 3; ++comp) pencil_set<PS>(s, comp * ROWS + r, x, vsum[i][comp]);
+        for (int comp = 0; comp < 3; ++comp) pencil_set<PS>(s, comp * ROWS + r, x, ok[i] ? vsum[i][comp] : 0.f);
     }
     __syncthreads();
     // receivers (vx, vy, vz at their staggered nodes, time (n + 1/2) dt)
     {
         const int rend = min(row0 + ROWS, g.nrows);
         const int e0 = rc.ptr[row0], e1 = rc.ptr[rend];
-        const int tn = *stepp - n0;
+        const int tn = step - n0;
         for (int e = e0 + threadIdx.x; e < e1; e += NT) {
             const int4 q = rc.ent[e];
             const int r = q.y - row0;
@@ -222,7 +267,7 @@ __global__ __launch_bounds__(NT) void k_vel(Geo g, Mat m, Pml pm, const float2* 
                     pencil_val<PS>(s, comp * ROWS + r, q.x);
         }
     }
-    lds_fft<NX, NPO, NT, -1, PS, 1, false>(s, twx);
+    lds_fft<NX, NPO, NT, -1, PS, 1, false, true>(s, tw);
     unstage_r2c<NX, ROWS, NT, NPO, PS>(s, S3, g, row0);
 }
 
@@ -237,11 +282,12 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
                                             const int* __restrict__ stepp, int n0, int ldt)
 {
     constexpr int ROWS = rows_for(NX);
-    constexpr int PS = NX + 1;
+    constexpr int PS = padded_len(NX);
     constexpr int NPI = 9 * ROWS / 2;
     constexpr int NPO = 6 * ROWS / 2;
     constexpr int CPT = (ROWS * NX + NT - 1) / NT;
     __shared__ float2 s[NPI * PS];
+    __shared__ float2 tw[NX];
 
     const int shot = blockIdx.y;
     const int row0 = blockIdx.x * ROWS;
@@ -251,33 +297,42 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
     const int step = *stepp;
     const int* __restrict__ iptr = inj.ptr + (long)shot * (g.nrows + 1);
 
-    stage_c2r<NX, ROWS, NT, NPI, PS>(s, D9, g, row0);
-    __syncthreads();
-    lds_fft<NX, NPI, NT, +1, PS, 1, false>(s, twx);
+    for (int i = threadIdx.x; i < NX; i += NT) tw[i] = twx[i];
+    fft_ld<NX, NPI, NT, +1, PS, 1, false, false, HermLoader<NX, ROWS>, NoSt, true>(s, tw, HermLoader<NX, ROWS>{D9, g, row0}, NoSt{});
 
     float ssum[CPT][6];
+    bool ok[CPT];
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
         const int c = threadIdx.x + i * NT;
-#pragma unroll
-        for (int q = 0; q < 6; ++q) ssum[i][q] = 0.f;
-        if (c >= ROWS * NX) continue;
         const int r = c / NX, x = c - r * NX;
         const int row = row0 + r;
-        if (row >= g.nrows) continue;
+        ok[i] = c < ROWS * NX && row < g.nrows;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) ssum[i][q] = 0.f;
+        if (!ok[i]) continue;
         const int y = row % g.ny, z = row / g.ny;
         const long cell = (long)row * NX + x;
-        const float ai[3] = {pm.ai[0][x], pm.ai[1][y], pm.ai[2][z]};
-        const float ah[3] = {pm.ah[0][x], pm.ah[1][y], pm.ah[2][z]};
+        // this cell's loads first (the split parts share one base pointer)
+        float sp[15];
+#pragma unroll
+        for (int q = 0; q < 15; ++q) sp[q] = F[(long)q * g.n + cell];
+        const float dlam = m.dlam[cell], dmu2 = m.dmu2[cell];
+        const float mxy = m.dmus[0][cell], mxz = m.dmus[1][cell], myz = m.dmus[2][cell];
+        const float bxi = pm.bi[0][x], bxh = pm.bh[0][x];
+        const float byi = pm.bi[1][y], byh = pm.bh[1][y];
+        const float bzi = pm.bi[2][z], bzh = pm.bh[2][z];
+        // normal parts (centre nodes): a_d times b of the other two axes
+        const float ai[3] = {pm.ai[0][x] * byi * bzi, pm.ai[1][y] * bxi * bzi, pm.ai[2][z] * bxi * byi};
+        // shear parts at their nodes: xy (h,h,i), xz (h,i,h), yz (i,h,h)
+        const float axy_x = pm.ah[0][x] * byh * bzi, axy_y = pm.ah[1][y] * bxh * bzi;
+        const float axz_x = pm.ah[0][x] * byi * bzh, axz_z = pm.ah[2][z] * bxh * byi;
+        const float ayz_y = pm.ah[1][y] * bxi * bzh, ayz_z = pm.ah[2][z] * bxi * byh;
         // derivatives: e0..e2 = D_d^- v_d, e3 = Dy+ vx, e4 = Dx+ vy, e5 = Dz+ vx,
         //              e6 = Dx+ vz, e7 = Dz+ vy, e8 = Dy+ vz
         float e[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) e[q] = pencil_val<PS>(s, q * ROWS + r, x);
-        const float dlam = m.dlam[cell], dmu2 = m.dmu2[cell];
-        float sp[15];
-#pragma unroll
-        for (int q = 0; q < 15; ++q) sp[q] = F[(long)q * g.n + cell];
         // normal parts sp[3c + d] (component c, axis d)
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc)
@@ -288,13 +343,12 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
             }
         // shear parts: 9 sxy(x) <- Dx+ vy, 10 sxy(y) <- Dy+ vx, 11 sxz(x) <- Dx+ vz,
         //              12 sxz(z) <- Dz+ vx, 13 syz(y) <- Dy+ vz, 14 syz(z) <- Dz+ vy
-        const float mxy = m.dmus[0][cell], mxz = m.dmus[1][cell], myz = m.dmus[2][cell];
-        sp[9] = ah[0] * (ah[0] * sp[9] + mxy * e[4]);
-        sp[10] = ah[1] * (ah[1] * sp[10] + mxy * e[3]);
-        sp[11] = ah[0] * (ah[0] * sp[11] + mxz * e[6]);
-        sp[12] = ah[2] * (ah[2] * sp[12] + mxz * e[5]);
-        sp[13] = ah[1] * (ah[1] * sp[13] + myz * e[8]);
-        sp[14] = ah[2] * (ah[2] * sp[14] + myz * e[7]);
+        sp[9] = axy_x * (axy_x * sp[9] + mxy * e[4]);
+        sp[10] = axy_y * (axy_y * sp[10] + mxy * e[3]);
+        sp[11] = axz_x * (axz_x * sp[11] + mxz * e[6]);
+        sp[12] = axz_z * (axz_z * sp[12] + mxz * e[5]);
+        sp[13] = ayz_y * (ayz_y * sp[13] + myz * e[8]);
+        sp[14] = ayz_z * (ayz_z * sp[14] + myz * e[7]);
         // point sources of this shot in this row
         const int j0 = iptr[row], j1 = iptr[row + 1];
         if (j0 != j1 && step < inj.nt_w) {
@@ -323,7 +377,7 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
         if (c >= ROWS * NX) continue;
         const int r = c / NX, x = c - r * NX;
 #pragma unroll
-        for (int q = 0; q < 6; ++q) pencil_set<PS>(s, q * ROWS + r, x, ssum[i][q]);
+        for (int q = 0; q < 6; ++q) pencil_set<PS>(s, q * ROWS + r, x, ok[i] ? ssum[i][q] : 0.f);
     }
     __syncthreads();
     {
@@ -338,7 +392,7 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
             traces[((long)shot * 4 * rc.n_rec + q.z) * ldt + tn] = -tr * (1.0f / 3.0f);
         }
     }
-    lds_fft<NX, NPO, NT, -1, PS, 1, false>(s, twx);
+    lds_fft<NX, NPO, NT, -1, PS, 1, false, true>(s, tw);
     unstage_r2c<NX, ROWS, NT, NPO, PS>(s, S6, g, row0);
 }
 
@@ -358,7 +412,7 @@ __global__ __launch_bounds__(NT) void k_xfwd(Geo g, const float2* __restrict__ t
                                              long out_shot_stride, SumDesc sd)
 {
     constexpr int ROWS = rows_for(NX);
-    constexpr int PS = NX + 1;
+    constexpr int PS = padded_len(NX);
     constexpr int NPMAX = 9 * ROWS / 2;
     __shared__ float2 s[NPMAX * PS];
     const int shot = blockIdx.y;
@@ -380,10 +434,10 @@ __global__ __launch_bounds__(NT) void k_xfwd(Geo g, const float2* __restrict__ t
     __syncthreads();
     // np is a multiple of ROWS (even): np / 2 complex pencils
     if (sd.nf == 3) {
-        lds_fft<NX, 3 * ROWS / 2, NT, -1, PS, 1, false>(s, twx);
+        lds_fft<NX, 3 * ROWS / 2, NT, -1, PS, 1, false, true>(s, twx);
         unstage_r2c<NX, ROWS, NT, 3 * ROWS / 2, PS>(s, O, g, row0);
     } else {
-        lds_fft<NX, 6 * ROWS / 2, NT, -1, PS, 1, false>(s, twx);
+        lds_fft<NX, 6 * ROWS / 2, NT, -1, PS, 1, false, true>(s, twx);
         unstage_r2c<NX, ROWS, NT, 6 * ROWS / 2, PS>(s, O, g, row0);
     }
 }
@@ -394,13 +448,11 @@ __global__ __launch_bounds__(NT) void k_xinv(Geo g, const float2* __restrict__ t
                                              float* __restrict__ out)
 {
     constexpr int ROWS = rows_for(NX);
-    constexpr int PS = NX + 1;
+    constexpr int PS = padded_len(NX);
     constexpr int NPI = 9 * ROWS / 2;
     __shared__ float2 s[NPI * PS];
     const int row0 = blockIdx.x * ROWS;
-    stage_c2r<NX, ROWS, NT, NPI, PS>(s, in, g, row0);
-    __syncthreads();
-    lds_fft<NX, NPI, NT, +1, PS, 1, false>(s, twx);
+    fft_ld<NX, NPI, NT, +1, PS, 1, false, false, HermLoader<NX, ROWS>, NoSt, true>(s, twx, HermLoader<NX, ROWS>{in, g, row0}, NoSt{});
     for (int e = threadIdx.x; e < 9 * ROWS * NX; e += NT) {
         const int p = e / NX, x = e - p * NX;
         const int f = p / ROWS, r = p - f * ROWS;
@@ -410,8 +462,26 @@ __global__ __launch_bounds__(NT) void k_xinv(Geo g, const float2* __restrict__ t
 }
 
 // ---------------------------------------------------------------------------
+// Column tile of a y or z transform: element (column c, position i) is at
+// base[c * cs + i * is]; columns c >= ncol are outside the array.
+struct Tile {
+    float2* __restrict__ base;
+    long cs, is;
+    int ncol;
+    __device__ float2 operator()(int c, int i) const
+    {
+        return c < ncol ? base[c * cs + i * is] : make_float2(0.f, 0.f);
+    }
+    __device__ void operator()(int c, int i, float2 v) const
+    {
+        if (c < ncol) base[c * cs + i * is] = v;
+    }
+};
+
 // y FFT (forward or inverse) of `nf` spectra starting at field f0, in place.
-// grid: (kx tiles, nz, shots * nf)
+// grid: (main tiles + Nyquist tile, nz, shots * nf).  Main tile bx covers
+// columns [16 bx, 16 bx + 16) of plane z = by; the Nyquist tile covers the
+// Nyquist pencils of planes [16 by, 16 by + 16).
 template <int NY, int NT, int DIR>
 __global__ __launch_bounds__(NT) void k_y(Geo g, const float2* __restrict__ twy, float2* __restrict__ spec,
                                           int f0, int nf)
@@ -419,26 +489,30 @@ __global__ __launch_bounds__(NT) void k_y(Geo g, const float2* __restrict__ twy,
     constexpr int TX = tile_for(NY);
     constexpr int IS = TX + 1;
     __shared__ float2 s[NY * IS];
-    const int kx0 = blockIdx.x * TX;
-    const int z = blockIdx.y;
+    __shared__ float2 tw[NY];
+    const int tmain = (g.nxm + TX - 1) / TX;
     const int shot = blockIdx.z / nf, f = f0 + blockIdx.z % nf;
-    float2* __restrict__ base = spec + (long)shot * g.sstride + f * g.nspec + (long)z * NY * g.ldx + kx0;
-    const int ncol = min(TX, g.nxh - kx0);
-    for (int e = threadIdx.x; e < NY * TX; e += NT) {
-        const int y = e / TX, c = e - y * TX;
-        s[y * IS + c] = c < ncol ? base[(long)y * g.ldx + c] : make_float2(0.f, 0.f);
+    float2* __restrict__ fb = spec + (long)shot * g.sstride + (long)f * g.nspec;
+    Tile t;
+    if ((int)blockIdx.x < tmain) {
+        const int kx0 = blockIdx.x * TX;
+        t = Tile{fb + (long)blockIdx.y * NY * g.ldx + kx0, 1, g.ldx, min(TX, g.nxm - kx0)};
+    } else {
+        const int z0 = blockIdx.y * TX;
+        if (z0 >= g.nz) return;
+        t = Tile{fb + g.nqoff + (long)z0 * NY, NY, 1, min(TX, g.nz - z0)};
     }
-    __syncthreads();
-    lds_fft<NY, TX, NT, DIR, 1, IS, true>(s, twy);
-    for (int e = threadIdx.x; e < NY * TX; e += NT) {
-        const int y = e / TX, c = e - y * TX;
-        if (c < ncol) base[(long)y * g.ldx + c] = s[y * IS + c];
-    }
+    for (int i = threadIdx.x; i < NY; i += NT) tw[i] = twy[i];
+    fft_ld<NY, TX, NT, DIR, 1, IS, true, true>(s, tw, t, t);
 }
 
 // z FFT, multiply by the staggered derivative symbols and kappa, inverse z
-// FFT.  grid: (kx tiles, ny, shots * nin).  Reads spectra `in0 + input`,
-// writes the derivative spectra 9.. (deriv block) of the shot.
+// FFT.  grid: (main tiles + Nyquist tile, ny, shots * nin).  Main tile bx
+// covers columns [16 bx, +16) of row ky = by; the Nyquist tile covers the
+// Nyquist pencils of rows [16 by, +16).  Reads spectrum `in0 + input`, writes
+// the derivative spectra (9 + output index) of the shot.  The forward
+// spectrum stays in registers; each output is multiplied there and inverted
+// with the reversed radix plan.
 template <int NZ, int NT>
 __global__ __launch_bounds__(NT) void k_z(Geo g, const float2* __restrict__ twz, float2* __restrict__ spec,
                                           int in0, const ZDesc* __restrict__ zd, int phase)
@@ -447,48 +521,76 @@ __global__ __launch_bounds__(NT) void k_z(Geo g, const float2* __restrict__ twz,
     const Ops& ops = zd->ops;
     constexpr int TX = tile_for(NZ);
     constexpr int IS = TX + 1;
-    __shared__ float2 A[NZ * IS];
-    __shared__ float2 B[NZ * IS];
-    const int kx0 = blockIdx.x * TX;
-    const int ky = blockIdx.y;
+    using RS = RegShape<NZ, TX, NT>;
+    constexpr int RL = RS::RL, QL = RS::QL;
+    __shared__ float2 s[NZ * IS];
+    __shared__ float2 tw[NZ];
+    __shared__ float2 symz[2][NZ];
+    const int tmain = (g.nxm + TX - 1) / TX;
     const int shot = blockIdx.z / ph.nin, fi = blockIdx.z % ph.nin;
-    const long plane = (long)g.ny * g.ldx;
-    float2* __restrict__ sb = spec + (long)shot * g.sstride;
-    const float2* __restrict__ in = sb + (in0 + fi) * g.nspec + (long)ky * g.ldx + kx0;
-    const int ncol = min(TX, g.nxh - kx0);
-    for (int e = threadIdx.x; e < NZ * TX; e += NT) {
-        const int z = e / TX, c = e - z * TX;
-        A[z * IS + c] = c < ncol ? in[z * plane + c] : make_float2(0.f, 0.f);
+    long off, zs;
+    const float* kap;
+    int ncol, kx0, kxc, ky0, kyc;
+    if ((int)blockIdx.x < tmain) {
+        kx0 = blockIdx.x * TX;
+        kxc = 1;
+        ky0 = blockIdx.y;
+        kyc = 0;
+        off = (long)ky0 * g.ldx + kx0;
+        zs = (long)g.ny * g.ldx;
+        ncol = min(TX, g.nxm - kx0);
+        kap = ops.kap + off;
+    } else {
+        ky0 = blockIdx.y * TX;
+        if (ky0 >= g.ny) return;
+        kyc = 1;
+        kx0 = g.nx / 2;
+        kxc = 0;
+        off = g.nqoff + ky0;
+        zs = g.ny;
+        ncol = min(TX, g.ny - ky0);
+        kap = ops.kapn + ky0;
+    }
+    for (int i = threadIdx.x; i < NZ; i += NT) {
+        tw[i] = twz[i];
+        symz[0][i] = ops.sym[2][0][i];
+        symz[1][i] = ops.sym[2][1][i];
     }
     __syncthreads();
-    lds_fft<NZ, TX, NT, -1, 1, IS, true>(A, twz);
-    const float* __restrict__ kap = ops.kap + (long)ky * g.ldx + kx0;
+    // kappa of the elements this thread multiplies (issued before the forward FFT)
+    float kr[QL][RL];
+#pragma unroll
+    for (int q = 0; q < QL; ++q)
+#pragma unroll
+        for (int r = 0; r < RL; ++r) {
+            int c, z;
+            const bool ok = reg_coords<NZ, RL, TX, NT, true>(q, r, c, z);
+            kr[q][r] = (ok && c < ncol) ? kap[z * zs + c] : 0.f;
+        }
+    float2* __restrict__ sb = spec + (long)shot * g.sstride;
+    const Tile in{sb + (long)(in0 + fi) * g.nspec + off, 1, zs, ncol};
+    float2 X[QL][RL];
+    fft_g2r<NZ, TX, NT, -1, 1, IS, true>(s, tw, in, X);
     for (int o = 0; o < ph.nout[fi]; ++o) {
         const int axis = ph.axis[fi][o], plus = ph.plus[fi][o];
         const float2* __restrict__ sym = ops.sym[axis][plus];
-        for (int e = threadIdx.x; e < NZ * TX; e += NT) {
-            const int z = e / TX, c = e - z * TX;
-            float2 v = make_float2(0.f, 0.f);
-            if (c < ncol) {
-                const float2 sd = sym[axis == 0 ? kx0 + c : (axis == 1 ? ky : z)];
-                v = c_scale(c_mul(sd, A[z * IS + c]), kap[z * plane + c]);
+        float2 Y[QL][RL];
+#pragma unroll
+        for (int q = 0; q < QL; ++q)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                int c, z;
+                reg_coords<NZ, RL, TX, NT, true>(q, r, c, z);
+                float2 sv;
+                if (axis == 2) sv = symz[plus][z];
+                else if (axis == 0) sv = sym[kx0 + kxc * min(c, ncol - 1)];
+                else sv = sym[ky0 + kyc * min(c, ncol - 1)];
+                Y[q][r] = c_scale(c_mul(sv, X[q][r]), kr[q][r]);
             }
-            B[z * IS + c] = v;
-        }
-        __syncthreads();
-        lds_fft<NZ, TX, NT, +1, 1, IS, true>(B, twz);
-        float2* __restrict__ out = sb + (9 + ph.oidx[fi][o]) * g.nspec + (long)ky * g.ldx + kx0;
-        for (int e = threadIdx.x; e < NZ * TX; e += NT) {
-            const int z = e / TX, c = e - z * TX;
-            if (c < ncol) out[z * plane + c] = B[z * IS + c];
-        }
-        __syncthreads();
+        __syncthreads();   // s was read by the previous pass
+        const Tile out{sb + (long)(9 + ph.oidx[fi][o]) * g.nspec + off, 1, zs, ncol};
+        fft_r2g<NZ, TX, NT, +1, 1, IS, true>(s, tw, Y, out);
     }
-}
-
-__global__ void k_step_inc(int* stepp)
-{
-    if (threadIdx.x == 0 && blockIdx.x == 0) *stepp += 1;
 }
 
 // non-finite check on sampled trace values: flag = 1 if any is not finite

@@ -152,7 +152,7 @@ def correlated_field(shape, corr_cells: float, seed: int) -> np.ndarray:
     k2 = sum(k * k for k in kk) * (2 * math.pi) ** 2
     # Fourier transform of exp(-2 r^2/L^2) is proportional to exp(-k^2 L^2 / 8)
     spec *= np.exp(-k2 * corr_cells ** 2 / 8.0)
-    f = np.fft.irfftn(spec, s=shape)
+    f = np.fft.irfftn(spec, s=shape, axes=tuple(range(len(shape))))
     f -= f.mean()
     return f / np.abs(f).max()
 
@@ -167,7 +167,7 @@ def layered(nx, ny, nz, water_cells, n_layers=6, vp_top=2000.0, vp_bot=4000.0,
     Water: vp 1500, vs 0, rho 1000.
     """
     shp = (nz, ny, nx)
-    vp = np.empty(shp)
+    vp = np.full(shp, 1500.0)
     thick = (nz - water_cells) // n_layers
     for l in range(n_layers):
         z0 = water_cells + l * thick
@@ -248,6 +248,7 @@ class Workload:
     shot_ofs: np.ndarray         # int32 [n_shots + 1]
     wavelet: np.ndarray          # float64 [n_src_total][nt_w]
     meta: dict = field(default_factory=dict)
+    pml_p: float = 0.1           # multi-axial PML ratio
 
     @property
     def n_shots(self):

@@ -1,0 +1,132 @@
+"""GPU checks at the full workload sizes, in the launch configuration the bench
+times (one context, graph replay of step pairs).
+
+ * 128^3 layered model, 2000 steps, one DC source: traces at a fixed sample
+   of 32 receivers against the stored FP64 oracle run (rel-L2 <= 1e-4 per
+   component).
+ * 384 x 384 x 256 model: the oracle cannot run it in a test, so the test uses
+   properties that hold at any size: doubling the moment tensor doubles every
+   trace exactly (scaling by 2 is exact in binary floating point), delaying
+   the wavelet by m samples delays every trace by m samples exactly (the
+   state stays exactly zero until the source starts), and the derivative
+   operators at lengths 384 and 256 match the oracle on a thin grid.
+ * 64 shots batched on the 128^3 model: selected shots equal the same shots
+   run alone, bit for bit.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1705_04874_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLD = os.path.join(ROOT, "tests", "golden", "c1_oracle_traces.npz")
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def B(gpu):
+    from paper_1705_04874_amd import binding
+    return binding
+
+
+def test_c1_full_against_oracle_golden(B):
+    if not os.path.exists(GOLD):
+        pytest.fail("tests/golden/c1_oracle_traces.npz missing (tests/golden/make_c1_golden.py writes it)")
+    g = np.load(GOLD, allow_pickle=False)
+    nt = int(g["nt"])
+    w = inputs.c1_workload(nt=nt)
+    from tests.golden.make_c1_golden import model_digest
+    assert str(g["digest"]) == model_digest(w), "workload generator changed since the golden was written"
+    say("c1 full", w.model.shape, nt)
+    s = B.Solver.from_workload(w)
+    s.set_workload_sources(w)
+    tr = s.run(nt).cpu().numpy()[0][:, g["receivers"]].astype(np.float64)
+    ref = g["traces"]
+    for c, name in enumerate(["p", "vx", "vy", "vz"]):
+        e = np.linalg.norm(tr[c] - ref[c]) / np.linalg.norm(ref[c])
+        say(f"  {name}: rel-L2 {e:.3e}")
+        assert e <= 1e-4
+
+
+@pytest.mark.parametrize("shape", [(256, 16, 384), (16, 384, 40)])
+def test_derivatives_at_large_lengths(B, shape):
+    import torch
+    say("derivs", shape)
+    h = (10.0, 10.0, 10.0)
+    rng = np.random.default_rng(7)
+    vp = 2500 + 500 * rng.random(shape)
+    vs = vp / 1.8
+    rho = 310 * vp ** 0.25
+    dt = 0.8e-3
+    s = B.Solver(vp, vs, rho, h, dt, pml=4, kspace=1)
+    s.set_sources([0, 0], np.zeros((0, 3)), np.zeros((0, 6)), np.zeros((0, 1)))
+    f = rng.standard_normal((3,) + shape)
+    got = s.derivs(1, torch.from_numpy(f.astype(np.float32)).cuda()).cpu().numpy()
+    table = [(0, -1, 0), (1, -1, 1), (2, -1, 2), (1, +1, 0), (0, +1, 1), (2, +1, 0), (0, +1, 2), (2, +1, 1),
+             (1, +1, 2)]
+    for o, (axis, sign, src) in enumerate(table):
+        ref = oracle.deriv(f[src], axis, sign, h=h, kspace=1, c_ref=vp.max(), dt=dt)
+        e = np.linalg.norm(got[o] - ref) / np.linalg.norm(ref)
+        assert e < 2e-5, (o, e)
+
+
+@pytest.fixture(scope="module")
+def c2_runs(B):
+    nt = 1000
+    w = inputs.c2_workload(nt=nt)
+    say("c2", w.model.shape, nt)
+    s = B.Solver.from_workload(w)
+    out = {}
+    s.set_workload_sources(w)
+    out["base"] = s.run(nt).cpu().numpy()[0]
+    s.set_sources(w.shot_ofs, w.src_ijk, 2.0 * w.src_m, w.wavelet)
+    out["double"] = s.run(nt).cpu().numpy()[0]
+    lag = 37
+    wl = np.concatenate([np.zeros((1, lag)), w.wavelet[:, :nt - lag]], axis=1)
+    s.set_sources(w.shot_ofs, w.src_ijk, w.src_m, wl)
+    out["lag"] = s.run(nt).cpu().numpy()[0]
+    out["lag_n"] = lag
+    s.close()
+    return out
+
+
+def test_c2_traces_are_finite_and_nonzero(c2_runs):
+    b = c2_runs["base"]
+    assert np.isfinite(b).all()
+    for c in range(4):
+        assert np.abs(b[c]).max() > 0
+
+
+def test_c2_amplitude_scaling_is_exact(c2_runs):
+    np.testing.assert_array_equal(c2_runs["double"], 2.0 * c2_runs["base"])
+
+
+def test_c2_time_shift_is_exact(c2_runs):
+    lag = c2_runs["lag_n"]
+    a, b = c2_runs["base"], c2_runs["lag"]
+    assert np.abs(b[..., :lag]).max() == 0.0
+    np.testing.assert_array_equal(b[..., lag:], a[..., :-lag])
+
+
+def test_c3_batch_of_64_shots_matches_single_shots(B):
+    nt = 400
+    w = inputs.c3_shots(64, nt=nt)
+    say("c3 batch", w.n_shots, nt)
+    s = B.Solver.from_workload(w)
+    s.set_workload_sources(w)
+    batch = s.run(nt).cpu().numpy()
+    s.close()
+    for k in [0, 31, 63]:
+        s1 = B.Solver.from_workload(w)
+        s1.set_sources([0, 1], w.src_ijk[k:k + 1], w.src_m[k:k + 1], w.wavelet[k:k + 1])
+        one = s1.run(nt).cpu().numpy()[0]
+        s1.close()
+        np.testing.assert_array_equal(batch[k], one)

@@ -184,3 +184,43 @@ def test_error_codes(B):
     with pytest.raises(B.PstdError) as e:
         s.set_sources([0, 1], np.array([[0, 0, 16]]), np.zeros((1, 6)), np.zeros((1, 4)))
     assert e.value.code == B.PSTD_EINVAL
+
+
+def test_graph_replay_equals_eager(B, monkeypatch):
+    w = small_workload(nt=41, shots=2)
+    s = B.Solver.from_workload(w)
+    s.set_workload_sources(w)
+    monkeypatch.setenv("PSTD_GRAPH", "1")
+    g = s.run(41).cpu().numpy()
+    s.reset()
+    monkeypatch.setenv("PSTD_GRAPH", "0")
+    e = s.run(41).cpu().numpy()
+    np.testing.assert_array_equal(g, e)
+    # a second call continues from step 41 in both modes
+    monkeypatch.setenv("PSTD_GRAPH", "1")
+    g2 = s.run(10).cpu().numpy()
+    s.reset()
+    monkeypatch.setenv("PSTD_GRAPH", "0")
+    s.run(41)
+    e2 = s.run(10).cpu().numpy()
+    np.testing.assert_array_equal(g2, e2)
+
+
+def test_run_many_uneven_grids(B):
+    """Several models of different sizes advanced together equal separate runs."""
+    ws = [small_workload(shape=(30, 24, 40), nt=50, shots=1, seed=4),
+          small_workload(shape=(24, 32, 48), nt=50, shots=2, seed=5),
+          small_workload(shape=(40, 30, 32), nt=50, shots=1, seed=6)]
+    solos = []
+    for w in ws:
+        s = B.Solver.from_workload(w)
+        s.set_workload_sources(w)
+        solos.append(s.run(50).cpu().numpy())
+    ss = []
+    for w in ws:
+        s = B.Solver.from_workload(w)
+        s.set_workload_sources(w)
+        ss.append(s)
+    outs = B.run_many(ss, 50)
+    for a, b in zip(outs, solos):
+        np.testing.assert_array_equal(a.cpu().numpy(), b)
