@@ -1,0 +1,104 @@
+/*
+ * sno — spectral neural operator surrogate of the seismogram simulation, on
+ * MI355X (gfx950).  Plain C ABI: host or device pointers and sizes only.
+ *
+ * The paper names a learned proxy of the forward simulation as future work
+ * (Sec. VII).  The surrogate maps a point source (position and moment tensor,
+ * 9 numbers) to four-component receiver traces on a line of receivers, with a
+ * Fourier neural operator along time:
+ *   lift      V0 = P [f; t] + pb                       (f: 9 normalised features)
+ *   layer l   Z = W_l V + b_l + IDFT_K( R_l[k] DFT_K(V)[k] ),  V = gelu(Z)
+ *             (no activation after the last layer; K retained modes; complex
+ *              C x C weights per mode)
+ *   project   Y = Q2 gelu(Q1 V + q1b) + q2b            (O = 4 n_rec outputs)
+ * Every contraction runs on BF16 MFMA with FP32 accumulation; master weights,
+ * gradients and Adam moments are FP32.  Training minimises the mean squared
+ * error of traces normalised per component by their training-set RMS.  An
+ * error head predicts each sample's relative L2 error from the pooled last
+ * hidden layer; predictions whose estimate exceeds a tolerance are recomputed
+ * by the pseudo-spectral solver (pstd3d), which stays the judge of accuracy.
+ *
+ * Layout: features X [n][9] (x, y, z cell indices, moment tensor xx yy zz xy xz
+ * yz in N*m), traces Y [n][4][n_rec][T] (components p, vx, vy, vz).  Errors:
+ * the PSTD_* codes of pstd3d.h.
+ */
+#ifndef SNO_H
+#define SNO_H
+
+#include <stdint.h>
+
+#include "pstd3d.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sno sno;
+
+typedef struct {
+    int n_rec;          /* receivers on the line (O = 4 n_rec outputs) */
+    int T;              /* time samples (power of two up to 4096) */
+    int C;              /* width (multiple of 16) */
+    int K;              /* retained Fourier modes (<= T/2) */
+    int L;              /* Fourier layers */
+    int H;              /* projection hidden width (multiple of 16) */
+    double feat_off[9]; /* feature f = (x - off) / scale */
+    double feat_scale[9];
+} sno_cfg;
+
+typedef struct {
+    int epochs;
+    int batch;
+    double lr;          /* peak learning rate, cosine decay to 0 */
+    uint64_t seed;      /* shuffling (std::mt19937_64) */
+    int n_calib;        /* last n_calib samples fit the error head, not the weights */
+} sno_train_cfg;
+
+/* Create a model; params (host float, sno_n_params values, order P, pb,
+ * {W_l, b_l, Rr_l, Ri_l}_l, Q1, q1b, Q2, q2b) are the initial weights. */
+int sno_create(const sno_cfg *cfg, const float *params, sno **out);
+long sno_n_params(const sno_cfg *cfg);
+void sno_destroy(sno *s);
+
+/* Train on n device samples (X [n][9] float, Y [n][4][n_rec][T] float), then
+ * fit the error head on the last n_calib samples.  loss_curve (host, may be
+ * NULL) receives the mean training loss of each epoch. */
+int sno_train(sno *s, const float *X, const float *Y, int n, const sno_train_cfg *cfg, float *loss_curve,
+              void *hip_stream);
+
+/* Predict n samples: Y [n][4][n_rec][T] device, est_err [n] device (the error
+ * head's estimate of the relative L2 error; NaN-free). */
+int sno_predict(sno *s, const float *X, int n, float *Y, float *est_err, void *hip_stream);
+
+/* Predict, then recompute with the solver every sample whose estimated error
+ * exceeds tol.  The solver context must have the surrogate's receivers, in
+ * the same order; sample i is a single point source at src_ijk[3i..] with
+ * moment tensor m6[6i..] (host) and wavelet (host, nt_w samples, shared);
+ * the solver runs decim * T steps and every decim-th sample is kept.  used
+ * (host, n, may be NULL) returns 1 where the solver answered.  Solver calls go
+ * in batches of at most max_batch shots. */
+int sno_predict_or_solve(sno *s, pstd3d_ctx *solver, const float *X, const int32_t *src_ijk, const double *m6,
+                         const double *wavelet, int nt_w, int decim, int n, double tol, int max_batch, float *Y,
+                         float *est_err, int *used, void *hip_stream);
+
+/* Test entries: forward of n samples with the current weights (Y device), and
+ * the gradient of the mean squared error against targets Yt (device, already
+ * normalised) into grad (device, sno_n_params floats). */
+int sno_forward(sno *s, const float *X, int n, float *Y, void *hip_stream);
+int sno_gradient(sno *s, const float *X, const float *Yt, int n, float *grad, float *loss, void *hip_stream);
+/* Copy the current FP32 weights to host memory. */
+int sno_get_params(const sno *s, float *params);
+/* Output normalisation: per-component scale (4 floats, host). */
+int sno_get_scale(const sno *s, float *scale4);
+
+/* Message of the last surrogate error on the calling thread. */
+const char *sno_last_error(void);
+
+/* Keep every decim-th sample: in [n][4][n_rec][nt] -> out [n][4][n_rec][nt/decim]
+ * (device). */
+int sno_decimate(const float *in, int n, int n_rec, int nt, int decim, float *out, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

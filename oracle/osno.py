@@ -1,0 +1,185 @@
+"""FP64 oracle of the spectral neural operator surrogate (test infrastructure only).
+
+The paper names a learned proxy of the forward simulation as future work
+(Sec. VII); the surrogate here maps a point source (position and moment tensor)
+to four-component receiver traces with a Fourier neural operator along time:
+
+  lift:     V0 = P A + pb,            A = [source features broadcast; t_j]   (C x T)
+  layer l:  Vh = V F                  truncated DFT, F = [cos | -sin](2 pi j k / T), k < K
+            U_k = R_l[k] Vh_k         complex C x C mixing per retained mode k
+            U  = Uh G                 inverse DFT of the K modes of a real signal
+            Z  = W_l V + b_l + U
+            V  = gelu(Z)  (no activation after the last layer)
+  project:  Y = Q2 gelu(Q1 V + q1b) + q2b                                      (O x T)
+
+gelu(x) = x/2 (1 + tanh(sqrt(2/pi) (x + 0.044715 x^3))).  Loss: mean squared
+error over the batch and all outputs.  Gradients are written out by hand
+(reverse mode), each step the transpose of its forward step.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Dims:
+    n_in: int = 9          # source features
+    C: int = 64            # width
+    T: int = 1024          # time samples
+    K: int = 16            # retained modes
+    L: int = 4             # Fourier layers
+    H: int = 128           # projection hidden width
+    O: int = 256           # outputs per time sample (4 components x 64 receivers)
+
+
+def param_shapes(d: Dims):
+    """Ordered (name, shape) list; the flat parameter vector follows this order."""
+    s = [("P", (d.C, d.n_in + 1)), ("pb", (d.C,))]
+    for l in range(d.L):
+        s += [(f"W{l}", (d.C, d.C)), (f"b{l}", (d.C,)), (f"Rr{l}", (d.K, d.C, d.C)), (f"Ri{l}", (d.K, d.C, d.C))]
+    s += [("Q1", (d.H, d.C)), ("q1b", (d.H,)), ("Q2", (d.O, d.H)), ("q2b", (d.O,))]
+    return s
+
+
+def n_params(d: Dims):
+    return sum(int(np.prod(sh)) for _, sh in param_shapes(d))
+
+
+def unflatten(theta, d: Dims):
+    out, o = {}, 0
+    for name, sh in param_shapes(d):
+        n = int(np.prod(sh))
+        out[name] = np.asarray(theta[o:o + n], dtype=np.float64).reshape(sh)
+        o += n
+    return out
+
+
+def flatten(p, d: Dims):
+    return np.concatenate([np.asarray(p[name], np.float64).ravel() for name, _ in param_shapes(d)])
+
+
+def dft_bases(d: Dims):
+    """F (T x 2K): [cos | -sin](2 pi j k / T); G (2K x T): inverse of the K modes
+    of a real signal, [w_k cos / T ; -w_k sin / T], w_0 = 1, w_k = 2."""
+    j = np.arange(d.T)[:, None]
+    k = np.arange(d.K)[None, :]
+    ang = 2 * math.pi * j * k / d.T
+    F = np.concatenate([np.cos(ang), -np.sin(ang)], axis=1)
+    w = np.where(np.arange(d.K) == 0, 1.0, 2.0)[None, :]
+    G = np.concatenate([(w * np.cos(ang)).T, (-w * np.sin(ang)).T], axis=0) / d.T
+    return F, G
+
+
+def gelu(x):
+    c = math.sqrt(2 / math.pi)
+    return 0.5 * x * (1 + np.tanh(c * (x + 0.044715 * x ** 3)))
+
+
+def gelu_grad(x):
+    c = math.sqrt(2 / math.pi)
+    u = c * (x + 0.044715 * x ** 3)
+    th = np.tanh(u)
+    return 0.5 * (1 + th) + 0.5 * x * (1 - th * th) * c * (1 + 3 * 0.044715 * x * x)
+
+
+def features(src, d: Dims):
+    """A (B x (n_in+1) x T): source features broadcast along time plus t_j = j / T."""
+    src = np.asarray(src, np.float64)
+    B = src.shape[0]
+    A = np.empty((B, d.n_in + 1, d.T))
+    A[:, :d.n_in, :] = src[:, :, None]
+    A[:, d.n_in, :] = np.arange(d.T) / d.T
+    return A
+
+
+def forward(theta, src, d: Dims, keep=False):
+    p = unflatten(theta, d)
+    F, G = dft_bases(d)
+    A = features(src, d)
+    V = np.einsum("ci,bit->bct", p["P"], A) + p["pb"][None, :, None]
+    cache = {"A": A, "V": [V], "Vh": [], "Z": []}
+    for l in range(d.L):
+        Vh = V @ F                                              # B x C x 2K
+        Vr, Vi = Vh[..., :d.K], Vh[..., d.K:]
+        Rr, Ri = p[f"Rr{l}"], p[f"Ri{l}"]                       # K x C x C
+        Ur = np.einsum("koc,bck->bok", Rr, Vr) - np.einsum("koc,bck->bok", Ri, Vi)
+        Ui = np.einsum("koc,bck->bok", Ri, Vr) + np.einsum("koc,bck->bok", Rr, Vi)
+        U = np.concatenate([Ur, Ui], axis=2) @ G                # B x C x T
+        Z = np.einsum("oc,bct->bot", p[f"W{l}"], V) + p[f"b{l}"][None, :, None] + U
+        V = gelu(Z) if l < d.L - 1 else Z
+        cache["Vh"].append(Vh)
+        cache["Z"].append(Z)
+        cache["V"].append(V)
+    Hp = np.einsum("hc,bct->bht", p["Q1"], V) + p["q1b"][None, :, None]
+    Hq = gelu(Hp)
+    Y = np.einsum("oh,bht->bot", p["Q2"], Hq) + p["q2b"][None, :, None]
+    cache.update(Hp=Hp, Hq=Hq)
+    return (Y, cache) if keep else Y
+
+
+def loss(theta, src, y, d: Dims):
+    Y = forward(theta, src, d)
+    return float(np.mean((Y - y) ** 2))
+
+
+def grad(theta, src, y, d: Dims):
+    """Gradient of the mean squared error with respect to the flat parameters."""
+    p = unflatten(theta, d)
+    F, G = dft_bases(d)
+    Y, c = forward(theta, src, d, keep=True)
+    g = {}
+    dY = 2.0 * (Y - y) / Y.size
+    g["Q2"] = np.einsum("bot,bht->oh", dY, c["Hq"])
+    g["q2b"] = dY.sum(axis=(0, 2))
+    dHq = np.einsum("oh,bot->bht", p["Q2"], dY)
+    dHp = dHq * gelu_grad(c["Hp"])
+    g["Q1"] = np.einsum("bht,bct->hc", dHp, c["V"][-1])
+    g["q1b"] = dHp.sum(axis=(0, 2))
+    dV = np.einsum("hc,bht->bct", p["Q1"], dHp)
+    for l in reversed(range(d.L)):
+        Z = c["Z"][l]
+        dZ = dV * gelu_grad(Z) if l < d.L - 1 else dV
+        Vin = c["V"][l]
+        g[f"W{l}"] = np.einsum("bot,bct->oc", dZ, Vin)
+        g[f"b{l}"] = dZ.sum(axis=(0, 2))
+        dUh = dZ @ G.T                                          # B x C x 2K
+        dUr, dUi = dUh[..., :d.K], dUh[..., d.K:]
+        Vh = c["Vh"][l]
+        Vr, Vi = Vh[..., :d.K], Vh[..., d.K:]
+        g[f"Rr{l}"] = np.einsum("bok,bck->koc", dUr, Vr) + np.einsum("bok,bck->koc", dUi, Vi)
+        g[f"Ri{l}"] = np.einsum("bok,bck->koc", dUi, Vr) - np.einsum("bok,bck->koc", dUr, Vi)
+        Rr, Ri = p[f"Rr{l}"], p[f"Ri{l}"]
+        dVr = np.einsum("koc,bok->bck", Rr, dUr) + np.einsum("koc,bok->bck", Ri, dUi)
+        dVi = -np.einsum("koc,bok->bck", Ri, dUr) + np.einsum("koc,bok->bck", Rr, dUi)
+        dV = np.einsum("oc,bot->bct", p[f"W{l}"], dZ) + np.concatenate([dVr, dVi], axis=2) @ F.T
+    g["P"] = np.einsum("bct,bit->ci", dV, c["A"])
+    g["pb"] = dV.sum(axis=(0, 2))
+    return flatten(g, d)
+
+
+def init_params(d: Dims, seed: int):
+    """Seeded initial weights: uniform(+-1/sqrt(fan_in)) for the pointwise maps,
+    uniform(0, 1) / (C C) for the spectral weights."""
+    rng = np.random.default_rng(seed)
+    p = {}
+    for name, sh in param_shapes(d):
+        if name.startswith(("Rr", "Ri")):
+            p[name] = rng.uniform(0.0, 1.0, sh) / (d.C * d.C)
+        elif len(sh) == 2:
+            lim = 1.0 / math.sqrt(sh[1])
+            p[name] = rng.uniform(-lim, lim, sh)
+        else:
+            p[name] = np.zeros(sh)
+    return flatten(p, d)
+
+
+def adam(theta, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step (step counts from 1); returns the new (theta, m, v)."""
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    mh = m / (1 - b1 ** step)
+    vh = v / (1 - b2 ** step)
+    return theta - lr * mh / (np.sqrt(vh) + eps), m, v

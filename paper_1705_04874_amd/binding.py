@@ -222,3 +222,140 @@ def seis_combine(traces, t0, src_idx, amp, t_origin, nt_out, dt_in, dt_out, out=
                            si.ctypes.data_as(_ip), am.ctypes.data_as(_dp), to.ctypes.data_as(_dp), int(nt_out),
                            float(dt_out), C.c_void_p(out.data_ptr()), _stream_handle(stream)), "seis_combine")
     return out
+
+
+# ---------------------------------------------------------------------------
+# spectral neural operator surrogate (include/sno.h)
+class SnoCfg(C.Structure):
+    _fields_ = [("n_rec", C.c_int), ("T", C.c_int), ("C", C.c_int), ("K", C.c_int), ("L", C.c_int), ("H", C.c_int),
+                ("feat_off", C.c_double * 9), ("feat_scale", C.c_double * 9)]
+
+
+class SnoTrainCfg(C.Structure):
+    _fields_ = [("epochs", C.c_int), ("batch", C.c_int), ("lr", C.c_double), ("seed", C.c_uint64),
+                ("n_calib", C.c_int)]
+
+
+_L.sno_n_params.argtypes = [C.POINTER(SnoCfg)]
+_L.sno_n_params.restype = C.c_long
+_L.sno_create.argtypes = [C.POINTER(SnoCfg), _fp, C.POINTER(C.c_void_p)]
+_L.sno_destroy.argtypes = [C.c_void_p]
+_L.sno_train.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(SnoTrainCfg), _fp, C.c_void_p]
+_L.sno_predict.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
+_L.sno_predict_or_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, _ip, _dp, _dp, C.c_int, C.c_int, C.c_int,
+                                    C.c_double, C.c_int, C.c_void_p, C.c_void_p, C.POINTER(C.c_int), C.c_void_p]
+_L.sno_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+_L.sno_gradient.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, _fp, C.c_void_p]
+_L.sno_get_params.argtypes = [C.c_void_p, _fp]
+_L.sno_get_scale.argtypes = [C.c_void_p, _fp]
+_L.sno_decimate.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+_L.sno_last_error.restype = C.c_char_p
+
+
+def _scheck(rc, what):
+    if rc != PSTD_OK:
+        msg = _L.sno_last_error().decode(errors="replace")
+        err = PstdError.__new__(PstdError)
+        RuntimeError.__init__(err, f"{what} failed with code {rc}: {msg}")
+        err.code = rc
+        raise err
+
+
+def _dev(t):
+    import torch
+    assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+    return C.c_void_p(t.data_ptr())
+
+
+class Surrogate:
+    """Spectral neural operator surrogate on the current GPU (see include/sno.h)."""
+
+    def __init__(self, n_rec, T, C_, K, L, H, feat_off, feat_scale, params):
+        self.cfg = SnoCfg(int(n_rec), int(T), int(C_), int(K), int(L), int(H),
+                          (C.c_double * 9)(*[float(v) for v in feat_off]),
+                          (C.c_double * 9)(*[float(v) for v in feat_scale]))
+        self.n_params = _L.sno_n_params(C.byref(self.cfg))
+        if self.n_params < 0:
+            raise ValueError("bad surrogate configuration")
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == self.n_params
+        h = C.c_void_p()
+        _scheck(_L.sno_create(C.byref(self.cfg), p.ctypes.data_as(_fp), C.byref(h)), "sno_create")
+        self._h = h
+        self.O = 4 * int(n_rec)
+
+    def _out(self, n):
+        import torch
+        return torch.empty((n, 4, self.cfg.n_rec, self.cfg.T), dtype=torch.float32, device="cuda")
+
+    def train(self, X, Y, epochs, batch, lr, seed=0, n_calib=0, stream=None):
+        tc = SnoTrainCfg(int(epochs), int(batch), float(lr), int(seed), int(n_calib))
+        curve = np.zeros(max(1, int(epochs)), np.float32)
+        _scheck(_L.sno_train(self._h, _dev(X), _dev(Y), X.shape[0], C.byref(tc), curve.ctypes.data_as(_fp),
+                             _stream_handle(stream)), "sno_train")
+        return curve[:epochs]
+
+    def predict(self, X, stream=None):
+        import torch
+        n = X.shape[0]
+        Y = self._out(n)
+        est = torch.empty(n, dtype=torch.float32, device="cuda")
+        _scheck(_L.sno_predict(self._h, _dev(X), n, _dev(Y), _dev(est), _stream_handle(stream)), "sno_predict")
+        return Y, est
+
+    def predict_or_solve(self, solver, X, src_ijk, m6, wavelet, decim, tol, max_batch=64, stream=None):
+        import torch
+        n = X.shape[0]
+        Y = self._out(n)
+        est = torch.empty(n, dtype=torch.float32, device="cuda")
+        ijk = _i32(src_ijk).reshape(-1, 3)
+        mm = _f64(m6).reshape(-1, 6)
+        wv = _f64(wavelet).reshape(-1)
+        used = (C.c_int * max(1, n))()
+        _scheck(_L.sno_predict_or_solve(self._h, solver._h, _dev(X), ijk.ctypes.data_as(_ip), mm.ctypes.data_as(_dp),
+                                        wv.ctypes.data_as(_dp), wv.size, int(decim), n, float(tol), int(max_batch),
+                                        _dev(Y), _dev(est), used, _stream_handle(stream)), "sno_predict_or_solve")
+        return Y, est, np.array(used[:n], dtype=bool)
+
+    def forward(self, X, stream=None):
+        Y = self._out(X.shape[0])
+        _scheck(_L.sno_forward(self._h, _dev(X), X.shape[0], _dev(Y), _stream_handle(stream)), "sno_forward")
+        return Y
+
+    def gradient(self, X, Yt, stream=None):
+        import torch
+        g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
+        loss = C.c_float()
+        _scheck(_L.sno_gradient(self._h, _dev(X), _dev(Yt), X.shape[0], _dev(g), C.byref(loss),
+                                _stream_handle(stream)), "sno_gradient")
+        return g, loss.value
+
+    def params(self):
+        out = np.empty(self.n_params, np.float32)
+        _scheck(_L.sno_get_params(self._h, out.ctypes.data_as(_fp)), "sno_get_params")
+        return out
+
+    def scale(self):
+        out = np.empty(4, np.float32)
+        _scheck(_L.sno_get_scale(self._h, out.ctypes.data_as(_fp)), "sno_get_scale")
+        return out
+
+    def close(self):
+        if self._h:
+            _L.sno_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def decimate(traces, decim, stream=None):
+    """Keep every decim-th sample of float32 device traces [n][4][n_rec][nt]."""
+    import torch
+    n, four, n_rec, nt = traces.shape
+    out = torch.empty((n, 4, n_rec, nt // decim), dtype=torch.float32, device=traces.device)
+    _scheck(_L.sno_decimate(_dev(traces), n, n_rec, nt, int(decim), _dev(out), _stream_handle(stream)), "sno_decimate")
+    return out

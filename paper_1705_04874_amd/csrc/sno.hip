@@ -1,0 +1,913 @@
+// Spectral neural operator surrogate: BF16-MFMA / FP32-accumulate kernels,
+// hand-written forward and backward passes, Adam, error head, solver fallback.
+//
+// Every contraction is one call of a strided, batched GEMM
+//   C[b](m, n) = alpha * sum_kb sum_k A[b, kb](m, k) B[b, kb](k, n) + beta * C[b](m, n) + bias(m)
+// whose operands are addressed through arbitrary element strides (so
+// transposes, the per-mode complex mixing and the weight gradients summed over
+// the batch are all the same kernel).  A 256-thread block computes a 64 x 64
+// tile; each K step stages A (64 x 16) and B (16 x 64) in LDS as BF16 with k
+// contiguous and each wave issues 2 x 2 MFMA 16x16x16 ops.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <string>
+#include <vector>
+
+#include "sno.h"
+
+namespace {
+
+typedef short bf4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+thread_local std::string g_serr;
+
+int sfail(int code, const std::string& msg)
+{
+    g_serr = msg;
+    return code;
+}
+
+#define S_TRY(expr)                                                                               \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return sfail(e_ == hipErrorOutOfMemory ? PSTD_ENOMEM : PSTD_EDEVICE,                  \
+                         std::string(#expr) + ": " + hipGetErrorString(e_));                      \
+    } while (0)
+
+// round to nearest even
+__device__ __forceinline__ short to_bf16(float f)
+{
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+struct GemmP {
+    int M, N, K, KB;
+    const float* A;
+    long sAm, sAk, sAb, sAkb;
+    const float* B;
+    long sBk, sBn, sBb, sBkb;
+    float* C;
+    long sCm, sCn, sCb;
+    float alpha, beta;
+    const float* bias;
+};
+
+__global__ __launch_bounds__(256) void k_gemm(GemmP p)
+{
+    __shared__ short As[64][16];
+    __shared__ short Bs[64][16];
+    const int b = blockIdx.z;
+    const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+    const float* __restrict__ A = p.A + b * p.sAb;
+    const float* __restrict__ B = p.B + b * p.sBb;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    f4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    const int am = t >> 2, aq = (t & 3) * 4;      // A tile: row am, k quad aq
+    const int bn = t & 63, bq = (t >> 6) * 4;     // B tile: column bn, k quad bq
+    for (int kb = 0; kb < p.KB; ++kb) {
+        const float* __restrict__ Ak = A + kb * p.sAkb;
+        const float* __restrict__ Bk = B + kb * p.sBkb;
+        for (int k0 = 0; k0 < p.K; k0 += 16) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = k0 + aq + i;
+                const float v = (m0 + am < p.M && k < p.K) ? Ak[(long)(m0 + am) * p.sAm + (long)k * p.sAk] : 0.f;
+                As[am][aq + i] = to_bf16(v);
+                const int kk = k0 + bq + i;
+                const float u = (n0 + bn < p.N && kk < p.K) ? Bk[(long)kk * p.sBk + (long)(n0 + bn) * p.sBn] : 0.f;
+                Bs[bn][bq + i] = to_bf16(u);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni) {
+                    const int mr = (w >> 1) * 32 + mi * 16 + (lane & 15);
+                    const int nc = (w & 1) * 32 + ni * 16 + (lane & 15);
+                    const bf4 av = *reinterpret_cast<const bf4*>(&As[mr][4 * (lane >> 4)]);
+                    const bf4 bv = *reinterpret_cast<const bf4*>(&Bs[nc][4 * (lane >> 4)]);
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[mi][ni], 0, 0, 0);
+                }
+            __syncthreads();
+        }
+    }
+    float* __restrict__ C = p.C + b * p.sCb;
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = m0 + (w >> 1) * 32 + mi * 16 + 4 * (lane >> 4) + i;
+                const int col = n0 + (w & 1) * 32 + ni * 16 + (lane & 15);
+                if (row < p.M && col < p.N) {
+                    float* c = C + (long)row * p.sCm + (long)col * p.sCn;
+                    float v = p.alpha * acc[mi][ni][i];
+                    if (p.beta != 0.f) v += p.beta * (*c);
+                    if (p.bias) v += p.bias[row];
+                    *c = v;
+                }
+            }
+}
+
+void gemm(hipStream_t st, int batch, int M, int N, int K, int KB, const float* A, long sAm, long sAk, long sAb,
+          long sAkb, const float* B, long sBk, long sBn, long sBb, long sBkb, float* C, long sCm, long sCn, long sCb,
+          float alpha = 1.f, float beta = 0.f, const float* bias = nullptr)
+{
+    GemmP p{M, N, K, KB, A, sAm, sAk, sAb, sAkb, B, sBk, sBn, sBb, sBkb, C, sCm, sCn, sCb, alpha, beta, bias};
+    hipLaunchKernelGGL(k_gemm, dim3((N + 63) / 64, (M + 63) / 64, batch), dim3(256), 0, st, p);
+}
+
+// ---------------------------------------------------------------------------
+constexpr float GELU_C = 0.7978845608028654f;   // sqrt(2 / pi)
+
+__device__ __forceinline__ float gelu_f(float x)
+{
+    return 0.5f * x * (1.f + tanhf(GELU_C * (x + 0.044715f * x * x * x)));
+}
+__device__ __forceinline__ float gelu_d(float x)
+{
+    const float th = tanhf(GELU_C * (x + 0.044715f * x * x * x));
+    return 0.5f * (1.f + th) + 0.5f * x * (1.f - th * th) * GELU_C * (1.f + 3.f * 0.044715f * x * x);
+}
+
+__global__ void k_gelu(const float* __restrict__ z, float* __restrict__ y, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        y[i] = gelu_f(z[i]);
+}
+
+__global__ void k_gelu_bwd(const float* __restrict__ dy, const float* __restrict__ z, float* __restrict__ dz, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        dz[i] = dy[i] * gelu_d(z[i]);
+}
+
+struct Feat {
+    float off[9], inv[9];
+};
+
+// A[b][i][t] = (X[b][i] - off_i) / scale_i for i < 9, A[b][9][t] = t / T
+__global__ void k_features(const float* __restrict__ X, Feat f, int B, int T, float* __restrict__ A)
+{
+    const long n = (long)B * 10 * T;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        const int t = e % T;
+        const int i = (e / T) % 10;
+        const int b = e / (10L * T);
+        A[e] = i < 9 ? (X[b * 9 + i] - f.off[i]) * f.inv[i] : (float)t / (float)T;
+    }
+}
+
+// out[r] = sum over b, t of X[b][r][t]  (fixed reduction order)
+__global__ __launch_bounds__(256) void k_rowsum(const float* __restrict__ X, int B, int R, int T, float* __restrict__ out)
+{
+    __shared__ float red[256];
+    const int r = blockIdx.x;
+    float s = 0.f;
+    for (int b = 0; b < B; ++b)
+        for (int t = threadIdx.x; t < T; t += 256) s += X[((long)b * R + r) * T + t];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[r] = red[0];
+}
+
+// dY = 2 (Y - Yt) / n; block partial sums of (Y - Yt)^2
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ Y, const float* __restrict__ Yt, long n,
+                                             float* __restrict__ dY, float* __restrict__ part)
+{
+    __shared__ float red[256];
+    float s = 0.f;
+    const float g = 2.f / (float)n;
+    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
+        const float d = Y[i] - Yt[i];
+        dY[i] = g * d;
+        s += d * d;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_sum_parts(const float* __restrict__ part, int np, float* __restrict__ out, float scale)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        float s = 0.f;
+        for (int i = 0; i < np; ++i) s += part[i];
+        *out = s * scale;
+    }
+}
+
+__global__ void k_adam(float* __restrict__ th, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                       long n, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const float mi = b1 * m[i] + (1.f - b1) * g[i];
+        const float vi = b2 * v[i] + (1.f - b2) * g[i] * g[i];
+        m[i] = mi;
+        v[i] = vi;
+        th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+// gather a batch: Xb[b] = X[idx[b]], Yb[b][o][t] = Y[idx[b]][o][t] / scale[o / n_rec]
+__global__ void k_gather(const float* __restrict__ X, const float* __restrict__ Y, const int* __restrict__ idx, int B,
+                         int O, int T, int n_rec, const float* __restrict__ scale, float* __restrict__ Xb,
+                         float* __restrict__ Yb)
+{
+    const long per = (long)O * T;
+    const long n = (long)B * per;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        const int b = e / per;
+        const long r = e - b * per;
+        const int o = r / T;
+        Yb[e] = Y[(long)idx[b] * per + r] / scale[o / n_rec];
+        if (r < 9) Xb[b * 9 + r] = X[(long)idx[b] * 9 + r];
+    }
+}
+
+// Y[b][o][t] *= scale[o / n_rec]
+__global__ void k_scale_out(float* __restrict__ Y, long n, int O, int T, int n_rec, const float* __restrict__ scale)
+{
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        const int o = (e / T) % O;
+        Y[e] *= scale[o / n_rec];
+    }
+}
+
+// per-component sums of squares: ss[c] += sum over samples, receivers, t of Y^2
+__global__ __launch_bounds__(256) void k_comp_sumsq(const float* __restrict__ Y, int n, int n_rec, int T,
+                                                    double* __restrict__ ss)
+{
+    __shared__ double red[256];
+    const int c = blockIdx.x;
+    double s = 0.0;
+    const long per = (long)n_rec * T;
+    for (int b = 0; b < n; ++b)
+        for (long i = threadIdx.x; i < per; i += 256) {
+            const double v = Y[((long)b * 4 + c) * per + i];
+            s += v * v;
+        }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) ss[c] = red[0];
+}
+
+// per sample: max over the 4 components of ||Yp - Yt|| / ||Yt|| (any units)
+__global__ __launch_bounds__(256) void k_relerr(const float* __restrict__ Yp, const float* __restrict__ Yt, int n_rec,
+                                                int T, float* __restrict__ err)
+{
+    __shared__ float rn[256], rd[256];
+    const int b = blockIdx.x;
+    const long per = (long)n_rec * T;
+    float worst = 0.f;
+    for (int c = 0; c < 4; ++c) {
+        float sn = 0.f, sd = 0.f;
+        const long base = ((long)b * 4 + c) * per;
+        for (long i = threadIdx.x; i < per; i += 256) {
+            const float d = Yp[base + i] - Yt[base + i];
+            sn += d * d;
+            sd += Yt[base + i] * Yt[base + i];
+        }
+        rn[threadIdx.x] = sn;
+        rd[threadIdx.x] = sd;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if (threadIdx.x < h) {
+                rn[threadIdx.x] += rn[threadIdx.x + h];
+                rd[threadIdx.x] += rd[threadIdx.x + h];
+            }
+            __syncthreads();
+        }
+        worst = fmaxf(worst, sqrtf(rn[0] / fmaxf(rd[0], 1e-30f)));
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) err[b] = worst;
+}
+
+// phi[b] = (mean over t of V[b][c][t] for c < C, 1)
+__global__ __launch_bounds__(256) void k_pool(const float* __restrict__ V, int C, int T, float* __restrict__ phi)
+{
+    __shared__ float red[256];
+    const int b = blockIdx.x / C, c = blockIdx.x % C;
+    float s = 0.f;
+    for (int t = threadIdx.x; t < T; t += 256) s += V[((long)b * C + c) * T + t];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        phi[(long)b * (C + 1) + c] = red[0] / T;
+        if (c == 0) phi[(long)b * (C + 1) + C] = 1.f;
+    }
+}
+
+// est[b] = exp(sum_j h[j] phi[b][j] + margin)
+__global__ void k_head(const float* __restrict__ phi, const float* __restrict__ h, int D, int B, float margin,
+                       float* __restrict__ est)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= B) return;
+    float s = margin;
+    for (int j = 0; j < D; ++j) s += h[j] * phi[(long)b * D + j];
+    est[b] = expf(fminf(s, 30.f));
+}
+
+__global__ void k_decim(const float* __restrict__ in, long rows, int nt, int decim, float* __restrict__ out)
+{
+    const int no = nt / decim;
+    const long n = rows * no;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        const long r = e / no;
+        const int j = e - r * no;
+        out[e] = in[r * nt + (long)j * decim];
+    }
+}
+
+int grid_for(long n) { return (int)std::min<long>((n + 255) / 256, 4096); }
+
+}  // namespace
+
+// ===========================================================================
+struct sno {
+    sno_cfg cfg{};
+    int O = 0, n_in = 9;
+    long np = 0;
+    long off_P, off_pb, off_W[16], off_b[16], off_Rr[16], off_Ri[16], off_Q1, off_q1b, off_Q2, off_q2b;
+    float *theta = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
+    float *F = nullptr, *G = nullptr;
+    float *dscale = nullptr;
+    float scale[4] = {1, 1, 1, 1};
+    std::vector<float> head;
+    float head_margin = 0.f;
+    float* dhead = nullptr;
+    Feat feat{};
+    int device = 0;
+    // workspace for batches of up to bmax samples
+    int bmax = 0;
+    float *A = nullptr, *Vb = nullptr, *Vh = nullptr, *Z = nullptr, *Uh = nullptr, *Hp = nullptr, *Hq = nullptr,
+          *Y = nullptr, *X0 = nullptr, *X1 = nullptr, *X2 = nullptr, *dH = nullptr, *dUh = nullptr, *dVh = nullptr,
+          *part = nullptr, *lossd = nullptr, *phi = nullptr, *Xb = nullptr, *Yb = nullptr;
+    int* idxd = nullptr;
+
+    float* V(int l) { return l < cfg.L ? Vb + (long)l * bmax * cfg.C * cfg.T : Z + (long)(cfg.L - 1) * bmax * cfg.C * cfg.T; }
+    float* Zl(int l) { return Z + (long)l * bmax * cfg.C * cfg.T; }
+    float* Vhl(int l) { return Vh + (long)l * bmax * cfg.C * 2 * cfg.K; }
+
+    void free_ws()
+    {
+        for (float* p : {A, Vb, Vh, Z, Uh, Hp, Hq, Y, X0, X1, X2, dH, dUh, dVh, part, lossd, phi, Xb, Yb}) (void)hipFree(p);
+        (void)hipFree(idxd);
+        A = Vb = Vh = Z = Uh = Hp = Hq = Y = X0 = X1 = X2 = dH = dUh = dVh = part = lossd = phi = Xb = Yb = nullptr;
+        idxd = nullptr;
+        bmax = 0;
+    }
+    ~sno()
+    {
+        free_ws();
+        for (float* p : {theta, grad, m1, m2, F, G, dscale, dhead}) (void)hipFree(p);
+    }
+
+    int ensure(int B)
+    {
+        if (B <= bmax) return PSTD_OK;
+        free_ws();
+        const long C = cfg.C, T = cfg.T, K2 = 2 * cfg.K, H = cfg.H, L = cfg.L;
+        auto al = [&](float** p, long n) { return hipMalloc(p, std::max<long>(n, 1) * sizeof(float)); };
+        if (al(&A, (long)B * 10 * T) || al(&Vb, L * B * C * T) || al(&Vh, L * B * C * K2) || al(&Z, L * B * C * T) ||
+            al(&Uh, (long)B * C * K2) || al(&Hp, (long)B * H * T) || al(&Hq, (long)B * H * T) ||
+            al(&Y, (long)B * O * T) || al(&X0, (long)B * std::max(C, (long)O) * T) || al(&X1, (long)B * C * T) ||
+            al(&X2, (long)B * C * T) || al(&dH, (long)B * H * T) || al(&dUh, (long)B * C * K2) ||
+            al(&dVh, (long)B * C * K2) || al(&part, 4096) || al(&lossd, 4) || al(&phi, (long)B * (C + 1)) ||
+            al(&Xb, (long)B * 9) || al(&Yb, (long)B * O * T) || hipMalloc(&idxd, B * sizeof(int)))
+            return sfail(PSTD_ENOMEM, "surrogate workspace");
+        bmax = B;
+        return PSTD_OK;
+    }
+};
+
+namespace {
+
+long layout(sno_cfg c, sno* s)
+{
+    const int O = 4 * c.n_rec;
+    long o = 0;
+    auto take = [&](long n) { long r = o; o += n; return r; };
+    long P = take((long)c.C * 10), pb = take(c.C);
+    long W[16], b[16], Rr[16], Ri[16];
+    for (int l = 0; l < c.L; ++l) {
+        W[l] = take((long)c.C * c.C);
+        b[l] = take(c.C);
+        Rr[l] = take((long)c.K * c.C * c.C);
+        Ri[l] = take((long)c.K * c.C * c.C);
+    }
+    long Q1 = take((long)c.H * c.C), q1b = take(c.H), Q2 = take((long)O * c.H), q2b = take(O);
+    if (s) {
+        s->off_P = P;
+        s->off_pb = pb;
+        for (int l = 0; l < c.L; ++l) {
+            s->off_W[l] = W[l];
+            s->off_b[l] = b[l];
+            s->off_Rr[l] = Rr[l];
+            s->off_Ri[l] = Ri[l];
+        }
+        s->off_Q1 = Q1;
+        s->off_q1b = q1b;
+        s->off_Q2 = Q2;
+        s->off_q2b = q2b;
+    }
+    return o;
+}
+
+bool cfg_ok(const sno_cfg* c)
+{
+    if (!c || c->n_rec < 1 || c->T < 16 || c->T > 4096 || (c->T & (c->T - 1)) || c->C < 16 || c->C % 16 ||
+        c->K < 1 || c->K > c->T / 2 || c->L < 1 || c->L > 16 || c->H < 16 || c->H % 16)
+        return false;
+    for (int i = 0; i < 9; ++i)
+        if (!(c->feat_scale[i] != 0.0) || !std::isfinite(c->feat_off[i]) || !std::isfinite(c->feat_scale[i])) return false;
+    return true;
+}
+
+// forward of B samples whose raw features are X (device); leaves the caches in s
+void forward(sno* s, hipStream_t st, const float* X, int B)
+{
+    const sno_cfg& c = s->cfg;
+    const long C = c.C, T = c.T, K = c.K, K2 = 2 * K, H = c.H, O = s->O;
+    const float* th = s->theta;
+    hipLaunchKernelGGL(k_features, dim3(grid_for(B * 10 * T)), dim3(256), 0, st, X, s->feat, B, (int)T, s->A);
+    gemm(st, B, C, T, 10, 1, th + s->off_P, 10, 1, 0, 0, s->A, T, 1, 10 * T, 0, s->V(0), T, 1, C * T, 1.f, 0.f,
+         th + s->off_pb);
+    for (int l = 0; l < c.L; ++l) {
+        float* V = s->V(l);
+        float* Vh = s->Vhl(l);
+        float* Z = s->Zl(l);
+        // truncated DFT along time
+        gemm(st, B, C, K2, T, 1, V, T, 1, C * T, 0, s->F, K2, 1, 0, 0, Vh, K2, 1, C * K2);
+        // complex mixing per mode: batch over modes, samples as columns
+        const float* Rr = th + s->off_Rr[l];
+        const float* Ri = th + s->off_Ri[l];
+        gemm(st, K, C, B, C, 1, Rr, C, 1, C * C, 0, Vh, K2, C * K2, 1, 0, s->Uh, K2, C * K2, 1, 1.f, 0.f);
+        gemm(st, K, C, B, C, 1, Ri, C, 1, C * C, 0, Vh + K, K2, C * K2, 1, 0, s->Uh, K2, C * K2, 1, -1.f, 1.f);
+        gemm(st, K, C, B, C, 1, Ri, C, 1, C * C, 0, Vh, K2, C * K2, 1, 0, s->Uh + K, K2, C * K2, 1, 1.f, 0.f);
+        gemm(st, K, C, B, C, 1, Rr, C, 1, C * C, 0, Vh + K, K2, C * K2, 1, 0, s->Uh + K, K2, C * K2, 1, 1.f, 1.f);
+        // Z = W V + b + inverse DFT of the mixed modes
+        gemm(st, B, C, T, C, 1, th + s->off_W[l], C, 1, 0, 0, V, T, 1, C * T, 0, Z, T, 1, C * T, 1.f, 0.f,
+             th + s->off_b[l]);
+        gemm(st, B, C, T, K2, 1, s->Uh, K2, 1, C * K2, 0, s->G, T, 1, 0, 0, Z, T, 1, C * T, 1.f, 1.f);
+        if (l < c.L - 1)
+            hipLaunchKernelGGL(k_gelu, dim3(grid_for(B * C * T)), dim3(256), 0, st, Z, s->V(l + 1), (long)B * C * T);
+    }
+    gemm(st, B, H, T, C, 1, th + s->off_Q1, C, 1, 0, 0, s->V(c.L), T, 1, C * T, 0, s->Hp, T, 1, H * T, 1.f, 0.f,
+         th + s->off_q1b);
+    hipLaunchKernelGGL(k_gelu, dim3(grid_for(B * H * T)), dim3(256), 0, st, s->Hp, s->Hq, (long)B * H * T);
+    gemm(st, B, O, T, H, 1, th + s->off_Q2, H, 1, 0, 0, s->Hq, T, 1, H * T, 0, s->Y, T, 1, O * T, 1.f, 0.f,
+         th + s->off_q2b);
+}
+
+// gradient of the mean squared error of s->Y against Yt (after forward)
+void backward(sno* s, hipStream_t st, const float* Yt, int B)
+{
+    const sno_cfg& c = s->cfg;
+    const long C = c.C, T = c.T, K = c.K, K2 = 2 * K, H = c.H, O = s->O;
+    const float* th = s->theta;
+    float* g = s->grad;
+    const long nY = (long)B * O * T;
+    float* dY = s->X0;
+    hipLaunchKernelGGL(k_mse, dim3(256), dim3(256), 0, st, s->Y, Yt, nY, dY, s->part);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, s->part, 256, s->lossd, 1.f / (float)nY);
+    // projection
+    gemm(st, 1, O, H, T, B, dY, T, 1, 0, O * T, s->Hq, 1, T, 0, H * T, g + s->off_Q2, H, 1, 0);
+    hipLaunchKernelGGL(k_rowsum, dim3(O), dim3(256), 0, st, dY, B, (int)O, (int)T, g + s->off_q2b);
+    gemm(st, B, H, T, O, 1, th + s->off_Q2, 1, H, 0, 0, dY, T, 1, O * T, 0, s->dH, T, 1, H * T);
+    hipLaunchKernelGGL(k_gelu_bwd, dim3(grid_for(B * H * T)), dim3(256), 0, st, s->dH, s->Hp, s->dH, (long)B * H * T);
+    gemm(st, 1, H, C, T, B, s->dH, T, 1, 0, H * T, s->V(c.L), 1, T, 0, C * T, g + s->off_Q1, C, 1, 0);
+    hipLaunchKernelGGL(k_rowsum, dim3(H), dim3(256), 0, st, s->dH, B, (int)H, (int)T, g + s->off_q1b);
+    float* bufs[3] = {s->X1, s->X2, s->X0};
+    float* dV = bufs[0];
+    gemm(st, B, C, T, H, 1, th + s->off_Q1, 1, C, 0, 0, s->dH, T, 1, H * T, 0, dV, T, 1, C * T);
+    for (int l = c.L - 1; l >= 0; --l) {
+        float* dZ = dV;
+        float* other[2];
+        int q = 0;
+        for (float* b : bufs)
+            if (b != dV) other[q++] = b;
+        if (l < c.L - 1) {
+            dZ = other[0];
+            hipLaunchKernelGGL(k_gelu_bwd, dim3(grid_for(B * C * T)), dim3(256), 0, st, dV, s->Zl(l), dZ,
+                               (long)B * C * T);
+        }
+        float* dVn = dZ == dV ? other[0] : other[1];
+        float* V = s->V(l);
+        float* Vh = s->Vhl(l);
+        gemm(st, 1, C, C, T, B, dZ, T, 1, 0, C * T, V, 1, T, 0, C * T, g + s->off_W[l], C, 1, 0);
+        hipLaunchKernelGGL(k_rowsum, dim3(C), dim3(256), 0, st, dZ, B, (int)C, (int)T, g + s->off_b[l]);
+        // dUh = dZ G^T
+        gemm(st, B, C, K2, T, 1, dZ, T, 1, C * T, 0, s->G, 1, T, 0, 0, s->dUh, K2, 1, C * K2);
+        // spectral weights: dRr = dUr Vr^T + dUi Vi^T ; dRi = dUi Vr^T - dUr Vi^T  (per mode, summed over samples)
+        gemm(st, K, C, C, B, 2, s->dUh, K2, C * K2, 1, K, Vh, C * K2, K2, 1, K, g + s->off_Rr[l], C, 1, C * C);
+        gemm(st, K, C, C, B, 1, s->dUh + K, K2, C * K2, 1, 0, Vh, C * K2, K2, 1, 0, g + s->off_Ri[l], C, 1, C * C,
+             1.f, 0.f);
+        gemm(st, K, C, C, B, 1, s->dUh, K2, C * K2, 1, 0, Vh + K, C * K2, K2, 1, 0, g + s->off_Ri[l], C, 1, C * C,
+             -1.f, 1.f);
+        // dVr = Rr^T dUr + Ri^T dUi ; dVi = -Ri^T dUr + Rr^T dUi
+        const float* Rr = th + s->off_Rr[l];
+        const float* Ri = th + s->off_Ri[l];
+        gemm(st, K, C, B, C, 1, Rr, 1, C, C * C, 0, s->dUh, K2, C * K2, 1, 0, s->dVh, K2, C * K2, 1, 1.f, 0.f);
+        gemm(st, K, C, B, C, 1, Ri, 1, C, C * C, 0, s->dUh + K, K2, C * K2, 1, 0, s->dVh, K2, C * K2, 1, 1.f, 1.f);
+        gemm(st, K, C, B, C, 1, Ri, 1, C, C * C, 0, s->dUh, K2, C * K2, 1, 0, s->dVh + K, K2, C * K2, 1, -1.f, 0.f);
+        gemm(st, K, C, B, C, 1, Rr, 1, C, C * C, 0, s->dUh + K, K2, C * K2, 1, 0, s->dVh + K, K2, C * K2, 1, 1.f, 1.f);
+        // dV = W^T dZ + dVh F^T
+        gemm(st, B, C, T, C, 1, th + s->off_W[l], 1, C, 0, 0, dZ, T, 1, C * T, 0, dVn, T, 1, C * T);
+        gemm(st, B, C, T, K2, 1, s->dVh, K2, 1, C * K2, 0, s->F, 1, K2, 0, 0, dVn, T, 1, C * T, 1.f, 1.f);
+        dV = dVn;
+    }
+    gemm(st, 1, C, 10, T, B, dV, T, 1, 0, C * T, s->A, 1, T, 0, 10 * T, g + s->off_P, 10, 1, 0);
+    hipLaunchKernelGGL(k_rowsum, dim3(C), dim3(256), 0, st, dV, B, (int)C, (int)T, g + s->off_pb);
+}
+
+// error head inputs of the last forward: pooled last hidden layer
+void pool(sno* s, hipStream_t st, int B)
+{
+    hipLaunchKernelGGL(k_pool, dim3(B * s->cfg.C), dim3(256), 0, st, s->V(s->cfg.L), s->cfg.C, s->cfg.T, s->phi);
+}
+
+}  // namespace
+
+extern "C" {
+
+long sno_n_params(const sno_cfg* cfg)
+{
+    if (!cfg_ok(cfg)) return -1;
+    return layout(*cfg, nullptr);
+}
+
+int sno_create(const sno_cfg* cfg, const float* params, sno** out)
+{
+    if (!out || !params) return sfail(PSTD_EINVAL, "null argument");
+    *out = nullptr;
+    if (!cfg_ok(cfg)) return sfail(PSTD_EINVAL, "bad surrogate configuration");
+    auto* s = new (std::nothrow) sno();
+    if (!s) return sfail(PSTD_ENOMEM, "host allocation");
+    s->cfg = *cfg;
+    s->O = 4 * cfg->n_rec;
+    s->np = layout(*cfg, s);
+    (void)hipGetDevice(&s->device);
+    for (int i = 0; i < 9; ++i) {
+        s->feat.off[i] = (float)cfg->feat_off[i];
+        s->feat.inv[i] = (float)(1.0 / cfg->feat_scale[i]);
+    }
+    const long np = s->np;
+    const int T = cfg->T, K = cfg->K;
+    // DFT bases (double, rounded once): F (T x 2K) = [cos | -sin], G (2K x T)
+    std::vector<float> F((size_t)T * 2 * K), G((size_t)2 * K * T);
+    for (int j = 0; j < T; ++j)
+        for (int k = 0; k < K; ++k) {
+            const double a = 2.0 * M_PI * (double)j * k / T;
+            const double w = k == 0 ? 1.0 : 2.0;
+            F[(size_t)j * 2 * K + k] = (float)std::cos(a);
+            F[(size_t)j * 2 * K + K + k] = (float)(-std::sin(a));
+            G[(size_t)k * T + j] = (float)(w * std::cos(a) / T);
+            G[(size_t)(K + k) * T + j] = (float)(-w * std::sin(a) / T);
+        }
+    int rc = PSTD_OK;
+    if (hipMalloc(&s->theta, np * 4) || hipMalloc(&s->grad, np * 4) || hipMalloc(&s->m1, np * 4) ||
+        hipMalloc(&s->m2, np * 4) || hipMalloc(&s->F, F.size() * 4) || hipMalloc(&s->G, G.size() * 4) ||
+        hipMalloc(&s->dscale, 16) || hipMalloc(&s->dhead, (cfg->C + 1) * 4))
+        rc = sfail(PSTD_ENOMEM, "surrogate parameters");
+    if (!rc && (hipMemcpy(s->theta, params, np * 4, hipMemcpyHostToDevice) ||
+                hipMemcpy(s->F, F.data(), F.size() * 4, hipMemcpyHostToDevice) ||
+                hipMemcpy(s->G, G.data(), G.size() * 4, hipMemcpyHostToDevice) ||
+                hipMemcpy(s->dscale, s->scale, 16, hipMemcpyHostToDevice) || hipMemset(s->m1, 0, np * 4) ||
+                hipMemset(s->m2, 0, np * 4) || hipMemset(s->grad, 0, np * 4)))
+        rc = sfail(PSTD_EDEVICE, "surrogate upload");
+    // error head defaults to "always unsure" until trained: exp(30)
+    s->head.assign(cfg->C + 1, 0.f);
+    s->head[cfg->C] = 30.f;
+    if (!rc && hipMemcpy(s->dhead, s->head.data(), (cfg->C + 1) * 4, hipMemcpyHostToDevice))
+        rc = sfail(PSTD_EDEVICE, "surrogate upload");
+    if (rc) {
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return PSTD_OK;
+}
+
+void sno_destroy(sno* s)
+{
+    if (!s) return;
+    (void)hipSetDevice(s->device);
+    (void)hipDeviceSynchronize();
+    delete s;
+}
+
+int sno_get_params(const sno* s, float* params)
+{
+    if (!s || !params) return sfail(PSTD_EINVAL, "null argument");
+    S_TRY(hipDeviceSynchronize());
+    S_TRY(hipMemcpy(params, s->theta, s->np * 4, hipMemcpyDeviceToHost));
+    return PSTD_OK;
+}
+
+int sno_get_scale(const sno* s, float* scale4)
+{
+    if (!s || !scale4) return sfail(PSTD_EINVAL, "null argument");
+    std::memcpy(scale4, s->scale, 16);
+    return PSTD_OK;
+}
+
+int sno_forward(sno* s, const float* X, int n, float* Y, void* hip_stream)
+{
+    if (!s || !X || !Y || n < 1) return sfail(PSTD_EINVAL, "bad arguments");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int bs = 32;
+    int rc = s->ensure(std::min(n, bs));
+    if (rc) return rc;
+    const long per = (long)s->O * s->cfg.T;
+    for (int b0 = 0; b0 < n; b0 += bs) {
+        const int B = std::min(bs, n - b0);
+        forward(s, st, X + (long)b0 * 9, B);
+        S_TRY(hipMemcpyAsync(Y + (long)b0 * per, s->Y, B * per * 4, hipMemcpyDeviceToDevice, st));
+    }
+    S_TRY(hipGetLastError());
+    S_TRY(hipStreamSynchronize(st));
+    return PSTD_OK;
+}
+
+int sno_gradient(sno* s, const float* X, const float* Yt, int n, float* grad, float* loss, void* hip_stream)
+{
+    if (!s || !X || !Yt || !grad || n < 1) return sfail(PSTD_EINVAL, "bad arguments");
+    hipStream_t st = (hipStream_t)hip_stream;
+    int rc = s->ensure(n);
+    if (rc) return rc;
+    forward(s, st, X, n);
+    backward(s, st, Yt, n);
+    S_TRY(hipMemcpyAsync(grad, s->grad, s->np * 4, hipMemcpyDeviceToDevice, st));
+    float l = 0.f;
+    S_TRY(hipMemcpyAsync(&l, s->lossd, 4, hipMemcpyDeviceToHost, st));
+    S_TRY(hipGetLastError());
+    S_TRY(hipStreamSynchronize(st));
+    if (loss) *loss = l;
+    return PSTD_OK;
+}
+
+int sno_train(sno* s, const float* X, const float* Y, int n, const sno_train_cfg* tc, float* loss_curve,
+              void* hip_stream)
+{
+    if (!s || !X || !Y || !tc || tc->epochs < 0 || tc->batch < 1 || !(tc->lr > 0) || tc->n_calib < 0)
+        return sfail(PSTD_EINVAL, "bad arguments");
+    const int n_fit = n - tc->n_calib;
+    if (n_fit < 1) return sfail(PSTD_EINVAL, "no training samples left after the calibration split");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const sno_cfg& c = s->cfg;
+    const int B = std::min(tc->batch, n_fit);
+    int rc = s->ensure(std::max(B, 32));
+    if (rc) return rc;
+    // output normalisation: per-component RMS over the fitting samples
+    double* ss = nullptr;
+    S_TRY(hipMalloc(&ss, 4 * sizeof(double)));
+    hipLaunchKernelGGL(k_comp_sumsq, dim3(4), dim3(256), 0, st, Y, n_fit, c.n_rec, c.T, ss);
+    double hs[4];
+    S_TRY(hipMemcpyAsync(hs, ss, sizeof(hs), hipMemcpyDeviceToHost, st));
+    S_TRY(hipStreamSynchronize(st));
+    (void)hipFree(ss);
+    for (int k = 0; k < 4; ++k) {
+        const double rms = std::sqrt(hs[k] / ((double)n_fit * c.n_rec * c.T));
+        s->scale[k] = rms > 0 ? (float)rms : 1.f;
+    }
+    S_TRY(hipMemcpyAsync(s->dscale, s->scale, 16, hipMemcpyHostToDevice, st));
+    // Adam with cosine learning-rate decay
+    std::mt19937_64 rng(tc->seed);
+    std::vector<int> order(n_fit);
+    for (int i = 0; i < n_fit; ++i) order[i] = i;
+    const int steps_per_epoch = n_fit / B;
+    const long total = (long)steps_per_epoch * tc->epochs;
+    long step = 0;
+    S_TRY(hipMemsetAsync(s->m1, 0, s->np * 4, st));
+    S_TRY(hipMemsetAsync(s->m2, 0, s->np * 4, st));
+    std::vector<float> lbuf(steps_per_epoch);
+    for (int ep = 0; ep < tc->epochs; ++ep) {
+        std::shuffle(order.begin(), order.end(), rng);
+        double lsum = 0.0;
+        for (int it = 0; it < steps_per_epoch; ++it) {
+            S_TRY(hipMemcpyAsync(s->idxd, order.data() + (long)it * B, B * sizeof(int), hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL(k_gather, dim3(grid_for((long)B * s->O * c.T)), dim3(256), 0, st, X, Y, s->idxd, B,
+                               s->O, c.T, c.n_rec, s->dscale, s->Xb, s->Yb);
+            forward(s, st, s->Xb, B);
+            backward(s, st, s->Yb, B);
+            ++step;
+            const double lr = tc->lr * 0.5 * (1.0 + std::cos(M_PI * (double)(step - 1) / (double)std::max(1L, total)));
+            const float c1 = (float)(1.0 - std::pow(0.9, (double)step));
+            const float c2 = (float)(1.0 - std::pow(0.999, (double)step));
+            hipLaunchKernelGGL(k_adam, dim3(grid_for(s->np)), dim3(256), 0, st, s->theta, s->grad, s->m1, s->m2, s->np,
+                               (float)lr, 0.9f, 0.999f, 1e-8f, c1, c2);
+            S_TRY(hipMemcpyAsync(&lbuf[it], s->lossd, 4, hipMemcpyDeviceToHost, st));
+        }
+        S_TRY(hipGetLastError());
+        S_TRY(hipStreamSynchronize(st));
+        for (float v : lbuf) lsum += v;
+        if (loss_curve) loss_curve[ep] = (float)(lsum / std::max(1, steps_per_epoch));
+        if (!std::isfinite(lsum)) return sfail(PSTD_EUNSTABLE, "training diverged");
+    }
+    // error head: least squares of log(relative error) on the pooled last
+    // hidden layer of the calibration samples, plus a one-sided 95 % margin
+    const int D = c.C + 1;
+    std::vector<float> phis, errs;
+    if (tc->n_calib > 1) {
+        float* err = nullptr;
+        float* Yp = nullptr;
+        const long per = (long)s->O * c.T;
+        const int bs = std::min(32, s->bmax);
+        S_TRY(hipMalloc(&err, tc->n_calib * 4));
+        S_TRY(hipMalloc(&Yp, (long)bs * per * 4));
+        phis.resize((size_t)tc->n_calib * D);
+        errs.resize(tc->n_calib);
+        for (int b0 = 0; b0 < tc->n_calib; b0 += bs) {
+            const int nb = std::min(bs, tc->n_calib - b0);
+            const int i0 = n_fit + b0;
+            forward(s, st, X + (long)i0 * 9, nb);
+            S_TRY(hipMemcpyAsync(Yp, s->Y, nb * per * 4, hipMemcpyDeviceToDevice, st));
+            hipLaunchKernelGGL(k_scale_out, dim3(grid_for(nb * per)), dim3(256), 0, st, Yp, nb * per, s->O, c.T,
+                               c.n_rec, s->dscale);
+            hipLaunchKernelGGL(k_relerr, dim3(nb), dim3(256), 0, st, Yp, Y + (long)i0 * per, c.n_rec, c.T, err + b0);
+            pool(s, st, nb);
+            S_TRY(hipMemcpyAsync(phis.data() + (size_t)b0 * D, s->phi, (size_t)nb * D * 4, hipMemcpyDeviceToHost, st));
+        }
+        S_TRY(hipMemcpyAsync(errs.data(), err, tc->n_calib * 4, hipMemcpyDeviceToHost, st));
+        S_TRY(hipGetLastError());
+        S_TRY(hipStreamSynchronize(st));
+        (void)hipFree(err);
+        (void)hipFree(Yp);
+        // normal equations (Phi^T Phi + ridge) h = Phi^T log e, Cholesky
+        std::vector<double> Ag((size_t)D * D, 0.0), r(D, 0.0);
+        for (int i = 0; i < tc->n_calib; ++i) {
+            const double le = std::log(std::max(1e-6, (double)errs[i]));
+            for (int a = 0; a < D; ++a) {
+                r[a] += phis[(size_t)i * D + a] * le;
+                for (int bb = 0; bb < D; ++bb) Ag[(size_t)a * D + bb] += (double)phis[(size_t)i * D + a] * phis[(size_t)i * D + bb];
+            }
+        }
+        for (int a = 0; a < D; ++a) Ag[(size_t)a * D + a] += 1e-3 * tc->n_calib;
+        std::vector<double> Lc((size_t)D * D, 0.0);
+        bool ok = true;
+        for (int i = 0; i < D && ok; ++i)
+            for (int j = 0; j <= i; ++j) {
+                double v = Ag[(size_t)i * D + j];
+                for (int k = 0; k < j; ++k) v -= Lc[(size_t)i * D + k] * Lc[(size_t)j * D + k];
+                if (i == j) {
+                    if (v <= 0) { ok = false; break; }
+                    Lc[(size_t)i * D + i] = std::sqrt(v);
+                } else {
+                    Lc[(size_t)i * D + j] = v / Lc[(size_t)j * D + j];
+                }
+            }
+        if (ok) {
+            std::vector<double> yv(D), h(D);
+            for (int i = 0; i < D; ++i) {
+                double v = r[i];
+                for (int k = 0; k < i; ++k) v -= Lc[(size_t)i * D + k] * yv[k];
+                yv[i] = v / Lc[(size_t)i * D + i];
+            }
+            for (int i = D - 1; i >= 0; --i) {
+                double v = yv[i];
+                for (int k = i + 1; k < D; ++k) v -= Lc[(size_t)k * D + i] * h[k];
+                h[i] = v / Lc[(size_t)i * D + i];
+            }
+            double res = 0.0;
+            for (int i = 0; i < tc->n_calib; ++i) {
+                double pr = 0.0;
+                for (int a = 0; a < D; ++a) pr += h[a] * phis[(size_t)i * D + a];
+                const double d = std::log(std::max(1e-6, (double)errs[i])) - pr;
+                res += d * d;
+            }
+            const double sd = std::sqrt(res / std::max(1, tc->n_calib - 1));
+            for (int a = 0; a < D; ++a) s->head[a] = (float)h[a];
+            s->head_margin = (float)(1.645 * sd);
+            S_TRY(hipMemcpy(s->dhead, s->head.data(), D * 4, hipMemcpyHostToDevice));
+        }
+    }
+    return PSTD_OK;
+}
+
+int sno_predict(sno* s, const float* X, int n, float* Y, float* est_err, void* hip_stream)
+{
+    if (!s || !X || !Y || n < 0) return sfail(PSTD_EINVAL, "bad arguments");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const sno_cfg& c = s->cfg;
+    const int bs = 32;
+    int rc = s->ensure(bs);
+    if (rc) return rc;
+    const long per = (long)s->O * c.T;
+    for (int b0 = 0; b0 < n; b0 += bs) {
+        const int B = std::min(bs, n - b0);
+        forward(s, st, X + (long)b0 * 9, B);
+        S_TRY(hipMemcpyAsync(Y + (long)b0 * per, s->Y, B * per * 4, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(k_scale_out, dim3(grid_for(B * per)), dim3(256), 0, st, Y + (long)b0 * per, B * per, s->O,
+                           c.T, c.n_rec, s->dscale);
+        if (est_err) {
+            pool(s, st, B);
+            hipLaunchKernelGGL(k_head, dim3((B + 63) / 64), dim3(64), 0, st, s->phi, s->dhead, c.C + 1, B,
+                               s->head_margin, est_err + b0);
+        }
+    }
+    S_TRY(hipGetLastError());
+    return PSTD_OK;
+}
+
+int sno_decimate(const float* in, int n, int n_rec, int nt, int decim, float* out, void* hip_stream)
+{
+    if (!in || !out || n < 0 || n_rec < 0 || nt < 1 || decim < 1) return sfail(PSTD_EINVAL, "bad arguments");
+    const long rows = (long)n * 4 * n_rec;
+    const long total = rows * (nt / decim);
+    if (total == 0) return PSTD_OK;
+    hipLaunchKernelGGL(k_decim, dim3(grid_for(total)), dim3(256), 0, (hipStream_t)hip_stream, in, rows, nt, decim, out);
+    S_TRY(hipGetLastError());
+    return PSTD_OK;
+}
+
+int sno_predict_or_solve(sno* s, pstd3d_ctx* solver, const float* X, const int32_t* src_ijk, const double* m6,
+                         const double* wavelet, int nt_w, int decim, int n, double tol, int max_batch, float* Y,
+                         float* est_err, int* used, void* hip_stream)
+{
+    if (!s || !solver || !X || !src_ijk || !m6 || !wavelet || !Y || !est_err || n < 0 || decim < 1 ||
+        max_batch < 1 || nt_w < 1)
+        return sfail(PSTD_EINVAL, "bad arguments");
+    hipStream_t st = (hipStream_t)hip_stream;
+    int rc = sno_predict(s, X, n, Y, est_err, hip_stream);
+    if (rc) return rc;
+    std::vector<float> est(n);
+    S_TRY(hipMemcpyAsync(est.data(), est_err, (size_t)n * 4, hipMemcpyDeviceToHost, st));
+    S_TRY(hipStreamSynchronize(st));
+    std::vector<int> redo;
+    for (int i = 0; i < n; ++i) {
+        const bool r = !(est[i] <= tol);
+        if (used) used[i] = r ? 1 : 0;
+        if (r) redo.push_back(i);
+    }
+    if (redo.empty()) return PSTD_OK;
+    const int T = s->cfg.T, nrec = s->cfg.n_rec;
+    const int nt = decim * T;
+    const long per = 4L * nrec * T;
+    float *tr = nullptr, *dec = nullptr;
+    const int mb = std::min<int>(max_batch, (int)redo.size());
+    S_TRY(hipMalloc(&tr, (size_t)mb * 4 * nrec * nt * 4));
+    S_TRY(hipMalloc(&dec, (size_t)mb * per * 4));
+    for (size_t b0 = 0; b0 < redo.size(); b0 += mb) {
+        const int nb = (int)std::min<size_t>(mb, redo.size() - b0);
+        std::vector<int32_t> ofs(nb + 1), ijk(3 * nb);
+        std::vector<double> mm(6 * nb), wv((size_t)nb * nt_w);
+        for (int q = 0; q < nb; ++q) {
+            const int i = redo[b0 + q];
+            ofs[q] = q;
+            for (int a = 0; a < 3; ++a) ijk[3 * q + a] = src_ijk[3 * i + a];
+            for (int a = 0; a < 6; ++a) mm[6 * q + a] = m6[6 * i + a];
+            std::memcpy(&wv[(size_t)q * nt_w], wavelet, sizeof(double) * nt_w);
+        }
+        ofs[nb] = nb;
+        rc = pstd3d_set_sources(solver, nb, ofs.data(), ijk.data(), mm.data(), wv.data(), nt_w);
+        if (!rc) rc = pstd3d_run(solver, nt, tr, hip_stream);
+        if (!rc) rc = sno_decimate(tr, nb, nrec, nt, decim, dec, hip_stream);
+        for (int q = 0; q < nb && !rc; ++q) {
+            const int i = redo[b0 + q];
+            if (hipMemcpyAsync(Y + (long)i * per, dec + (long)q * per, per * 4, hipMemcpyDeviceToDevice, st) !=
+                hipSuccess)
+                rc = sfail(PSTD_EDEVICE, "copy of solver traces");
+        }
+        if (rc) break;
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(tr);
+    (void)hipFree(dec);
+    return rc;
+}
+
+const char* sno_last_error(void) { return g_serr.c_str(); }
+
+}  // extern "C"

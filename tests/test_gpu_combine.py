@@ -1,0 +1,116 @@
+"""GPU parity of seis_combine (superposition of shifted, scaled single-event
+traces, Sec. IV) against the FP64 oracle, through the C ABI.
+
+Both sides accumulate in double precision in event order; the GPU rounds once
+to float, so the bar is max |gpu - oracle| <= 1e-6 * max |oracle|.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1705_04874_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def B(gpu):
+    from paper_1705_04874_amd import binding
+    return binding
+
+
+def check(got, ref, tol=1e-6):
+    err = np.abs(got.astype(np.float64) - ref).max()
+    scale = np.abs(ref).max()
+    assert scale > 0
+    assert err <= tol * scale, err / scale
+
+
+@pytest.mark.parametrize("dt_out", [1e-3, 0.7e-3, 1.3e-3])
+def test_small_against_oracle(B, dt_out):
+    import torch
+    rng = np.random.default_rng(1)
+    tr = rng.standard_normal((5, 4, 7, 300)).astype(np.float32)
+    t0 = [1e-3, 0.5e-3, 0.5e-3, 0.5e-3]
+    n_ev = 40
+    src = rng.integers(0, 5, n_ev).astype(np.int32)
+    amp = rng.lognormal(0, 1, n_ev)
+    to = rng.uniform(-0.2, 1.2, n_ev)          # some events start before 0 or end after the record
+    nt_out = 1200
+    got = B.seis_combine(torch.from_numpy(tr).cuda(), t0, src, amp, to, nt_out, 1e-3, dt_out).cpu().numpy()
+    ref = oracle.combine(tr, t0, src, amp, to, nt_out, 1e-3, dt_out)
+    check(got, ref)
+
+
+def test_integer_shifts_are_the_papers_shift_and_add(B):
+    import torch
+    rng = np.random.default_rng(2)
+    nt = 500
+    dt = 1e-3
+    tr = rng.standard_normal((4, 4, 3, nt)).astype(np.float32)
+    src = np.array([3, 1, 1, 0, 2, 3], np.int32)
+    amp = rng.uniform(0.5, 2.0, src.size)
+    shifts = rng.integers(0, nt, src.size)
+    got = B.seis_combine(torch.from_numpy(tr).cuda(), [0.0] * 4, src, amp, shifts * dt, 2 * nt, dt, dt).cpu().numpy()
+    rec = np.zeros((4, 3, 2 * nt))
+    for e in range(src.size):
+        rec[..., shifts[e]:shifts[e] + nt] += amp[e] * tr[src[e]].astype(np.float64)
+    check(got, rec)
+
+
+def test_empty_event_list_gives_zeros(B):
+    import torch
+    tr = torch.ones((2, 4, 3, 10), device="cuda")
+    out = B.seis_combine(tr, [0.0] * 4, [], [], [], 50, 1e-3, 1e-3).cpu().numpy()
+    assert out.shape == (4, 3, 50) and not out.any()
+
+
+def test_full_size_record_on_sampled_receivers(B):
+    """64 sources x 4096 receivers x 2000 samples combined into 300 events of a
+    12 s record at 1 ms; the oracle recomputes 16 receivers."""
+    import torch
+    n_src, n_rec, nt_in, dt_in = 64, 4096, 2000, 0.8e-3
+    g = torch.Generator(device="cuda").manual_seed(5)
+    tr = torch.randn((n_src, 4, n_rec, nt_in), device="cuda", generator=g)
+    ev = inputs.event_catalogue(300, n_src, 10.0, 1.0, seed=2)
+    t0 = [dt_in, 0.5 * dt_in, 0.5 * dt_in, 0.5 * dt_in]
+    say("combine full", tuple(tr.shape), 300)
+    out = B.seis_combine(tr, t0, ev.src_idx, ev.amp, ev.t_origin, 12000, dt_in, 1e-3)
+    sample = np.arange(0, n_rec, 257)[:16]
+    got = out[:, torch.as_tensor(sample, device="cuda")].cpu().numpy()
+    sub = tr[:, :, torch.as_tensor(sample, device="cuda")].cpu().numpy()
+    ref = oracle.combine(sub, t0, ev.src_idx, ev.amp, ev.t_origin, 12000, dt_in, 1e-3)
+    check(got, ref)
+
+
+def test_superposition_equals_joint_solver_run(B):
+    """Combining single-source GPU traces with whole-sample delays equals one GPU
+    run with all the delayed, scaled sources (linearity of eq. 2)."""
+    shape = (32, 24, 40)
+    nz, ny, nx = shape
+    vp = np.full(shape, 2800.0)
+    vs = np.full(shape, 1600.0)
+    rho = np.full(shape, 2200.0)
+    vp[:5], vs[:5], rho[:5] = 1500.0, 0.0, 1000.0
+    dt, nt = 0.8e-3, 160
+    rec = inputs.receiver_block(6, 34, 6, 18, 5)
+    w = inputs.ricker(30.0, dt, nt)
+    pos = np.array([[20, 12, 18], [14, 9, 22], [26, 15, 16]], np.int32)
+    mts = np.stack([inputs.double_couple(0.3, 0.7, 1.1, 1000.0), inputs.explosive(700.0), inputs.clvd(400.0)])
+    s = B.Solver(vp, vs, rho, (10.0, 10.0, 10.0), dt, pml=6, rec=rec)
+    s.set_sources(np.arange(4, dtype=np.int32), pos, mts, np.repeat(w[None], 3, 0))
+    singles = s.run(nt)
+    src = np.array([0, 1, 2, 1], np.int32)
+    amp = np.array([1.5, 0.5, 2.0, 1.25])
+    lag = np.array([3, 11, 0, 25])
+    got = B.seis_combine(singles, [0.0] * 4, src, amp, lag * dt, nt, dt, dt).cpu().numpy()
+    wav = np.stack([np.concatenate([np.zeros(l), w[:nt - l]]) for l in lag])
+    s.set_sources([0, 4], pos[src], amp[:, None] * mts[src], wav)
+    joint = s.run(nt).cpu().numpy()[0]
+    for c in range(4):
+        e = np.linalg.norm(got[c] - joint[c]) / np.linalg.norm(joint[c])
+        assert e < 1e-5, (c, e)

@@ -1,0 +1,123 @@
+"""GPU parity of the spectral neural operator surrogate against the FP64 oracle
+(oracle/osno.py), through the C ABI.
+
+The GPU contracts in BF16 (8 mantissa bits) with FP32 accumulation, so the bar
+is BF16-level: relative L2 <= 2e-2 per output and per gradient block.
+"""
+import numpy as np
+import pytest
+
+from oracle import osno
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def B(gpu):
+    from paper_1705_04874_amd import binding
+    return binding
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def make(B, d, theta):
+    return B.Surrogate(d.O // 4, d.T, d.C, d.K, d.L, d.H, np.zeros(9), np.ones(9), theta.astype(np.float32))
+
+
+SMALL = osno.Dims(C=16, T=64, K=4, L=2, H=32, O=8)
+FULL = osno.Dims(C=64, T=1024, K=16, L=4, H=128, O=256)
+
+
+@pytest.mark.parametrize("d", [SMALL, FULL], ids=["small", "full"])
+def test_forward_matches_oracle(B, d):
+    import torch
+    rng = np.random.default_rng(0)
+    theta = osno.init_params(d, 1) + 0.02 * rng.standard_normal(osno.n_params(d))
+    theta = theta.astype(np.float32).astype(np.float64)
+    X = rng.uniform(-1, 1, (3, 9))
+    ref = osno.forward(theta, X, d)
+    s = make(B, d, theta)
+    got = s.forward(torch.tensor(X, dtype=torch.float32, device="cuda")).cpu().numpy().reshape(ref.shape)
+    e = rel(got, ref)
+    say("forward", d, e)
+    assert e < 2e-2
+
+
+def test_gradient_matches_oracle(B):
+    import torch
+    d = SMALL
+    rng = np.random.default_rng(1)
+    theta = osno.init_params(d, 2) + 0.05 * rng.standard_normal(osno.n_params(d))
+    theta = theta.astype(np.float32).astype(np.float64)
+    X = rng.uniform(-1, 1, (4, 9))
+    Yt = rng.standard_normal((4, d.O, d.T))
+    ref = osno.grad(theta, X, Yt, d)
+    s = make(B, d, theta)
+    g, loss = s.gradient(torch.tensor(X, dtype=torch.float32, device="cuda"),
+                         torch.tensor(Yt, dtype=torch.float32, device="cuda"))
+    g = g.cpu().numpy()
+    assert abs(loss - osno.loss(theta, X, Yt, d)) < 2e-2 * osno.loss(theta, X, Yt, d)
+    o = 0
+    for name, sh in osno.param_shapes(d):
+        n = int(np.prod(sh))
+        e = rel(g[o:o + n], ref[o:o + n])
+        say(f"  grad {name}: rel-L2 {e:.2e}")
+        assert e < 2e-2, name
+        o += n
+
+
+def test_training_reduces_loss_on_a_teacher(B):
+    """Targets from a fixed random network of the same family: training the
+    student must cut the loss by a large factor."""
+    import torch
+    d = SMALL
+    rng = np.random.default_rng(3)
+    teacher = osno.init_params(d, 7) + 0.1 * rng.standard_normal(osno.n_params(d))
+    X = rng.uniform(-1, 1, (128, 9))
+    Y = osno.forward(teacher, X, d).reshape(128, 4, d.O // 4, d.T)
+    s = make(B, d, osno.init_params(d, 8))
+    curve = s.train(torch.tensor(X, dtype=torch.float32, device="cuda"),
+                    torch.tensor(Y, dtype=torch.float32, device="cuda"), epochs=60, batch=16, lr=3e-3, seed=1,
+                    n_calib=32)
+    say("loss curve", curve[0], curve[-1])
+    assert np.isfinite(curve).all()
+    assert curve[-1] < 0.2 * curve[0]
+    Yp, est = s.predict(torch.tensor(X[96:], dtype=torch.float32, device="cuda"))
+    est = est.cpu().numpy()
+    assert np.isfinite(est).all() and (est > 0).all()
+
+
+def test_predict_or_solve_fallback(B):
+    """tol = 0 sends every sample to the solver (equal to direct solver runs,
+    decimated); tol = inf keeps every surrogate prediction."""
+    import torch
+    from paper_1705_04874_amd import inputs
+    shape = (32, 24, 40)
+    vp = np.full(shape, 2800.0)
+    vs = np.full(shape, 1600.0)
+    rho = np.full(shape, 2200.0)
+    vp[:5], vs[:5], rho[:5] = 1500.0, 0.0, 1000.0
+    dt, T, decim = 0.8e-3, 64, 2
+    rec = inputs.receiver_line_x(12, 28, 12, 5)             # 16 receivers
+    solver = B.Solver(vp, vs, rho, (10.0, 10.0, 10.0), dt, pml=6, rec=rec)
+    d = osno.Dims(C=16, T=T, K=4, L=2, H=32, O=4 * rec.shape[0])
+    s = make(B, d, osno.init_params(d, 4))
+    ijk = np.array([[20, 12, 18], [14, 9, 22], [26, 15, 16]], np.int32)
+    m6 = np.stack([inputs.double_couple(0.3, 0.7, 1.1, 1000.0), inputs.explosive(700.0), inputs.clvd(400.0)])
+    X = torch.tensor(np.concatenate([ijk, m6 / 1000.0], axis=1), dtype=torch.float32, device="cuda")
+    w = inputs.ricker(30.0, dt, decim * T)
+    Y0, est0, used0 = s.predict_or_solve(solver, X, ijk, m6, w, decim, tol=0.0, max_batch=2)
+    assert used0.all()
+    solver.set_sources(np.arange(4, dtype=np.int32), ijk, m6, np.repeat(w[None], 3, 0))
+    direct = solver.run(decim * T).cpu().numpy()[..., ::decim]
+    np.testing.assert_array_equal(Y0.cpu().numpy(), direct)
+    Y1, est1, used1 = s.predict_or_solve(solver, X, ijk, m6, w, decim, tol=float("inf"))
+    assert not used1.any()
+    Yp, _ = s.predict(X)
+    np.testing.assert_array_equal(Y1.cpu().numpy(), Yp.cpu().numpy())

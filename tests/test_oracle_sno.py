@@ -1,0 +1,69 @@
+"""Pins of the surrogate oracle (oracle/osno.py) against library routines and calculus.
+
+ * the truncated DFT and its inverse equal numpy's FFT with truncation and
+   zero padding (a different implementation of the same definition);
+ * the hand-written gradient equals central finite differences of the loss
+   for every parameter block (FP64);
+ * gelu's derivative equals finite differences;
+ * Adam's first step moves every weight by lr * sign(g) (bias correction).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import osno
+
+D = osno.Dims(n_in=3, C=4, T=32, K=5, L=2, H=6, O=5)
+
+
+def test_truncated_dft_matches_numpy_fft():
+    d = osno.Dims(T=64, K=7)
+    F, G = osno.dft_bases(d)
+    rng = np.random.default_rng(0)
+    v = rng.standard_normal((3, d.T))
+    vh = v @ F
+    ref = np.fft.rfft(v, axis=1)[:, :d.K]
+    assert np.abs(vh[:, :d.K] - ref.real).max() < 1e-12
+    assert np.abs(vh[:, d.K:] - ref.imag).max() < 1e-12
+    spec = np.zeros((3, d.T // 2 + 1), complex)
+    spec[:, :d.K] = ref
+    back = np.fft.irfft(spec, n=d.T, axis=1)
+    assert np.abs(vh @ G - back).max() < 1e-12
+
+
+def test_gelu_derivative():
+    x = np.linspace(-4, 4, 101)
+    h = 1e-6
+    fd = (osno.gelu(x + h) - osno.gelu(x - h)) / (2 * h)
+    assert np.abs(fd - osno.gelu_grad(x)).max() < 1e-8
+
+
+def test_gradient_matches_finite_differences():
+    rng = np.random.default_rng(1)
+    theta = osno.init_params(D, 3)
+    theta += 0.05 * rng.standard_normal(theta.size)        # break the zero biases / positive R
+    src = rng.standard_normal((2, D.n_in))
+    y = rng.standard_normal((2, D.O, D.T))
+    g = osno.grad(theta, src, y, D)
+    o = 0
+    h = 1e-6
+    for name, sh in osno.param_shapes(D):
+        n = int(np.prod(sh))
+        idx = o + rng.choice(n, size=min(n, 6), replace=False)
+        for i in idx:
+            tp = theta.copy()
+            tm = theta.copy()
+            tp[i] += h
+            tm[i] -= h
+            fd = (osno.loss(tp, src, y, D) - osno.loss(tm, src, y, D)) / (2 * h)
+            assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (name, i, fd, g[i])
+        o += n
+    assert o == theta.size
+
+
+def test_adam_first_step():
+    theta = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -1e-3, 2.0])
+    t, m, v = osno.adam(theta, g, np.zeros(3), np.zeros(3), 1, 0.01)
+    assert np.allclose(t, theta - 0.01 * np.sign(g), atol=1e-7)
