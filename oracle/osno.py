@@ -160,22 +160,6 @@ def grad(theta, src, y, d: Dims):
     return flatten(g, d)
 
 
-def init_params(d: Dims, seed: int):
-    """Seeded initial weights: uniform(+-1/sqrt(fan_in)) for the pointwise maps,
-    uniform(0, 1) / (C C) for the spectral weights."""
-    rng = np.random.default_rng(seed)
-    p = {}
-    for name, sh in param_shapes(d):
-        if name.startswith(("Rr", "Ri")):
-            p[name] = rng.uniform(0.0, 1.0, sh) / (d.C * d.C)
-        elif len(sh) == 2:
-            lim = 1.0 / math.sqrt(sh[1])
-            p[name] = rng.uniform(-lim, lim, sh)
-        else:
-            p[name] = np.zeros(sh)
-    return flatten(p, d)
-
-
 def adam(theta, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
     """One Adam step (step counts from 1); returns the new (theta, m, v)."""
     m = b1 * m + (1 - b1) * g

@@ -263,37 +263,37 @@ class Workload:
 DV_UNIT_MOMENT = 1000.0  # N*m: 1 Pa over a 10 m cube cell
 
 
-def c0_workload() -> Workload:
+def two_layer_workload() -> Workload:
     """Two layers, 32^3, dx 10 m, dt 1 ms, 300 steps, 8-cell PML, explosive at (16,16,24),
     30 Hz Ricker, 16 receivers on the seabed line x = 8..23, y = 16, z = 8."""
     m = two_layer(32, 8)
     nt = 300
     dt = 1e-3
     rec = receiver_line_x(8, 24, 16, 8)
-    return Workload("c0_two_layer_32", m, (10.0, 10.0, 10.0), dt, nt, 8, 2.0, 1, 0.0, rec,
+    return Workload("two_layer_32x32x32", m, (10.0, 10.0, 10.0), dt, nt, 8, 2.0, 1, 0.0, rec,
                     np.array([[16, 16, 24]], np.int32), explosive(DV_UNIT_MOMENT)[None, :],
                     np.array([0, 1], np.int32), ricker(30.0, dt, nt)[None, :])
 
 
-def c1_model(seed=0) -> Model:
+def layered128_model(seed=0) -> Model:
     return layered(128, 128, 128, water_cells=20, seed=seed)
 
 
-def c1_workload(seed_model=0, seed_src=1, nt=2000) -> Workload:
+def layered128_workload(seed_model=0, seed_src=1, nt=2000) -> Workload:
     """128^3, dx 10 m, dt 0.8 ms, 16-cell PML, water over the top 20 cells, 6 layers,
     one random DC at (64, 64, z ~ U{24..104}), 25 Hz Ricker, 64x64 seabed receivers."""
-    m = c1_model(seed_model)
+    m = layered128_model(seed_model)
     rng = np.random.default_rng(seed_src)
     z = int(rng.integers(24, 105))
     mt = random_dc(rng, DV_UNIT_MOMENT)
     dt = 0.8e-3
     rec = receiver_block(32, 96, 32, 96, 20)
-    return Workload("c1_layered_128", m, (10.0, 10.0, 10.0), dt, nt, 16, 2.0, 1, 0.0, rec,
+    return Workload("layered_128x128x128", m, (10.0, 10.0, 10.0), dt, nt, 16, 2.0, 1, 0.0, rec,
                     np.array([[64, 64, z]], np.int32), mt[None, :], np.array([0, 1], np.int32),
                     ricker(25.0, dt, nt)[None, :], meta={"src_z": z})
 
 
-def c2_workload(seed_model=0, seed_src=1, nt=4000) -> Workload:
+def layered384_workload(seed_model=0, seed_src=1, nt=4000) -> Workload:
     """384x384x256, same family scaled in z (water 40 cells, 6 x 36 layers), 20-cell PML,
     one random DC laterally centred, 128x128 seabed receivers at z = 40."""
     m = layered(384, 384, 256, water_cells=40, seed=seed_model)
@@ -302,16 +302,16 @@ def c2_workload(seed_model=0, seed_src=1, nt=4000) -> Workload:
     mt = random_dc(rng, DV_UNIT_MOMENT)
     dt = 0.8e-3
     rec = receiver_block(128, 256, 128, 256, 40)
-    return Workload("c2_layered_384x384x256", m, (10.0, 10.0, 10.0), dt, nt, 20, 2.0, 1, 0.0, rec,
+    return Workload("layered_384x384x256", m, (10.0, 10.0, 10.0), dt, nt, 20, 2.0, 1, 0.0, rec,
                     np.array([[192, 192, z]], np.int32), mt[None, :], np.array([0, 1], np.int32),
                     ricker(25.0, dt, nt)[None, :], meta={"src_z": z})
 
 
-def c3_shots(n_shots=64, seed_model=0, seed_src=2, nt=2000) -> Workload:
+def layered128_shots(n_shots=64, seed_model=0, seed_src=2, nt=2000) -> Workload:
     """n_shots single-source shots on the 128^3 layered model: positions uniform in the
     500 m cube centred at (64, 64, 70) (x, y in [39, 89), z in [45, 95)), tensors
     0.8 DC + 0.2 ISO, 25 Hz Ricker, 64x64 seabed receivers."""
-    m = c1_model(seed_model)
+    m = layered128_model(seed_model)
     rng = np.random.default_rng(seed_src)
     ijk = np.stack([rng.integers(39, 89, n_shots), rng.integers(39, 89, n_shots),
                     rng.integers(45, 95, n_shots)], axis=1).astype(np.int32)
@@ -319,7 +319,7 @@ def c3_shots(n_shots=64, seed_model=0, seed_src=2, nt=2000) -> Workload:
     dt = 0.8e-3
     rec = receiver_block(32, 96, 32, 96, 20)
     w = np.repeat(ricker(25.0, dt, nt)[None, :], n_shots, axis=0)
-    return Workload(f"c3_shots{n_shots}_layered_128", m, (10.0, 10.0, 10.0), dt, nt, 16, 2.0, 1,
+    return Workload(f"layered_128x128x128_shots{n_shots}", m, (10.0, 10.0, 10.0), dt, nt, 16, 2.0, 1,
                     0.0, rec, ijk, mts, np.arange(n_shots + 1, dtype=np.int32), w)
 
 
@@ -346,3 +346,32 @@ def ragged_models(n_models=24, seed=5, nt=2000):
                             rec, np.array([[nx // 2, ny // 2, zs]], np.int32), mt[None, :],
                             np.array([0, 1], np.int32), ricker(25.0, dt, nt)[None, :]))
     return out
+
+
+# ----------------------------------------------------------------------------
+# surrogate initial weights (random numbers the training starts from)
+# ----------------------------------------------------------------------------
+def sno_param_shapes(C: int, K: int, L: int, H: int, O: int, n_in: int = 9):
+    """(name, shape) of the surrogate's flat parameter vector, in the order of
+    include/sno.h: P, pb, {W_l, b_l, Rr_l, Ri_l}, Q1, q1b, Q2, q2b."""
+    s = [("P", (C, n_in + 1)), ("pb", (C,))]
+    for l in range(L):
+        s += [(f"W{l}", (C, C)), (f"b{l}", (C,)), (f"Rr{l}", (K, C, C)), (f"Ri{l}", (K, C, C))]
+    s += [("Q1", (H, C)), ("q1b", (H,)), ("Q2", (O, H)), ("q2b", (O,))]
+    return s
+
+
+def sno_init_params(C: int, K: int, L: int, H: int, O: int, seed: int, n_in: int = 9) -> np.ndarray:
+    """Seeded initial weights (float64 flat vector): uniform(+-1/sqrt(fan_in)) for
+    the pointwise maps, uniform(0, 1) / C^2 for the spectral weights, zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, sh in sno_param_shapes(C, K, L, H, O, n_in):
+        if name.startswith(("Rr", "Ri")):
+            parts.append(rng.uniform(0.0, 1.0, sh) / (C * C))
+        elif len(sh) == 2:
+            lim = 1.0 / np.sqrt(sh[1])
+            parts.append(rng.uniform(-lim, lim, sh))
+        else:
+            parts.append(np.zeros(sh))
+    return np.concatenate([p.ravel() for p in parts])

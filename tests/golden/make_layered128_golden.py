@@ -1,8 +1,8 @@
-"""Write tests/golden/c1_oracle_traces.npz: FP64 oracle traces of the 128^3 layered
+"""Write tests/golden/layered128_oracle_traces.npz: FP64 oracle traces of the 128^3 layered
 workload (2000 steps, one double-couple source) at a fixed sample of receivers.
 
 Calls only the oracle and the seeded input generators. Run from the repo root:
-    python tests/golden/make_c1_golden.py [--nt 2000]
+    python tests/golden/make_layered128_golden.py [--nt 2000]
 """
 import argparse
 import hashlib
@@ -32,9 +32,9 @@ def model_digest(w):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--nt", type=int, default=2000)
-    ap.add_argument("--out", default=os.path.join(ROOT, "tests", "golden", "c1_oracle_traces.npz"))
+    ap.add_argument("--out", default=os.path.join(ROOT, "tests", "golden", "layered128_oracle_traces.npz"))
     a = ap.parse_args()
-    w = inputs.c1_workload(nt=a.nt)
+    w = inputs.layered128_workload(nt=a.nt)
     s = oracle.Solver.from_workload(w, rec=w.rec[SAMPLE])
     s.set_sources(w.src_ijk, w.src_m, w.wavelet)
     t = time.time()

@@ -24,7 +24,7 @@ from paper_1705_04874_amd import inputs
 pytestmark = pytest.mark.gpu
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-GOLD = os.path.join(ROOT, "tests", "golden", "c1_oracle_traces.npz")
+GOLD = os.path.join(ROOT, "tests", "golden", "layered128_oracle_traces.npz")
 
 
 def say(*a):
@@ -37,15 +37,15 @@ def B(gpu):
     return binding
 
 
-def test_c1_full_against_oracle_golden(B):
+def test_layered128_full_against_oracle_golden(B):
     if not os.path.exists(GOLD):
-        pytest.fail("tests/golden/c1_oracle_traces.npz missing (tests/golden/make_c1_golden.py writes it)")
+        pytest.fail("tests/golden/layered128_oracle_traces.npz missing (tests/golden/make_layered128_golden.py writes it)")
     g = np.load(GOLD, allow_pickle=False)
     nt = int(g["nt"])
-    w = inputs.c1_workload(nt=nt)
-    from tests.golden.make_c1_golden import model_digest
+    w = inputs.layered128_workload(nt=nt)
+    from tests.golden.make_layered128_golden import model_digest
     assert str(g["digest"]) == model_digest(w), "workload generator changed since the golden was written"
-    say("c1 full", w.model.shape, nt)
+    say("layered128 full", w.model.shape, nt)
     s = B.Solver.from_workload(w)
     s.set_workload_sources(w)
     tr = s.run(nt).cpu().numpy()[0][:, g["receivers"]].astype(np.float64)
@@ -79,10 +79,10 @@ def test_derivatives_at_large_lengths(B, shape):
 
 
 @pytest.fixture(scope="module")
-def c2_runs(B):
+def layered384_runs(B):
     nt = 1000
-    w = inputs.c2_workload(nt=nt)
-    say("c2", w.model.shape, nt)
+    w = inputs.layered384_workload(nt=nt)
+    say("layered384", w.model.shape, nt)
     s = B.Solver.from_workload(w)
     out = {}
     s.set_workload_sources(w)
@@ -98,28 +98,28 @@ def c2_runs(B):
     return out
 
 
-def test_c2_traces_are_finite_and_nonzero(c2_runs):
-    b = c2_runs["base"]
+def test_layered384_traces_are_finite_and_nonzero(layered384_runs):
+    b = layered384_runs["base"]
     assert np.isfinite(b).all()
     for c in range(4):
         assert np.abs(b[c]).max() > 0
 
 
-def test_c2_amplitude_scaling_is_exact(c2_runs):
-    np.testing.assert_array_equal(c2_runs["double"], 2.0 * c2_runs["base"])
+def test_layered384_amplitude_scaling_is_exact(layered384_runs):
+    np.testing.assert_array_equal(layered384_runs["double"], 2.0 * layered384_runs["base"])
 
 
-def test_c2_time_shift_is_exact(c2_runs):
-    lag = c2_runs["lag_n"]
-    a, b = c2_runs["base"], c2_runs["lag"]
+def test_layered384_time_shift_is_exact(layered384_runs):
+    lag = layered384_runs["lag_n"]
+    a, b = layered384_runs["base"], layered384_runs["lag"]
     assert np.abs(b[..., :lag]).max() == 0.0
     np.testing.assert_array_equal(b[..., lag:], a[..., :-lag])
 
 
-def test_c3_batch_of_64_shots_matches_single_shots(B):
+def test_batch_of_64_shots_matches_single_shots(B):
     nt = 400
-    w = inputs.c3_shots(64, nt=nt)
-    say("c3 batch", w.n_shots, nt)
+    w = inputs.layered128_shots(64, nt=nt)
+    say("batch", w.n_shots, nt)
     s = B.Solver.from_workload(w)
     s.set_workload_sources(w)
     batch = s.run(nt).cpu().numpy()

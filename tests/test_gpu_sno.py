@@ -8,8 +8,13 @@ import numpy as np
 import pytest
 
 from oracle import osno
+from paper_1705_04874_amd import inputs
 
 pytestmark = pytest.mark.gpu
+
+
+def init(d, seed):
+    return inputs.sno_init_params(d.C, d.K, d.L, d.H, d.O, seed, d.n_in)
 
 
 def say(*a):
@@ -38,7 +43,7 @@ FULL = osno.Dims(C=64, T=1024, K=16, L=4, H=128, O=256)
 def test_forward_matches_oracle(B, d):
     import torch
     rng = np.random.default_rng(0)
-    theta = osno.init_params(d, 1) + 0.02 * rng.standard_normal(osno.n_params(d))
+    theta = init(d, 1) + 0.02 * rng.standard_normal(osno.n_params(d))
     theta = theta.astype(np.float32).astype(np.float64)
     X = rng.uniform(-1, 1, (3, 9))
     ref = osno.forward(theta, X, d)
@@ -53,7 +58,7 @@ def test_gradient_matches_oracle(B):
     import torch
     d = SMALL
     rng = np.random.default_rng(1)
-    theta = osno.init_params(d, 2) + 0.05 * rng.standard_normal(osno.n_params(d))
+    theta = init(d, 2) + 0.05 * rng.standard_normal(osno.n_params(d))
     theta = theta.astype(np.float32).astype(np.float64)
     X = rng.uniform(-1, 1, (4, 9))
     Yt = rng.standard_normal((4, d.O, d.T))
@@ -78,10 +83,10 @@ def test_training_reduces_loss_on_a_teacher(B):
     import torch
     d = SMALL
     rng = np.random.default_rng(3)
-    teacher = osno.init_params(d, 7) + 0.1 * rng.standard_normal(osno.n_params(d))
+    teacher = init(d, 7) + 0.1 * rng.standard_normal(osno.n_params(d))
     X = rng.uniform(-1, 1, (128, 9))
     Y = osno.forward(teacher, X, d).reshape(128, 4, d.O // 4, d.T)
-    s = make(B, d, osno.init_params(d, 8))
+    s = make(B, d, init(d, 8))
     curve = s.train(torch.tensor(X, dtype=torch.float32, device="cuda"),
                     torch.tensor(Y, dtype=torch.float32, device="cuda"), epochs=60, batch=16, lr=3e-3, seed=1,
                     n_calib=32)
@@ -107,7 +112,7 @@ def test_predict_or_solve_fallback(B):
     rec = inputs.receiver_line_x(12, 28, 12, 5)             # 16 receivers
     solver = B.Solver(vp, vs, rho, (10.0, 10.0, 10.0), dt, pml=6, rec=rec)
     d = osno.Dims(C=16, T=T, K=4, L=2, H=32, O=4 * rec.shape[0])
-    s = make(B, d, osno.init_params(d, 4))
+    s = make(B, d, init(d, 4))
     ijk = np.array([[20, 12, 18], [14, 9, 22], [26, 15, 16]], np.int32)
     m6 = np.stack([inputs.double_couple(0.3, 0.7, 1.1, 1000.0), inputs.explosive(700.0), inputs.clvd(400.0)])
     X = torch.tensor(np.concatenate([ijk, m6 / 1000.0], axis=1), dtype=torch.float32, device="cuda")

@@ -75,9 +75,9 @@ def run_both(B, w, nt, **over):
     return g, refs
 
 
-def test_c0_two_layer_full(B):
-    w = inputs.c0_workload()
-    say("c0", w.model.shape, w.nt)
+def test_two_layer_32_full(B):
+    w = inputs.two_layer_workload()
+    say("two layer", w.model.shape, w.nt)
     g, refs = run_both(B, w, w.nt)
     for c in range(4):
         e = rel(g[0, c], refs[0][c])

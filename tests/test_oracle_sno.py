@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 from oracle import osno
+from paper_1705_04874_amd import inputs
 
 D = osno.Dims(n_in=3, C=4, T=32, K=5, L=2, H=6, O=5)
 
@@ -41,7 +42,7 @@ def test_gelu_derivative():
 
 def test_gradient_matches_finite_differences():
     rng = np.random.default_rng(1)
-    theta = osno.init_params(D, 3)
+    theta = inputs.sno_init_params(D.C, D.K, D.L, D.H, D.O, 3, D.n_in)
     theta += 0.05 * rng.standard_normal(theta.size)        # break the zero biases / positive R
     src = rng.standard_normal((2, D.n_in))
     y = rng.standard_normal((2, D.O, D.T))
