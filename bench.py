@@ -78,7 +78,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle sample time")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="run a 1 GiB device copy first (reference kernel for HBM counters)")
+                    help="run 1 GiB device copies first (reference kernels for HBM counters)")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
     ap.add_argument("--profile-steps", type=int, default=1, help="shots in the per-kernel event pass")
     args = ap.parse_args()
@@ -109,6 +109,8 @@ def main():
         a.fill_(1.0)
         torch.cuda.synchronize()
         b.copy_(a)
+        torch.cuda.synchronize()
+        torch.mul(a, 1.0, out=b)          # plain elementwise copy kernel: 1 GiB read, 1 GiB written
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_read": a.numel() * 4,
                           "copy_calibration_bytes_written": b.numel() * 4}), file=sys.stderr, flush=True)
@@ -230,6 +232,7 @@ def main():
         "parity_rel_l2": parity,
         "kernels": kernels,
         "device_bytes": s.device_bytes,
+        "tuning": s.tuning(),
     }
     print(json.dumps(out), flush=True)
     s.close()

@@ -148,6 +148,33 @@ int pstd3d_profile(pstd3d_ctx *c, int enable);
  * last pstd3d_profile(c, 1). */
 int pstd3d_profile_read(const pstd3d_ctx *c, int kind, double *total_ms, long *launches);
 
+/* Autotuner.  Four launch-shape knobs of a time step:
+ *   PSTD_TUNE_Y, PSTD_TUNE_Z  the y and z transforms work on tiles of this
+ *        many adjacent pencils (8, 16, 32 or 64, where the tile fits the LDS
+ *        and register budget of its length);
+ *   PSTD_TUNE_VEL, PSTD_TUNE_STR  threads per block of the velocity and the
+ *        stress update kernels (x transforms fused with the split-PML
+ *        updates): 128, 256 or 512, at most the cells of a block.
+ * The first pstd3d_set_sources of a context times every built value of every
+ * knob on the context's own state (HIP events, one warm-up and three
+ * launches each) and keeps the fastest; the state is cleared afterwards.
+ * pstd3d_set_tuning forces values (host int[PSTD_TUNE_COUNT]; a value must be
+ * built, PSTD_EUNSUPPORTED otherwise); forced values take effect at once, and
+ * a 0 entry is tuned again at the next pstd3d_set_sources.  The traces agree
+ * across values to FP32 rounding (the same butterflies and updates, possibly
+ * contracted into fused multiply-adds differently). */
+#define PSTD_TUNE_Y 0
+#define PSTD_TUNE_Z 1
+#define PSTD_TUNE_VEL 2
+#define PSTD_TUNE_STR 3
+#define PSTD_TUNE_COUNT 4
+int pstd3d_set_tuning(pstd3d_ctx *c, const int value[PSTD_TUNE_COUNT]);
+/* The chosen value of `knob` (may be NULL), and its built values (host,
+ * up to max entries) with the microseconds per launch measured by the last
+ * tuning (0 where not measured).  Returns the number of built values or a
+ * negative error code. */
+int pstd3d_get_tuning(const pstd3d_ctx *c, int knob, int *chosen, int *values, float *us, int max);
+
 /* Bytes of device memory held by the context. */
 long pstd3d_device_bytes(const pstd3d_ctx *c);
 void pstd3d_destroy(pstd3d_ctx *c);

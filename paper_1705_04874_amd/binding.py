@@ -50,6 +50,9 @@ _L.pstd3d_derivs.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_vo
 _L.pstd3d_reset.argtypes = [C.c_void_p, C.c_void_p]
 _L.pstd3d_profile.argtypes = [C.c_void_p, C.c_int]
 _L.pstd3d_profile_read.argtypes = [C.c_void_p, C.c_int, _dp, C.POINTER(C.c_long)]
+_L.pstd3d_set_tuning.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
+_L.pstd3d_get_tuning.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _fp, C.c_int]
+TUNE_KNOBS = ("y_tile", "z_tile", "vel_threads", "str_threads")
 _L.pstd3d_device_bytes.argtypes = [C.c_void_p]
 _L.pstd3d_device_bytes.restype = C.c_long
 _L.pstd3d_destroy.argtypes = [C.c_void_p]
@@ -109,6 +112,30 @@ class Solver:
                   rec=w.rec)
         kw.update(over)
         return cls(w.model.vp, w.model.vs, w.model.rho, **kw)
+
+    def set_tuning(self, y_tile=0, z_tile=0, vel_threads=0, str_threads=0):
+        """Force launch-shape knobs (0: autotuned at the next set_sources)."""
+        v = (C.c_int * 4)(int(y_tile), int(z_tile), int(vel_threads), int(str_threads))
+        _check(_L.pstd3d_set_tuning(self._h, v), "pstd3d_set_tuning")
+
+    def tuning_values(self):
+        """The chosen value of every knob, as keyword arguments of set_tuning."""
+        t = self.tuning()
+        return {k: t[k] for k in TUNE_KNOBS}
+
+    def tuning(self):
+        """{knob: chosen value} and {knob + '_candidates': {value: measured us per launch}}."""
+        out = {}
+        for k, name in enumerate(TUNE_KNOBS):
+            ch = C.c_int()
+            vals = (C.c_int * 8)()
+            us = (C.c_float * 8)()
+            n = _L.pstd3d_get_tuning(self._h, k, C.byref(ch), vals, us, 8)
+            if n < 0:
+                _check(n, "pstd3d_get_tuning")
+            out[name] = ch.value
+            out[name + "_candidates"] = {int(vals[i]): round(float(us[i]), 2) for i in range(n)}
+        return out
 
     def set_sources(self, shot_ofs, src_ijk, m6, wavelet):
         so = _i32(shot_ofs)

@@ -36,13 +36,25 @@ int fail(int code, const std::string& msg)
 constexpr int NT = 256;
 
 // ---------------------------------------------------------------------------
-// per-length kernel launchers
+// per-length kernel launchers.  Tuning knobs (the autotuner picks one value of
+// each per context): the column-tile width of the y and z kernels and the
+// threads per block of the two update kernels.
+using VelFn = void (*)(dim3, hipStream_t, Geo, Mat, Pml, const float2*, float*, float2*, Rec, float*, const int*,
+                       int*, int, int);
+using StrFn = void (*)(dim3, hipStream_t, Geo, Mat, Pml, const float2*, float*, float2*, Rec, Inj, float*,
+                       const int*, int, int);
 struct XFns {
-    void (*vel)(dim3, hipStream_t, Geo, Mat, Pml, const float2*, float*, float2*, Rec, float*, const int*, int*, int, int);
-    void (*str)(dim3, hipStream_t, Geo, Mat, Pml, const float2*, float*, float2*, Rec, Inj, float*, const int*, int, int);
     void (*xfwd)(dim3, hipStream_t, Geo, const float2*, const float*, long, float2*, long, SumDesc);
     void (*xinv)(dim3, hipStream_t, Geo, const float2*, const float2*, float*);
     int rows;
+};
+struct VelVar {
+    VelFn fn;
+    int nt;
+};
+struct StrVar {
+    StrFn fn;
+    int nt;
 };
 struct YFns {
     void (*fwd)(dim3, hipStream_t, Geo, const float2*, float2*, int, int);
@@ -53,19 +65,24 @@ struct ZFns {
     void (*op)(dim3, hipStream_t, Geo, const float2*, float2*, int, const ZDesc*, int);
     int tile;
 };
+constexpr int MAX_VARIANTS = 4;
+constexpr int TILE_CANDIDATES[MAX_VARIANTS] = {8, 16, 32, 64};
+
+// threads per block of the update kernels of length N: 128, 256 and 512,
+// none above the cells of a block
+constexpr int nt_candidate(int n, int i)
+{
+    const int cells = rows_for(n) * n;
+    const int c[3] = {128, 256, 512};
+    const int v = c[i];
+    if (v > cells || v % 64 || v > 1024) return 0;
+    for (int j = 0; j < i; ++j)
+        if (c[j] == v) return 0;
+    return v;
+}
 
 template <int N>
 struct Launch {
-    static void vel(dim3 gr, hipStream_t st, Geo g, Mat m, Pml p, const float2* tw, float* f, float2* s, Rec r,
-                    float* tr, const int* sp, int* sn, int n0, int ldt)
-    {
-        hipLaunchKernelGGL((k_vel<N, NT>), gr, dim3(NT), 0, st, g, m, p, tw, f, s, r, tr, sp, sn, n0, ldt);
-    }
-    static void str(dim3 gr, hipStream_t st, Geo g, Mat m, Pml p, const float2* tw, float* f, float2* s, Rec r,
-                    Inj in, float* tr, const int* sp, int n0, int ldt)
-    {
-        hipLaunchKernelGGL((k_str<N, NT>), gr, dim3(NT), 0, st, g, m, p, tw, f, s, r, in, tr, sp, n0, ldt);
-    }
     static void xfwd(dim3 gr, hipStream_t st, Geo g, const float2* tw, const float* in, long is, float2* out,
                      long os, SumDesc sd)
     {
@@ -75,19 +92,63 @@ struct Launch {
     {
         hipLaunchKernelGGL((k_xinv<N, NT>), gr, dim3(NT), 0, st, g, tw, in, out);
     }
+};
+
+template <int N, int T>
+struct LaunchX {
+    static void vel(dim3 gr, hipStream_t st, Geo g, Mat m, Pml p, const float2* tw, float* f, float2* s, Rec r,
+                    float* tr, const int* sp, int* sn, int n0, int ldt)
+    {
+        hipLaunchKernelGGL((k_vel<N, T>), gr, dim3(T), 0, st, g, m, p, tw, f, s, r, tr, sp, sn, n0, ldt);
+    }
+    static void str(dim3 gr, hipStream_t st, Geo g, Mat m, Pml p, const float2* tw, float* f, float2* s, Rec r,
+                    Inj in, float* tr, const int* sp, int n0, int ldt)
+    {
+        hipLaunchKernelGGL((k_str<N, T>), gr, dim3(T), 0, st, g, m, p, tw, f, s, r, in, tr, sp, n0, ldt);
+    }
+};
+
+template <int N, int I = 0>
+void x_variants(VelVar* v, StrVar* s, int& n)
+{
+    if constexpr (I < 3) {
+        constexpr int T = nt_candidate(N, I);
+        if constexpr (T > 0) {
+            v[n] = VelVar{LaunchX<N, T>::vel, T};
+            s[n] = StrVar{LaunchX<N, T>::str, T};
+            ++n;
+        }
+        x_variants<N, I + 1>(v, s, n);
+    }
+}
+
+template <int N, int TX>
+struct LaunchYZ {
     static void yf(dim3 gr, hipStream_t st, Geo g, const float2* tw, float2* s, int f0, int nf)
     {
-        hipLaunchKernelGGL((k_y<N, NT, -1>), gr, dim3(NT), 0, st, g, tw, s, f0, nf);
+        hipLaunchKernelGGL((k_y<N, NT, -1, TX>), gr, dim3(NT), 0, st, g, tw, s, f0, nf);
     }
     static void yi(dim3 gr, hipStream_t st, Geo g, const float2* tw, float2* s, int f0, int nf)
     {
-        hipLaunchKernelGGL((k_y<N, NT, +1>), gr, dim3(NT), 0, st, g, tw, s, f0, nf);
+        hipLaunchKernelGGL((k_y<N, NT, +1, TX>), gr, dim3(NT), 0, st, g, tw, s, f0, nf);
     }
     static void z(dim3 gr, hipStream_t st, Geo g, const float2* tw, float2* s, int in0, const ZDesc* zd, int ph)
     {
-        hipLaunchKernelGGL((k_z<N, NT>), gr, dim3(NT), 0, st, g, tw, s, in0, zd, ph);
+        hipLaunchKernelGGL((k_z<N, NT, TX>), gr, dim3(NT), 0, st, g, tw, s, in0, zd, ph);
     }
 };
+
+// the variants of length N: y tiles and z tiles (counts returned)
+template <int N, int I = 0>
+void yz_variants(YFns* y, int& ny, ZFns* z, int& nz)
+{
+    if constexpr (I < MAX_VARIANTS) {
+        constexpr int TX = TILE_CANDIDATES[I];
+        if constexpr (y_tile_built(N, TX)) y[ny++] = YFns{LaunchYZ<N, TX>::yf, LaunchYZ<N, TX>::yi, TX};
+        if constexpr (z_tile_built(N, TX)) z[nz++] = ZFns{LaunchYZ<N, TX>::z, TX};
+        yz_variants<N, I + 1>(y, ny, z, nz);
+    }
+}
 
 // Grid lengths the library is built for (all factor into 2, 3 and 5).
 #define PSTD_LENGTHS(X)                                                                          \
@@ -95,46 +156,69 @@ struct Launch {
     X(128) X(144) X(150) X(160) X(180) X(192) X(200) X(240) X(256) X(288) X(300) X(320) X(360)  \
     X(384) X(400) X(480) X(512)
 
-bool x_fns(int n, XFns* f)
+bool x_fns(int n, XFns* f, VelVar* vv = nullptr, StrVar* sv = nullptr, int* nv = nullptr)
 {
+    VelVar v[3];
+    StrVar t[3];
+    int k = 0;
     switch (n) {
-#define CASE(N)                                                                                        \
-    case N:                                                                                            \
-        *f = XFns{Launch<N>::vel, Launch<N>::str, Launch<N>::xfwd, Launch<N>::xinv, rows_for(N)};      \
-        return true;
+#define CASE(N)                                                              \
+    case N:                                                                  \
+        *f = XFns{Launch<N>::xfwd, Launch<N>::xinv, rows_for(N)};            \
+        x_variants<N>(v, t, k);                                              \
+        break;
         PSTD_LENGTHS(CASE)
 #undef CASE
     default:
         return false;
     }
+    if (nv) {
+        *nv = k;
+        for (int i = 0; i < k; ++i) {
+            vv[i] = v[i];
+            sv[i] = t[i];
+        }
+    }
+    return true;
 }
 
-bool y_fns(int n, YFns* f)
+// all y variants of length n (returns the count; 0: length not built)
+int y_variants(int n, YFns* f)
 {
+    YFns y[MAX_VARIANTS];
+    ZFns z[MAX_VARIANTS];
+    int ny = 0, nz = 0;
     switch (n) {
-#define CASE(N)                                              \
-    case N:                                                  \
-        *f = YFns{Launch<N>::yf, Launch<N>::yi, tile_for(N)}; \
-        return true;
+#define CASE(N)                             \
+    case N:                                 \
+        yz_variants<N>(y, ny, z, nz);       \
+        break;
         PSTD_LENGTHS(CASE)
 #undef CASE
     default:
-        return false;
+        return 0;
     }
+    for (int i = 0; i < ny; ++i) f[i] = y[i];
+    return ny;
 }
 
-bool z_fns(int n, ZFns* f)
+int z_variants(int n, ZFns* f)
 {
+    YFns y[MAX_VARIANTS];
+    ZFns z[MAX_VARIANTS];
+    int ny = 0, nz = 0;
     switch (n) {
-#define CASE(N)                                  \
-    case N:                                      \
-        *f = ZFns{Launch<N>::z, tile_for(N)};    \
-        return true;
+#define CASE(N)                             \
+    case N:                                 \
+        yz_variants<N>(y, ny, z, nz);       \
+        break;
         PSTD_LENGTHS(CASE)
 #undef CASE
     default:
-        return false;
+        return 0;
     }
+    for (int i = 0; i < nz; ++i) f[i] = z[i];
+    return nz;
 }
 
 // V phase: stress spectra (sxx, syy, szz, sxy, sxz, syz) -> 9 derivatives,
@@ -213,8 +297,32 @@ struct pstd3d_ctx {
     int device = 0;
     Geo g{};
     XFns xf{};
-    YFns yf{};
+    // tuning knobs: built variants, forced values (0: autotune), the choice
+    VelVar velv[3]{};
+    StrVar strv[3]{};
+    YFns yv[MAX_VARIANTS]{};   // y variants of length ny
+    ZFns zv[MAX_VARIANTS]{};   // z variants of length nz
+    int nvar[PSTD_TUNE_COUNT] = {0, 0, 0, 0};
+    int force[PSTD_TUNE_COUNT] = {0, 0, 0, 0};
+    int sel[PSTD_TUNE_COUNT] = {0, 0, 0, 0};
+    bool tuned = false;
+    float tune_us[PSTD_TUNE_COUNT][MAX_VARIANTS] = {};   // measured us per launch of each variant
+    YFns yf{};                 // the chosen variants
     ZFns zf{};
+    VelVar vel{};
+    StrVar str{};
+
+    int knob_value(int k, int i) const
+    {
+        return k == PSTD_TUNE_Y ? yv[i].tile : k == PSTD_TUNE_Z ? zv[i].tile : k == PSTD_TUNE_VEL ? velv[i].nt : strv[i].nt;
+    }
+    void apply()
+    {
+        yf = yv[sel[PSTD_TUNE_Y]];
+        zf = zv[sel[PSTD_TUNE_Z]];
+        vel = velv[sel[PSTD_TUNE_VEL]];
+        str = strv[sel[PSTD_TUNE_STR]];
+    }
     // model-wide device tables
     float* mat = nullptr;      // 8 arrays of n
     float* pmlb = nullptr;     // ai[3], ah[3] back to back
@@ -511,7 +619,7 @@ void enqueue_step(pstd3d_ctx* c, hipStream_t st, float* traces, int n0, int ldt,
     c->yf.inv(dim3(tyn, g.nz, S * 9), st, g, c->twy, c->spec, 9, 9);
     c->ev_end(e, st);
     e = c->ev_begin(PSTD_K_VEL, st);
-    c->xf.vel(gx, st, g, c->M, c->P, c->twx, c->fields, c->spec, rec_of(c), traces, cur, nxt, n0, ldt);
+    c->vel.fn(gx, st, g, c->M, c->P, c->twx, c->fields, c->spec, rec_of(c), traces, cur, nxt, n0, ldt);
     c->ev_end(e, st);
     // S phase
     e = c->ev_begin(PSTD_K_YFWD_V, st);
@@ -524,14 +632,108 @@ void enqueue_step(pstd3d_ctx* c, hipStream_t st, float* traces, int n0, int ldt,
     c->yf.inv(dim3(tyn, g.nz, S * 9), st, g, c->twy, c->spec, 9, 9);
     c->ev_end(e, st);
     e = c->ev_begin(PSTD_K_STR, st);
-    c->xf.str(gx, st, g, c->M, c->P, c->twx, c->fields, c->spec, rec_of(c), inj_of(c), traces, cur, n0, ldt);
+    c->str.fn(gx, st, g, c->M, c->P, c->twx, c->fields, c->spec, rec_of(c), inj_of(c), traces, cur, n0, ldt);
     c->ev_end(e, st);
 }
 
 bool len_ok(int n)
 {
     XFns a;
-    return x_fns(n, &a);
+    YFns y[MAX_VARIANTS];
+    ZFns z[MAX_VARIANTS];
+    return x_fns(n, &a) && y_variants(n, y) > 0 && z_variants(n, z) > 0;
+}
+
+// variant used before (or without) tuning: tile 16 and 256 threads where
+// built, else the first
+int default_variant(const pstd3d_ctx* c, int k)
+{
+    const int want = (k == PSTD_TUNE_Y || k == PSTD_TUNE_Z) ? 16 : 256;
+    for (int i = 0; i < c->nvar[k]; ++i)
+        if (c->knob_value(k, i) == want) return i;
+    return 0;
+}
+
+// Autotuner.  Every built variant of every knob runs on this context's own
+// state, one warm-up and three timed launches each (HIP events): the y
+// inverse of the 9 derivative spectra, the z operator of the velocity phase,
+// and the two update kernels with no receivers and no sources; the fastest
+// of each knob is kept.  Fields and spectra are overwritten: it runs only
+// where the state is cleared afterwards.
+int autotune(pstd3d_ctx* c)
+{
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int* zero = nullptr;
+    auto cleanup = [&]() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipFree(zero);
+    };
+    const Geo& g = c->g;
+    const int S = c->n_shots;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    if (he == hipSuccess) he = hipMalloc(&zero, (size_t)S * (g.nrows + 1) * sizeof(int));
+    if (he == hipSuccess) he = hipMemset(zero, 0, (size_t)S * (g.nrows + 1) * sizeof(int));
+    if (he != hipSuccess) {
+        cleanup();
+        return fail(PSTD_EDEVICE, std::string("autotune setup: ") + hipGetErrorString(he));
+    }
+    const Rec norec{zero, c->rec_ent, 0};
+    const Inj noinj{zero, c->inj_ent, c->wav, 0};
+    auto timed = [&](auto&& launch, float* us) -> hipError_t {
+        launch();
+        hipError_t e = hipEventRecord(e0, nullptr);
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipGetLastError();
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        *us = ms * 1000.f / 3.f;
+        return e;
+    };
+    const dim3 gx((g.nrows + c->xf.rows - 1) / c->xf.rows, S);
+    for (int k = 0; k < PSTD_TUNE_COUNT; ++k) {
+        int best = -1;
+        for (int i = 0; i < c->nvar[k]; ++i) {
+            c->tune_us[k][i] = 0.f;
+            if (c->force[k] && c->knob_value(k, i) != c->force[k]) continue;
+            hipError_t e = hipSuccess;
+            if (k == PSTD_TUNE_Y) {
+                const YFns v = c->yv[i];
+                const int tyn = (g.nxm + v.tile - 1) / v.tile + g.has_nyq;
+                e = timed([&] { v.inv(dim3(tyn, g.nz, S * 9), nullptr, g, c->twy, c->spec, 9, 9); }, &c->tune_us[k][i]);
+            } else if (k == PSTD_TUNE_Z) {
+                const ZFns v = c->zv[i];
+                const int tzn = (g.nxm + v.tile - 1) / v.tile + g.has_nyq;
+                e = timed([&] { v.op(dim3(tzn, g.ny, S * 6), nullptr, g, c->twz, c->spec, 0, c->zdesc, 0); },
+                          &c->tune_us[k][i]);
+            } else if (k == PSTD_TUNE_VEL) {
+                const VelVar v = c->velv[i];
+                e = timed([&] { v.fn(gx, nullptr, g, c->M, c->P, c->twx, c->fields, c->spec, norec, nullptr,
+                                     c->stepd, c->stepd + 1, 0, 1); }, &c->tune_us[k][i]);
+            } else {
+                const StrVar v = c->strv[i];
+                e = timed([&] { v.fn(gx, nullptr, g, c->M, c->P, c->twx, c->fields, c->spec, norec, noinj, nullptr,
+                                     c->stepd, 0, 1); }, &c->tune_us[k][i]);
+            }
+            if (e != hipSuccess) {
+                cleanup();
+                return fail(PSTD_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+            }
+            if (best < 0 || c->tune_us[k][i] < c->tune_us[k][best]) best = i;
+        }
+        if (best < 0) {
+            cleanup();
+            return fail(PSTD_EUNSUPPORTED, "forced tuning value not built for this grid length");
+        }
+        c->sel[k] = best;
+    }
+    cleanup();
+    c->apply();
+    c->tuned = true;
+    return PSTD_OK;
 }
 
 // Recompute the x-transformed stress sums from the split fields.
@@ -608,9 +810,12 @@ int pstd3d_create(const pstd3d_model* m, const double d[3], double dt, const pst
     c->kspace = m->kspace ? 1 : 0;
     c->n_rec = m->n_rec;
     (void)hipGetDevice(&c->device);
-    x_fns(nx, &c->xf);
-    y_fns(ny, &c->yf);
-    z_fns(nz, &c->zf);
+    c->nvar[PSTD_TUNE_Y] = y_variants(ny, c->yv);
+    c->nvar[PSTD_TUNE_Z] = z_variants(nz, c->zv);
+    x_fns(nx, &c->xf, c->velv, c->strv, &c->nvar[PSTD_TUNE_VEL]);
+    c->nvar[PSTD_TUNE_STR] = c->nvar[PSTD_TUNE_VEL];
+    for (int k = 0; k < PSTD_TUNE_COUNT; ++k) c->sel[k] = default_variant(c, k);
+    c->apply();
     Geo& g = c->g;
     g.nx = nx;
     g.ny = ny;
@@ -705,8 +910,18 @@ int pstd3d_set_sources(pstd3d_ctx* c, int n_shots, const int32_t* shot_ofs, cons
     const size_t sbytes = (size_t)n_shots * c->g.sstride * sizeof(float2);
     HIP_TRY(hipMalloc(&c->fields, fbytes));
     HIP_TRY(hipMalloc(&c->spec, sbytes));
+    c->n_shots = n_shots;
     HIP_TRY(hipMemset(c->fields, 0, fbytes));
     HIP_TRY(hipMemset(c->spec, 0, sbytes));
+    if (!c->tuned) {
+        int trc = autotune(c);
+        if (trc) {
+            c->release_shots();
+            return trc;
+        }
+        HIP_TRY(hipMemset(c->fields, 0, fbytes));
+        HIP_TRY(hipMemset(c->spec, 0, sbytes));
+    }
     int rc = dev_upload(&c->inj_ptr, ptr);
     if (rc) return rc;
     rc = dev_upload(&c->inj_ent, ent);
@@ -963,6 +1178,43 @@ int pstd3d_derivs(pstd3d_ctx* c, int phase, const float* in_dev, float* out_dev,
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
     return PSTD_OK;
+}
+
+int pstd3d_set_tuning(pstd3d_ctx* c, const int value[PSTD_TUNE_COUNT])
+{
+    if (!c || !value) return fail(PSTD_EINVAL, "bad arguments");
+    int idx[PSTD_TUNE_COUNT];
+    bool all = true;
+    for (int k = 0; k < PSTD_TUNE_COUNT; ++k) {
+        if (value[k] < 0) return fail(PSTD_EINVAL, "negative tuning value");
+        idx[k] = -1;
+        if (value[k] == 0) {
+            all = false;
+            continue;
+        }
+        for (int i = 0; i < c->nvar[k]; ++i)
+            if (c->knob_value(k, i) == value[k]) idx[k] = i;
+        if (idx[k] < 0) return fail(PSTD_EUNSUPPORTED, "tuning value not built for this grid length");
+    }
+    for (int k = 0; k < PSTD_TUNE_COUNT; ++k) {
+        c->force[k] = value[k];
+        if (idx[k] >= 0) c->sel[k] = idx[k];
+    }
+    c->apply();
+    c->tuned = all;
+    return PSTD_OK;
+}
+
+int pstd3d_get_tuning(const pstd3d_ctx* c, int knob, int* chosen, int* values, float* us, int max)
+{
+    if (!c || knob < 0 || knob >= PSTD_TUNE_COUNT || max < 0 || (max > 0 && (!values || !us)))
+        return fail(PSTD_EINVAL, "bad arguments");
+    if (chosen) *chosen = c->knob_value(knob, c->sel[knob]);
+    for (int i = 0; i < c->nvar[knob] && i < max; ++i) {
+        values[i] = c->knob_value(knob, i);
+        us[i] = c->tune_us[knob][i];
+    }
+    return c->nvar[knob];
 }
 
 long pstd3d_device_bytes(const pstd3d_ctx* c)

@@ -83,7 +83,17 @@ struct ZDesc {
 };
 
 constexpr int rows_for(int nx) { return nx <= 32 ? 16 : nx <= 64 ? 8 : nx <= 160 ? 4 : 2; }
-constexpr int tile_for(int n) { return n >= 384 ? 8 : 16; }
+
+// Column-tile widths of the y and z kernels that the library is built with:
+// a tile of TX pencils of length N stages N (TX + 1) complex values in LDS
+// (at most 64 KB) and, in the z kernel, keeps N TX / NT of them per thread in
+// registers twice (spectrum and one derivative), at most 16 each.  Width 8 is
+// built only where 16 does not fit.
+constexpr bool y_tile_ok(int n, int tx) { return (long)n * (tx + 1) * 8 + n * 8 <= 65536; }
+constexpr bool z_tile_ok(int n, int tx) { return n * tx <= 16 * 256 && (long)n * (tx + 1) * 8 + 3L * n * 8 <= 65536; }
+constexpr bool y_tile_built(int n, int tx) { return y_tile_ok(n, tx) && (tx != 8 || !y_tile_ok(n, 16)); }
+constexpr bool z_tile_built(int n, int tx) { return z_tile_ok(n, tx) && (tx != 8 || !z_tile_ok(n, 16)); }
+
 
 // index of spectrum element (row, kx) within one field's spectrum
 __device__ __forceinline__ long spec_idx(const Geo& g, int row, int k)
@@ -480,13 +490,12 @@ struct Tile {
 
 // y FFT (forward or inverse) of `nf` spectra starting at field f0, in place.
 // grid: (main tiles + Nyquist tile, nz, shots * nf).  Main tile bx covers
-// columns [16 bx, 16 bx + 16) of plane z = by; the Nyquist tile covers the
-// Nyquist pencils of planes [16 by, 16 by + 16).
-template <int NY, int NT, int DIR>
+// columns [TX bx, TX bx + TX) of plane z = by; the Nyquist tile covers the
+// Nyquist pencils of planes [TX by, TX by + TX).
+template <int NY, int NT, int DIR, int TX>
 __global__ __launch_bounds__(NT) void k_y(Geo g, const float2* __restrict__ twy, float2* __restrict__ spec,
                                           int f0, int nf)
 {
-    constexpr int TX = tile_for(NY);
     constexpr int IS = TX + 1;
     __shared__ float2 s[NY * IS];
     __shared__ float2 tw[NY];
@@ -508,18 +517,17 @@ __global__ __launch_bounds__(NT) void k_y(Geo g, const float2* __restrict__ twy,
 
 // z FFT, multiply by the staggered derivative symbols and kappa, inverse z
 // FFT.  grid: (main tiles + Nyquist tile, ny, shots * nin).  Main tile bx
-// covers columns [16 bx, +16) of row ky = by; the Nyquist tile covers the
-// Nyquist pencils of rows [16 by, +16).  Reads spectrum `in0 + input`, writes
+// covers columns [TX bx, +TX) of row ky = by; the Nyquist tile covers the
+// Nyquist pencils of rows [TX by, +TX).  Reads spectrum `in0 + input`, writes
 // the derivative spectra (9 + output index) of the shot.  The forward
 // spectrum stays in registers; each output is multiplied there and inverted
 // with the reversed radix plan.
-template <int NZ, int NT>
+template <int NZ, int NT, int TX>
 __global__ __launch_bounds__(NT) void k_z(Geo g, const float2* __restrict__ twz, float2* __restrict__ spec,
                                           int in0, const ZDesc* __restrict__ zd, int phase)
 {
     const PhaseDesc& ph = zd->ph[phase];
     const Ops& ops = zd->ops;
-    constexpr int TX = tile_for(NZ);
     constexpr int IS = TX + 1;
     using RS = RegShape<NZ, TX, NT>;
     constexpr int RL = RS::RL, QL = RS::QL;

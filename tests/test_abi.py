@@ -10,13 +10,19 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 LIB = os.path.join(ROOT, "paper_1705_04874_amd", "libpstd3d.so")
-HEADER = os.path.join(ROOT, "include", "pstd3d.h")
+INCLUDE = os.path.join(ROOT, "include")
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(pstd3d_\w+|seis_combine)\s*\(", text)))
+    """Every function declared in include/*.h (comments stripped)."""
+    names = set()
+    for h in sorted(os.listdir(INCLUDE)):
+        if not h.endswith(".h"):
+            continue
+        text = re.sub(r"/\*.*?\*/", "", open(os.path.join(INCLUDE, h)).read(), flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        names |= set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_][\w\s\*]*?\b([a-z]\w*)\s*\(", text, flags=re.M))
+    return sorted(n for n in names if n not in ("defined",))
 
 
 @pytest.fixture(scope="module")

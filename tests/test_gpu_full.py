@@ -123,9 +123,11 @@ def test_batch_of_64_shots_matches_single_shots(B):
     s = B.Solver.from_workload(w)
     s.set_workload_sources(w)
     batch = s.run(nt).cpu().numpy()
+    tuning = s.tuning_values()
     s.close()
     for k in [0, 31, 63]:
         s1 = B.Solver.from_workload(w)
+        s1.set_tuning(**tuning)   # the batch's launch shapes: identical arithmetic per shot
         s1.set_sources([0, 1], w.src_ijk[k:k + 1], w.src_m[k:k + 1], w.wavelet[k:k + 1])
         one = s1.run(nt).cpu().numpy()[0]
         s1.close()

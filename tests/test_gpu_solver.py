@@ -129,6 +129,7 @@ def test_shots_are_independent(B):
     for k in range(w.n_shots):
         a, b = int(w.shot_ofs[k]), int(w.shot_ofs[k + 1])
         s1 = B.Solver.from_workload(w)
+        s1.set_tuning(**s.tuning_values())   # the same launch shapes: identical arithmetic
         s1.set_sources([0, b - a], w.src_ijk[a:b], w.src_m[a:b], w.wavelet[a:b])
         one = s1.run(w.nt).cpu().numpy()[0]
         np.testing.assert_array_equal(batch[k], one)
@@ -145,6 +146,7 @@ def test_run_is_stateful_and_checkpoint_is_exact(B):
     b = s.run(50).cpu().numpy()
     np.testing.assert_array_equal(np.concatenate([a, b], axis=3), full)
     s2 = B.Solver.from_workload(w)
+    s2.set_tuning(**s.tuning_values())
     s2.set_workload_sources(w)
     s2.set_state(st, 30)
     c = s2.run(50).cpu().numpy()
@@ -211,16 +213,53 @@ def test_run_many_uneven_grids(B):
     ws = [small_workload(shape=(30, 24, 40), nt=50, shots=1, seed=4),
           small_workload(shape=(24, 32, 48), nt=50, shots=2, seed=5),
           small_workload(shape=(40, 30, 32), nt=50, shots=1, seed=6)]
-    solos = []
+    solos, tunings = [], []
     for w in ws:
         s = B.Solver.from_workload(w)
         s.set_workload_sources(w)
         solos.append(s.run(50).cpu().numpy())
+        tunings.append(s.tuning_values())
     ss = []
-    for w in ws:
+    for w, tu in zip(ws, tunings):
         s = B.Solver.from_workload(w)
+        s.set_tuning(**tu)
         s.set_workload_sources(w)
         ss.append(s)
     outs = B.run_many(ss, 50)
     for a, b in zip(outs, solos):
         np.testing.assert_array_equal(a.cpu().numpy(), b)
+
+
+def test_every_tuning_value_gives_the_same_traces(B):
+    """The autotuner may pick any built launch shape: y / z tile widths and the
+    update kernels' threads per block.  Each computes every pencil with the
+    same butterflies and every cell with the same update, so the traces agree
+    to FP32 rounding (fused multiply-adds may be contracted differently)."""
+    w = small_workload(shape=(48, 128, 64), nt=30, shots=2, seed=8)
+    s = B.Solver.from_workload(w)
+    s.set_workload_sources(w)
+    t = s.tuning()
+    say("tuning", t)
+    for k in B.TUNE_KNOBS:
+        cand = t[k + "_candidates"]
+        assert t[k] in cand
+        # the chosen value was measured and is the fastest measured
+        assert cand[t[k]] == min(v for v in cand.values() if v > 0), k
+    assert len(t["y_tile_candidates"]) >= 2 and len(t["z_tile_candidates"]) >= 2
+    assert len(t["vel_threads_candidates"]) >= 2
+    ref = s.run(w.nt).cpu().numpy()
+    scale = np.abs(ref).max(axis=(2, 3), keepdims=True)
+    combos = [dict(y_tile=y, z_tile=z, vel_threads=256, str_threads=256)
+              for y in t["y_tile_candidates"] for z in t["z_tile_candidates"]]
+    combos += [dict(y_tile=16, z_tile=16, vel_threads=v, str_threads=v) for v in t["vel_threads_candidates"]]
+    for kw in combos:
+        s.set_tuning(**kw)
+        got_t = s.tuning()
+        assert all(got_t[k] == v for k, v in kw.items())
+        s.reset()
+        got = s.run(w.nt).cpu().numpy()
+        err = np.abs(got - ref).max(axis=(2, 3), keepdims=True) / scale
+        assert err.max() < 1e-5, (kw, float(err.max()))
+    with pytest.raises(B.PstdError) as e:
+        s.set_tuning(y_tile=7)
+    assert e.value.code == B.PSTD_EUNSUPPORTED
