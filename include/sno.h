@@ -5,17 +5,22 @@
  * The paper names a learned proxy of the forward simulation as future work
  * (Sec. VII).  The surrogate maps a point source (position and moment tensor,
  * 9 numbers) to four-component receiver traces on a line of receivers, with a
- * Fourier neural operator along time:
- *   lift      V0 = P [f; t] + pb                       (f: 9 normalised features)
+ * Fourier neural operator along time.  The elastic system is linear in its
+ * source (eq. 2; Sec. IV's superposition rests on it), so the traces are a
+ * combination of six responses weighted by the moment-tensor components, and
+ * the network sees only the position:
+ *   lift      V0 = P A + pb,  A = [p; t/T; cos, sin(2 pi c_f t/T) per Fourier
+ *             feature frequency c_f]   (p: 3 normalised position features)
  *   layer l   Z = W_l V + b_l + IDFT_K( R_l[k] DFT_K(V)[k] ),  V = gelu(Z)
  *             (no activation after the last layer; K retained modes; complex
  *              C x C weights per mode)
- *   project   Y = Q2 gelu(Q1 V + q1b) + q2b            (O = 4 n_rec outputs)
+ *   project   Y6 = Q2 gelu(Q1 V + q1b) + q2b           (6 O rows, O = 4 n_rec)
+ *   output    Y[o] = sum_j m_j Y6[j O + o],  m_j = M_j / feat_scale[3 + j]
  * Every contraction runs on BF16 MFMA with FP32 accumulation; master weights,
  * gradients and Adam moments are FP32.  Training minimises the mean squared
  * error of traces normalised per component by their training-set RMS.  An
  * error head predicts each sample's relative L2 error from the pooled last
- * hidden layer; predictions whose estimate exceeds a tolerance are recomputed
+ * hidden layer and the moment features; predictions whose estimate exceeds a tolerance are recomputed
  * by the pseudo-spectral solver (pstd3d), which stays the judge of accuracy.
  *
  * Layout: features X [n][9] (x, y, z cell indices, moment tensor xx yy zz xy xz
@@ -42,9 +47,13 @@ typedef struct {
     int K;              /* retained Fourier modes (<= T/2) */
     int L;              /* Fourier layers */
     int H;              /* projection hidden width (multiple of 16) */
-    double feat_off[9]; /* feature f = (x - off) / scale */
+    double feat_off[9]; /* feature f = (x - off) / scale; off must be 0 for the 6
+                           moment components (the output is linear in them) */
     double feat_scale[9];
+    int n_four;         /* Fourier time features (0 .. SNO_MAX_FOUR) */
+    double four_cycles[64]; /* their frequencies, cycles per window of T samples */
 } sno_cfg;
+#define SNO_MAX_FOUR 64  /* size of four_cycles */
 
 typedef struct {
     int epochs;
@@ -54,8 +63,9 @@ typedef struct {
     int n_calib;        /* last n_calib samples fit the error head, not the weights */
 } sno_train_cfg;
 
-/* Create a model; params (host float, sno_n_params values, order P, pb,
- * {W_l, b_l, Rr_l, Ri_l}_l, Q1, q1b, Q2, q2b) are the initial weights. */
+/* Create a model; params (host float, sno_n_params values, order P [C][4 +
+ * 2 n_four], pb [C], {W_l [C][C], b_l [C], Rr_l, Ri_l [K][C][C]}_l, Q1 [H][C],
+ * q1b [H], Q2 [6 O][H], q2b [6 O]) are the initial weights. */
 int sno_create(const sno_cfg *cfg, const float *params, sno **out);
 long sno_n_params(const sno_cfg *cfg);
 void sno_destroy(sno *s);

@@ -2,15 +2,22 @@
 
 The paper names a learned proxy of the forward simulation as future work
 (Sec. VII); the surrogate here maps a point source (position and moment tensor)
-to four-component receiver traces with a Fourier neural operator along time:
+to four-component receiver traces with a Fourier neural operator along time.
+The elastic system is linear in the source term (eq. 2; the superposition of
+Sec. IV rests on it), so the output is a linear combination of six responses
+weighted by the moment-tensor components, and the network sees the position
+only:
 
-  lift:     V0 = P A + pb,            A = [source features broadcast; t_j]   (C x T)
+  lift:     V0 = P A + pb,   A = [position broadcast; t_j / T;
+                                  cos, sin(2 pi c_f t_j / T) for the Fourier
+                                  feature frequencies c_f (cycles per window)]
   layer l:  Vh = V F                  truncated DFT, F = [cos | -sin](2 pi j k / T), k < K
             U_k = R_l[k] Vh_k         complex C x C mixing per retained mode k
             U  = Uh G                 inverse DFT of the K modes of a real signal
             Z  = W_l V + b_l + U
             V  = gelu(Z)  (no activation after the last layer)
-  project:  Y = Q2 gelu(Q1 V + q1b) + q2b                                      (O x T)
+  project:  Y6 = Q2 gelu(Q1 V + q1b) + q2b                              (6 O x T)
+  output:   Y[o] = sum_j m_j Y6[j O + o],  m = the 6 moment-tensor features
 
 gelu(x) = x/2 (1 + tanh(sqrt(2/pi) (x + 0.044715 x^3))).  Loss: mean squared
 error over the batch and all outputs.  Gradients are written out by hand
@@ -26,7 +33,9 @@ import numpy as np
 
 @dataclass
 class Dims:
-    n_in: int = 9          # source features
+    n_pos: int = 3         # position features (broadcast along time)
+    n_mt: int = 6          # moment-tensor features (the output is linear in them)
+    four: tuple = ()       # Fourier time features: frequencies in cycles per window
     C: int = 64            # width
     T: int = 1024          # time samples
     K: int = 16            # retained modes
@@ -35,12 +44,17 @@ class Dims:
     O: int = 256           # outputs per time sample (4 components x 64 receivers)
 
 
+def n_lift(d: Dims):
+    """Input channels of the lift: position, t / T, cos and sin per frequency."""
+    return d.n_pos + 1 + 2 * len(d.four)
+
+
 def param_shapes(d: Dims):
     """Ordered (name, shape) list; the flat parameter vector follows this order."""
-    s = [("P", (d.C, d.n_in + 1)), ("pb", (d.C,))]
+    s = [("P", (d.C, n_lift(d))), ("pb", (d.C,))]
     for l in range(d.L):
         s += [(f"W{l}", (d.C, d.C)), (f"b{l}", (d.C,)), (f"Rr{l}", (d.K, d.C, d.C)), (f"Ri{l}", (d.K, d.C, d.C))]
-    s += [("Q1", (d.H, d.C)), ("q1b", (d.H,)), ("Q2", (d.O, d.H)), ("q2b", (d.O,))]
+    s += [("Q1", (d.H, d.C)), ("q1b", (d.H,)), ("Q2", (d.n_mt * d.O, d.H)), ("q2b", (d.n_mt * d.O,))]
     return s
 
 
@@ -86,13 +100,23 @@ def gelu_grad(x):
 
 
 def features(src, d: Dims):
-    """A (B x (n_in+1) x T): source features broadcast along time plus t_j = j / T."""
+    """A (B x n_lift x T): the position features of src (B x (n_pos + n_mt))
+    broadcast along time, t_j = j / T, then cos and sin of 2 pi c_f t_j / T."""
     src = np.asarray(src, np.float64)
     B = src.shape[0]
-    A = np.empty((B, d.n_in + 1, d.T))
-    A[:, :d.n_in, :] = src[:, :, None]
-    A[:, d.n_in, :] = np.arange(d.T) / d.T
+    t = np.arange(d.T) / d.T
+    A = np.empty((B, n_lift(d), d.T))
+    A[:, :d.n_pos, :] = src[:, :d.n_pos, None]
+    A[:, d.n_pos, :] = t
+    for f, c in enumerate(d.four):
+        A[:, d.n_pos + 1 + 2 * f, :] = np.cos(2 * math.pi * c * t)
+        A[:, d.n_pos + 2 + 2 * f, :] = np.sin(2 * math.pi * c * t)
     return A
+
+
+def moments(src, d: Dims):
+    """The n_mt moment-tensor features of src (B x n_mt)."""
+    return np.asarray(src, np.float64)[:, d.n_pos:d.n_pos + d.n_mt]
 
 
 def forward(theta, src, d: Dims, keep=False):
@@ -115,8 +139,11 @@ def forward(theta, src, d: Dims, keep=False):
         cache["V"].append(V)
     Hp = np.einsum("hc,bct->bht", p["Q1"], V) + p["q1b"][None, :, None]
     Hq = gelu(Hp)
-    Y = np.einsum("oh,bht->bot", p["Q2"], Hq) + p["q2b"][None, :, None]
-    cache.update(Hp=Hp, Hq=Hq)
+    Y6 = np.einsum("oh,bht->bot", p["Q2"], Hq) + p["q2b"][None, :, None]
+    Y6 = Y6.reshape(Y6.shape[0], d.n_mt, d.O, d.T)
+    m = moments(src, d)
+    Y = np.einsum("bj,bjot->bot", m, Y6)
+    cache.update(Hp=Hp, Hq=Hq, m=m)
     return (Y, cache) if keep else Y
 
 
@@ -132,9 +159,10 @@ def grad(theta, src, y, d: Dims):
     Y, c = forward(theta, src, d, keep=True)
     g = {}
     dY = 2.0 * (Y - y) / Y.size
-    g["Q2"] = np.einsum("bot,bht->oh", dY, c["Hq"])
-    g["q2b"] = dY.sum(axis=(0, 2))
-    dHq = np.einsum("oh,bot->bht", p["Q2"], dY)
+    dY6 = (c["m"][:, :, None, None] * dY[:, None, :, :]).reshape(Y.shape[0], d.n_mt * d.O, d.T)
+    g["Q2"] = np.einsum("bot,bht->oh", dY6, c["Hq"])
+    g["q2b"] = dY6.sum(axis=(0, 2))
+    dHq = np.einsum("oh,bot->bht", p["Q2"], dY6)
     dHp = dHq * gelu_grad(c["Hp"])
     g["Q1"] = np.einsum("bht,bct->hc", dHp, c["V"][-1])
     g["q1b"] = dHp.sum(axis=(0, 2))

@@ -255,7 +255,8 @@ def seis_combine(traces, t0, src_idx, amp, t_origin, nt_out, dt_in, dt_out, out=
 # spectral neural operator surrogate (include/sno.h)
 class SnoCfg(C.Structure):
     _fields_ = [("n_rec", C.c_int), ("T", C.c_int), ("C", C.c_int), ("K", C.c_int), ("L", C.c_int), ("H", C.c_int),
-                ("feat_off", C.c_double * 9), ("feat_scale", C.c_double * 9)]
+                ("feat_off", C.c_double * 9), ("feat_scale", C.c_double * 9),
+                ("n_four", C.c_int), ("four_cycles", C.c_double * 64)]
 
 
 class SnoTrainCfg(C.Structure):
@@ -297,10 +298,15 @@ def _dev(t):
 class Surrogate:
     """Spectral neural operator surrogate on the current GPU (see include/sno.h)."""
 
-    def __init__(self, n_rec, T, C_, K, L, H, feat_off, feat_scale, params):
+    def __init__(self, n_rec, T, C_, K, L, H, feat_off, feat_scale, params, four_cycles=()):
+        four = [float(v) for v in four_cycles]
+        if len(four) > 64:
+            raise ValueError("at most 64 Fourier feature frequencies")
         self.cfg = SnoCfg(int(n_rec), int(T), int(C_), int(K), int(L), int(H),
                           (C.c_double * 9)(*[float(v) for v in feat_off]),
-                          (C.c_double * 9)(*[float(v) for v in feat_scale]))
+                          (C.c_double * 9)(*[float(v) for v in feat_scale]),
+                          len(four), (C.c_double * 64)(*(four + [0.0] * (64 - len(four)))))
+        self.n_lift = 4 + 2 * len(four)
         self.n_params = _L.sno_n_params(C.byref(self.cfg))
         if self.n_params < 0:
             raise ValueError("bad surrogate configuration")

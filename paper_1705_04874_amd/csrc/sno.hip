@@ -157,17 +157,65 @@ __global__ void k_gelu_bwd(const float* __restrict__ dy, const float* __restrict
 
 struct Feat {
     float off[9], inv[9];
+    float cyc[SNO_MAX_FOUR];   // Fourier feature frequencies, cycles per window
+    int n_four;
 };
 
-// A[b][i][t] = (X[b][i] - off_i) / scale_i for i < 9, A[b][9][t] = t / T
-__global__ void k_features(const float* __restrict__ X, Feat f, int B, int T, float* __restrict__ A)
+// lift input A[b][i][t], NA = 4 + 2 n_four channels: the 3 normalised position
+// features, t / T, then cos and sin of 2 pi c_f t / T per frequency
+__global__ void k_features(const float* __restrict__ X, Feat f, int B, int T, int NA, float* __restrict__ A)
 {
-    const long n = (long)B * 10 * T;
+    const long n = (long)B * NA * T;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
         const int t = e % T;
-        const int i = (e / T) % 10;
-        const int b = e / (10L * T);
-        A[e] = i < 9 ? (X[b * 9 + i] - f.off[i]) * f.inv[i] : (float)t / (float)T;
+        const int i = (e / T) % NA;
+        const int b = e / ((long)NA * T);
+        float v;
+        if (i < 3) {
+            v = (X[b * 9 + i] - f.off[i]) * f.inv[i];
+        } else if (i == 3) {
+            v = (float)t / (float)T;
+        } else {
+            // phase c t / T reduced to [0, 1) turns before the sine and cosine
+            const int q = (i - 4) >> 1;
+            const float ph = f.cyc[q] * (float)t / (float)T;
+            const float r = 2.f * 3.14159265358979f * (ph - floorf(ph));
+            v = ((i - 4) & 1) ? sinf(r) : cosf(r);
+        }
+        A[e] = v;
+    }
+}
+
+// moment features m[b][j] = X[b][3 + j] / scale
+__device__ __forceinline__ float mfeat(const float* X, const Feat& f, int b, int j) { return X[b * 9 + 3 + j] * f.inv[3 + j]; }
+
+// Y[b][o][t] = sum_j m_j Y6[b][j O + o][t]
+__global__ void k_mcomb(const float* __restrict__ Y6, const float* __restrict__ X, Feat f, int B, int O, int T,
+                        float* __restrict__ Y)
+{
+    const long per = (long)O * T;
+    const long n = (long)B * per;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        const int b = e / per;
+        const long r = e - b * per;
+        float s = 0.f;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) s += mfeat(X, f, b, j) * Y6[((long)b * 6 + j) * per + r];
+        Y[e] = s;
+    }
+}
+
+// dY6[b][j O + o][t] = m_j dY[b][o][t]
+__global__ void k_mspread(const float* __restrict__ dY, const float* __restrict__ X, Feat f, int B, int O, int T,
+                          float* __restrict__ dY6)
+{
+    const long per = (long)O * T;
+    const long n = (long)B * 6 * per;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        const int bj = e / per;
+        const long r = e - bj * per;
+        const int b = bj / 6, j = bj - b * 6;
+        dY6[e] = mfeat(X, f, b, j) * dY[(long)b * per + r];
     }
 }
 
@@ -309,8 +357,9 @@ __global__ __launch_bounds__(256) void k_relerr(const float* __restrict__ Yp, co
     if (threadIdx.x == 0) err[b] = worst;
 }
 
-// phi[b] = (mean over t of V[b][c][t] for c < C, 1)
-__global__ __launch_bounds__(256) void k_pool(const float* __restrict__ V, int C, int T, float* __restrict__ phi)
+// phi[b] = (mean over t of V[b][c][t] for c < C, the 6 moment features, 1)
+__global__ __launch_bounds__(256) void k_pool(const float* __restrict__ V, const float* __restrict__ X, Feat f, int C,
+                                              int T, float* __restrict__ phi)
 {
     __shared__ float red[256];
     const int b = blockIdx.x / C, c = blockIdx.x % C;
@@ -323,8 +372,12 @@ __global__ __launch_bounds__(256) void k_pool(const float* __restrict__ V, int C
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        phi[(long)b * (C + 1) + c] = red[0] / T;
-        if (c == 0) phi[(long)b * (C + 1) + C] = 1.f;
+        float* ph = phi + (long)b * (C + 7);
+        ph[c] = red[0] / T;
+        if (c == 0) {
+            for (int j = 0; j < 6; ++j) ph[C + j] = mfeat(X, f, b, j);
+            ph[C + 6] = 1.f;
+        }
     }
 }
 
@@ -357,7 +410,7 @@ int grid_for(long n) { return (int)std::min<long>((n + 255) / 256, 4096); }
 // ===========================================================================
 struct sno {
     sno_cfg cfg{};
-    int O = 0, n_in = 9;
+    int O = 0, NA = 4;   // outputs per time sample, lift input channels
     long np = 0;
     long off_P, off_pb, off_W[16], off_b[16], off_Rr[16], off_Ri[16], off_Q1, off_q1b, off_Q2, off_q2b;
     float *theta = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
@@ -373,7 +426,8 @@ struct sno {
     int bmax = 0;
     float *A = nullptr, *Vb = nullptr, *Vh = nullptr, *Z = nullptr, *Uh = nullptr, *Hp = nullptr, *Hq = nullptr,
           *Y = nullptr, *X0 = nullptr, *X1 = nullptr, *X2 = nullptr, *dH = nullptr, *dUh = nullptr, *dVh = nullptr,
-          *part = nullptr, *lossd = nullptr, *phi = nullptr, *Xb = nullptr, *Yb = nullptr;
+          *part = nullptr, *lossd = nullptr, *phi = nullptr, *Xb = nullptr, *Yb = nullptr, *Y6 = nullptr,
+          *dY6 = nullptr;
     int* idxd = nullptr;
 
     float* V(int l) { return l < cfg.L ? Vb + (long)l * bmax * cfg.C * cfg.T : Z + (long)(cfg.L - 1) * bmax * cfg.C * cfg.T; }
@@ -382,9 +436,11 @@ struct sno {
 
     void free_ws()
     {
-        for (float* p : {A, Vb, Vh, Z, Uh, Hp, Hq, Y, X0, X1, X2, dH, dUh, dVh, part, lossd, phi, Xb, Yb}) (void)hipFree(p);
+        for (float* p : {A, Vb, Vh, Z, Uh, Hp, Hq, Y, X0, X1, X2, dH, dUh, dVh, part, lossd, phi, Xb, Yb, Y6, dY6})
+            (void)hipFree(p);
         (void)hipFree(idxd);
-        A = Vb = Vh = Z = Uh = Hp = Hq = Y = X0 = X1 = X2 = dH = dUh = dVh = part = lossd = phi = Xb = Yb = nullptr;
+        A = Vb = Vh = Z = Uh = Hp = Hq = Y = X0 = X1 = X2 = dH = dUh = dVh = part = lossd = phi = Xb = Yb = Y6 = dY6 =
+            nullptr;
         idxd = nullptr;
         bmax = 0;
     }
@@ -400,11 +456,11 @@ struct sno {
         free_ws();
         const long C = cfg.C, T = cfg.T, K2 = 2 * cfg.K, H = cfg.H, L = cfg.L;
         auto al = [&](float** p, long n) { return hipMalloc(p, std::max<long>(n, 1) * sizeof(float)); };
-        if (al(&A, (long)B * 10 * T) || al(&Vb, L * B * C * T) || al(&Vh, L * B * C * K2) || al(&Z, L * B * C * T) ||
+        if (al(&A, (long)B * NA * T) || al(&Y6, (long)B * 6 * O * T) || al(&dY6, (long)B * 6 * O * T) || al(&Vb, L * B * C * T) || al(&Vh, L * B * C * K2) || al(&Z, L * B * C * T) ||
             al(&Uh, (long)B * C * K2) || al(&Hp, (long)B * H * T) || al(&Hq, (long)B * H * T) ||
             al(&Y, (long)B * O * T) || al(&X0, (long)B * std::max(C, (long)O) * T) || al(&X1, (long)B * C * T) ||
             al(&X2, (long)B * C * T) || al(&dH, (long)B * H * T) || al(&dUh, (long)B * C * K2) ||
-            al(&dVh, (long)B * C * K2) || al(&part, 4096) || al(&lossd, 4) || al(&phi, (long)B * (C + 1)) ||
+            al(&dVh, (long)B * C * K2) || al(&part, 4096) || al(&lossd, 4) || al(&phi, (long)B * (C + 7)) ||
             al(&Xb, (long)B * 9) || al(&Yb, (long)B * O * T) || hipMalloc(&idxd, B * sizeof(int)))
             return sfail(PSTD_ENOMEM, "surrogate workspace");
         bmax = B;
@@ -419,7 +475,7 @@ long layout(sno_cfg c, sno* s)
     const int O = 4 * c.n_rec;
     long o = 0;
     auto take = [&](long n) { long r = o; o += n; return r; };
-    long P = take((long)c.C * 10), pb = take(c.C);
+    long P = take((long)c.C * (4 + 2 * c.n_four)), pb = take(c.C);
     long W[16], b[16], Rr[16], Ri[16];
     for (int l = 0; l < c.L; ++l) {
         W[l] = take((long)c.C * c.C);
@@ -427,7 +483,7 @@ long layout(sno_cfg c, sno* s)
         Rr[l] = take((long)c.K * c.C * c.C);
         Ri[l] = take((long)c.K * c.C * c.C);
     }
-    long Q1 = take((long)c.H * c.C), q1b = take(c.H), Q2 = take((long)O * c.H), q2b = take(O);
+    long Q1 = take((long)c.H * c.C), q1b = take(c.H), Q2 = take(6L * O * c.H), q2b = take(6L * O);
     if (s) {
         s->off_P = P;
         s->off_pb = pb;
@@ -452,6 +508,11 @@ bool cfg_ok(const sno_cfg* c)
         return false;
     for (int i = 0; i < 9; ++i)
         if (!(c->feat_scale[i] != 0.0) || !std::isfinite(c->feat_off[i]) || !std::isfinite(c->feat_scale[i])) return false;
+    for (int i = 3; i < 9; ++i)
+        if (c->feat_off[i] != 0.0) return false;
+    if (c->n_four < 0 || c->n_four > SNO_MAX_FOUR) return false;
+    for (int f = 0; f < c->n_four; ++f)
+        if (!(c->four_cycles[f] > 0.0 && c->four_cycles[f] <= c->T / 2)) return false;
     return true;
 }
 
@@ -461,8 +522,9 @@ void forward(sno* s, hipStream_t st, const float* X, int B)
     const sno_cfg& c = s->cfg;
     const long C = c.C, T = c.T, K = c.K, K2 = 2 * K, H = c.H, O = s->O;
     const float* th = s->theta;
-    hipLaunchKernelGGL(k_features, dim3(grid_for(B * 10 * T)), dim3(256), 0, st, X, s->feat, B, (int)T, s->A);
-    gemm(st, B, C, T, 10, 1, th + s->off_P, 10, 1, 0, 0, s->A, T, 1, 10 * T, 0, s->V(0), T, 1, C * T, 1.f, 0.f,
+    const long NA = s->NA;
+    hipLaunchKernelGGL(k_features, dim3(grid_for(B * NA * T)), dim3(256), 0, st, X, s->feat, B, (int)T, (int)NA, s->A);
+    gemm(st, B, C, T, NA, 1, th + s->off_P, NA, 1, 0, 0, s->A, T, 1, NA * T, 0, s->V(0), T, 1, C * T, 1.f, 0.f,
          th + s->off_pb);
     for (int l = 0; l < c.L; ++l) {
         float* V = s->V(l);
@@ -487,12 +549,14 @@ void forward(sno* s, hipStream_t st, const float* X, int B)
     gemm(st, B, H, T, C, 1, th + s->off_Q1, C, 1, 0, 0, s->V(c.L), T, 1, C * T, 0, s->Hp, T, 1, H * T, 1.f, 0.f,
          th + s->off_q1b);
     hipLaunchKernelGGL(k_gelu, dim3(grid_for(B * H * T)), dim3(256), 0, st, s->Hp, s->Hq, (long)B * H * T);
-    gemm(st, B, O, T, H, 1, th + s->off_Q2, H, 1, 0, 0, s->Hq, T, 1, H * T, 0, s->Y, T, 1, O * T, 1.f, 0.f,
+    gemm(st, B, 6 * O, T, H, 1, th + s->off_Q2, H, 1, 0, 0, s->Hq, T, 1, H * T, 0, s->Y6, T, 1, 6 * O * T, 1.f, 0.f,
          th + s->off_q2b);
+    hipLaunchKernelGGL(k_mcomb, dim3(grid_for(B * O * T)), dim3(256), 0, st, s->Y6, X, s->feat, B, (int)O, (int)T, s->Y);
 }
 
-// gradient of the mean squared error of s->Y against Yt (after forward)
-void backward(sno* s, hipStream_t st, const float* Yt, int B)
+// gradient of the mean squared error of s->Y against Yt (after the forward of
+// the same features X)
+void backward(sno* s, hipStream_t st, const float* X, const float* Yt, int B)
 {
     const sno_cfg& c = s->cfg;
     const long C = c.C, T = c.T, K = c.K, K2 = 2 * K, H = c.H, O = s->O;
@@ -502,10 +566,13 @@ void backward(sno* s, hipStream_t st, const float* Yt, int B)
     float* dY = s->X0;
     hipLaunchKernelGGL(k_mse, dim3(256), dim3(256), 0, st, s->Y, Yt, nY, dY, s->part);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, s->part, 256, s->lossd, 1.f / (float)nY);
-    // projection
-    gemm(st, 1, O, H, T, B, dY, T, 1, 0, O * T, s->Hq, 1, T, 0, H * T, g + s->off_Q2, H, 1, 0);
-    hipLaunchKernelGGL(k_rowsum, dim3(O), dim3(256), 0, st, dY, B, (int)O, (int)T, g + s->off_q2b);
-    gemm(st, B, H, T, O, 1, th + s->off_Q2, 1, H, 0, 0, dY, T, 1, O * T, 0, s->dH, T, 1, H * T);
+    // moment combination and projection
+    const long O6 = 6 * O;
+    hipLaunchKernelGGL(k_mspread, dim3(grid_for(B * O6 * T)), dim3(256), 0, st, dY, X, s->feat, B, (int)O, (int)T,
+                       s->dY6);
+    gemm(st, 1, O6, H, T, B, s->dY6, T, 1, 0, O6 * T, s->Hq, 1, T, 0, H * T, g + s->off_Q2, H, 1, 0);
+    hipLaunchKernelGGL(k_rowsum, dim3(O6), dim3(256), 0, st, s->dY6, B, (int)O6, (int)T, g + s->off_q2b);
+    gemm(st, B, H, T, O6, 1, th + s->off_Q2, 1, H, 0, 0, s->dY6, T, 1, O6 * T, 0, s->dH, T, 1, H * T);
     hipLaunchKernelGGL(k_gelu_bwd, dim3(grid_for(B * H * T)), dim3(256), 0, st, s->dH, s->Hp, s->dH, (long)B * H * T);
     gemm(st, 1, H, C, T, B, s->dH, T, 1, 0, H * T, s->V(c.L), 1, T, 0, C * T, g + s->off_Q1, C, 1, 0);
     hipLaunchKernelGGL(k_rowsum, dim3(H), dim3(256), 0, st, s->dH, B, (int)H, (int)T, g + s->off_q1b);
@@ -548,14 +615,17 @@ void backward(sno* s, hipStream_t st, const float* Yt, int B)
         gemm(st, B, C, T, K2, 1, s->dVh, K2, 1, C * K2, 0, s->F, 1, K2, 0, 0, dVn, T, 1, C * T, 1.f, 1.f);
         dV = dVn;
     }
-    gemm(st, 1, C, 10, T, B, dV, T, 1, 0, C * T, s->A, 1, T, 0, 10 * T, g + s->off_P, 10, 1, 0);
+    const long NA = s->NA;
+    gemm(st, 1, C, NA, T, B, dV, T, 1, 0, C * T, s->A, 1, T, 0, NA * T, g + s->off_P, NA, 1, 0);
     hipLaunchKernelGGL(k_rowsum, dim3(C), dim3(256), 0, st, dV, B, (int)C, (int)T, g + s->off_pb);
 }
 
-// error head inputs of the last forward: pooled last hidden layer
-void pool(sno* s, hipStream_t st, int B)
+// error head inputs of the last forward (features X): pooled last hidden
+// layer and the moment features
+void pool(sno* s, hipStream_t st, const float* X, int B)
 {
-    hipLaunchKernelGGL(k_pool, dim3(B * s->cfg.C), dim3(256), 0, st, s->V(s->cfg.L), s->cfg.C, s->cfg.T, s->phi);
+    hipLaunchKernelGGL(k_pool, dim3(B * s->cfg.C), dim3(256), 0, st, s->V(s->cfg.L), X, s->feat, s->cfg.C, s->cfg.T,
+                       s->phi);
 }
 
 }  // namespace
@@ -577,7 +647,10 @@ int sno_create(const sno_cfg* cfg, const float* params, sno** out)
     if (!s) return sfail(PSTD_ENOMEM, "host allocation");
     s->cfg = *cfg;
     s->O = 4 * cfg->n_rec;
+    s->NA = 4 + 2 * cfg->n_four;
     s->np = layout(*cfg, s);
+    s->feat.n_four = cfg->n_four;
+    for (int f = 0; f < cfg->n_four; ++f) s->feat.cyc[f] = (float)cfg->four_cycles[f];
     (void)hipGetDevice(&s->device);
     for (int i = 0; i < 9; ++i) {
         s->feat.off[i] = (float)cfg->feat_off[i];
@@ -599,7 +672,7 @@ int sno_create(const sno_cfg* cfg, const float* params, sno** out)
     int rc = PSTD_OK;
     if (hipMalloc(&s->theta, np * 4) || hipMalloc(&s->grad, np * 4) || hipMalloc(&s->m1, np * 4) ||
         hipMalloc(&s->m2, np * 4) || hipMalloc(&s->F, F.size() * 4) || hipMalloc(&s->G, G.size() * 4) ||
-        hipMalloc(&s->dscale, 16) || hipMalloc(&s->dhead, (cfg->C + 1) * 4))
+        hipMalloc(&s->dscale, 16) || hipMalloc(&s->dhead, (cfg->C + 7) * 4))
         rc = sfail(PSTD_ENOMEM, "surrogate parameters");
     if (!rc && (hipMemcpy(s->theta, params, np * 4, hipMemcpyHostToDevice) ||
                 hipMemcpy(s->F, F.data(), F.size() * 4, hipMemcpyHostToDevice) ||
@@ -608,9 +681,9 @@ int sno_create(const sno_cfg* cfg, const float* params, sno** out)
                 hipMemset(s->m2, 0, np * 4) || hipMemset(s->grad, 0, np * 4)))
         rc = sfail(PSTD_EDEVICE, "surrogate upload");
     // error head defaults to "always unsure" until trained: exp(30)
-    s->head.assign(cfg->C + 1, 0.f);
-    s->head[cfg->C] = 30.f;
-    if (!rc && hipMemcpy(s->dhead, s->head.data(), (cfg->C + 1) * 4, hipMemcpyHostToDevice))
+    s->head.assign(cfg->C + 7, 0.f);
+    s->head[cfg->C + 6] = 30.f;
+    if (!rc && hipMemcpy(s->dhead, s->head.data(), (cfg->C + 7) * 4, hipMemcpyHostToDevice))
         rc = sfail(PSTD_EDEVICE, "surrogate upload");
     if (rc) {
         delete s;
@@ -668,7 +741,7 @@ int sno_gradient(sno* s, const float* X, const float* Yt, int n, float* grad, fl
     int rc = s->ensure(n);
     if (rc) return rc;
     forward(s, st, X, n);
-    backward(s, st, Yt, n);
+    backward(s, st, X, Yt, n);
     S_TRY(hipMemcpyAsync(grad, s->grad, s->np * 4, hipMemcpyDeviceToDevice, st));
     float l = 0.f;
     S_TRY(hipMemcpyAsync(&l, s->lossd, 4, hipMemcpyDeviceToHost, st));
@@ -721,7 +794,7 @@ int sno_train(sno* s, const float* X, const float* Y, int n, const sno_train_cfg
             hipLaunchKernelGGL(k_gather, dim3(grid_for((long)B * s->O * c.T)), dim3(256), 0, st, X, Y, s->idxd, B,
                                s->O, c.T, c.n_rec, s->dscale, s->Xb, s->Yb);
             forward(s, st, s->Xb, B);
-            backward(s, st, s->Yb, B);
+            backward(s, st, s->Xb, s->Yb, B);
             ++step;
             const double lr = tc->lr * 0.5 * (1.0 + std::cos(M_PI * (double)(step - 1) / (double)std::max(1L, total)));
             const float c1 = (float)(1.0 - std::pow(0.9, (double)step));
@@ -738,7 +811,7 @@ int sno_train(sno* s, const float* X, const float* Y, int n, const sno_train_cfg
     }
     // error head: least squares of log(relative error) on the pooled last
     // hidden layer of the calibration samples, plus a one-sided 95 % margin
-    const int D = c.C + 1;
+    const int D = c.C + 7;
     std::vector<float> phis, errs;
     if (tc->n_calib > 1) {
         float* err = nullptr;
@@ -757,7 +830,7 @@ int sno_train(sno* s, const float* X, const float* Y, int n, const sno_train_cfg
             hipLaunchKernelGGL(k_scale_out, dim3(grid_for(nb * per)), dim3(256), 0, st, Yp, nb * per, s->O, c.T,
                                c.n_rec, s->dscale);
             hipLaunchKernelGGL(k_relerr, dim3(nb), dim3(256), 0, st, Yp, Y + (long)i0 * per, c.n_rec, c.T, err + b0);
-            pool(s, st, nb);
+            pool(s, st, X + (long)i0 * 9, nb);
             S_TRY(hipMemcpyAsync(phis.data() + (size_t)b0 * D, s->phi, (size_t)nb * D * 4, hipMemcpyDeviceToHost, st));
         }
         S_TRY(hipMemcpyAsync(errs.data(), err, tc->n_calib * 4, hipMemcpyDeviceToHost, st));
@@ -832,8 +905,8 @@ int sno_predict(sno* s, const float* X, int n, float* Y, float* est_err, void* h
         hipLaunchKernelGGL(k_scale_out, dim3(grid_for(B * per)), dim3(256), 0, st, Y + (long)b0 * per, B * per, s->O,
                            c.T, c.n_rec, s->dscale);
         if (est_err) {
-            pool(s, st, B);
-            hipLaunchKernelGGL(k_head, dim3((B + 63) / 64), dim3(64), 0, st, s->phi, s->dhead, c.C + 1, B,
+            pool(s, st, X + (long)b0 * 9, B);
+            hipLaunchKernelGGL(k_head, dim3((B + 63) / 64), dim3(64), 0, st, s->phi, s->dhead, c.C + 7, B,
                                s->head_margin, est_err + b0);
         }
     }

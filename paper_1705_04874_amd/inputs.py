@@ -351,22 +351,22 @@ def ragged_models(n_models=24, seed=5, nt=2000):
 # ----------------------------------------------------------------------------
 # surrogate initial weights (random numbers the training starts from)
 # ----------------------------------------------------------------------------
-def sno_param_shapes(C: int, K: int, L: int, H: int, O: int, n_in: int = 9):
+def sno_param_shapes(C: int, K: int, L: int, H: int, O: int, n_lift: int, n_mt: int = 6):
     """(name, shape) of the surrogate's flat parameter vector, in the order of
     include/sno.h: P, pb, {W_l, b_l, Rr_l, Ri_l}, Q1, q1b, Q2, q2b."""
-    s = [("P", (C, n_in + 1)), ("pb", (C,))]
+    s = [("P", (C, n_lift)), ("pb", (C,))]
     for l in range(L):
         s += [(f"W{l}", (C, C)), (f"b{l}", (C,)), (f"Rr{l}", (K, C, C)), (f"Ri{l}", (K, C, C))]
-    s += [("Q1", (H, C)), ("q1b", (H,)), ("Q2", (O, H)), ("q2b", (O,))]
+    s += [("Q1", (H, C)), ("q1b", (H,)), ("Q2", (n_mt * O, H)), ("q2b", (n_mt * O,))]
     return s
 
 
-def sno_init_params(C: int, K: int, L: int, H: int, O: int, seed: int, n_in: int = 9) -> np.ndarray:
+def sno_init_params(C: int, K: int, L: int, H: int, O: int, n_lift: int, seed: int, n_mt: int = 6) -> np.ndarray:
     """Seeded initial weights (float64 flat vector): uniform(+-1/sqrt(fan_in)) for
     the pointwise maps, uniform(0, 1) / C^2 for the spectral weights, zero biases."""
     rng = np.random.default_rng(seed)
     parts = []
-    for name, sh in sno_param_shapes(C, K, L, H, O, n_in):
+    for name, sh in sno_param_shapes(C, K, L, H, O, n_lift, n_mt):
         if name.startswith(("Rr", "Ri")):
             parts.append(rng.uniform(0.0, 1.0, sh) / (C * C))
         elif len(sh) == 2:
@@ -375,3 +375,8 @@ def sno_init_params(C: int, K: int, L: int, H: int, O: int, seed: int, n_in: int
         else:
             parts.append(np.zeros(sh))
     return np.concatenate([p.ravel() for p in parts])
+
+
+def sno_fourier_cycles(n: int, lo: float, hi: float) -> tuple:
+    """n Fourier feature frequencies (cycles per window) evenly spaced in [lo, hi]."""
+    return tuple(float(v) for v in np.linspace(lo, hi, n)) if n > 0 else ()

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 
 def init(d, seed):
-    return inputs.sno_init_params(d.C, d.K, d.L, d.H, d.O, seed, d.n_in)
+    return inputs.sno_init_params(d.C, d.K, d.L, d.H, d.O, osno.n_lift(d), seed, d.n_mt)
 
 
 def say(*a):
@@ -32,11 +32,12 @@ def rel(a, b):
 
 
 def make(B, d, theta):
-    return B.Surrogate(d.O // 4, d.T, d.C, d.K, d.L, d.H, np.zeros(9), np.ones(9), theta.astype(np.float32))
+    return B.Surrogate(d.O // 4, d.T, d.C, d.K, d.L, d.H, np.zeros(9), np.ones(9), theta.astype(np.float32),
+                       four_cycles=d.four)
 
 
-SMALL = osno.Dims(C=16, T=64, K=4, L=2, H=32, O=8)
-FULL = osno.Dims(C=64, T=1024, K=16, L=4, H=128, O=256)
+SMALL = osno.Dims(four=(3.0, 7.0, 12.5), C=16, T=64, K=4, L=2, H=32, O=8)
+FULL = osno.Dims(four=inputs.sno_fourier_cycles(32, 4.0, 128.0), C=64, T=1024, K=16, L=4, H=256, O=256)
 
 
 @pytest.mark.parametrize("d", [SMALL, FULL], ids=["small", "full"])
@@ -52,6 +53,22 @@ def test_forward_matches_oracle(B, d):
     e = rel(got, ref)
     say("forward", d, e)
     assert e < 2e-2
+
+
+def test_output_is_linear_in_the_moment_tensor(B):
+    """Sources at one position: the traces of a combined mechanism equal the
+    combination of the traces (eq. 2 is linear in its source)."""
+    import torch
+    d = SMALL
+    rng = np.random.default_rng(5)
+    s = make(B, d, init(d, 6) + 0.05 * rng.standard_normal(osno.n_params(d)))
+    pos = rng.uniform(-1, 1, 3)
+    m1, m2 = rng.uniform(-1, 1, (2, 6))
+    X = np.stack([np.concatenate([pos, m]) for m in (m1, m2, 1.5 * m1 - 0.25 * m2, np.zeros(6))])
+    y = s.forward(torch.tensor(X, dtype=torch.float32, device="cuda")).cpu().numpy().astype(np.float64)
+    comb = 1.5 * y[0] - 0.25 * y[1]
+    assert np.abs(y[2] - comb).max() <= 1e-5 * np.abs(comb).max()
+    assert np.abs(y[3]).max() == 0.0
 
 
 def test_gradient_matches_oracle(B):
@@ -111,7 +128,7 @@ def test_predict_or_solve_fallback(B):
     dt, T, decim = 0.8e-3, 64, 2
     rec = inputs.receiver_line_x(12, 28, 12, 5)             # 16 receivers
     solver = B.Solver(vp, vs, rho, (10.0, 10.0, 10.0), dt, pml=6, rec=rec)
-    d = osno.Dims(C=16, T=T, K=4, L=2, H=32, O=4 * rec.shape[0])
+    d = osno.Dims(four=(5.0, 9.0), C=16, T=T, K=4, L=2, H=32, O=4 * rec.shape[0])
     s = make(B, d, init(d, 4))
     ijk = np.array([[20, 12, 18], [14, 9, 22], [26, 15, 16]], np.int32)
     m6 = np.stack([inputs.double_couple(0.3, 0.7, 1.1, 1000.0), inputs.explosive(700.0), inputs.clvd(400.0)])
@@ -126,3 +143,71 @@ def test_predict_or_solve_fallback(B):
     assert not used1.any()
     Yp, _ = s.predict(X)
     np.testing.assert_array_equal(Y1.cpu().numpy(), Yp.cpu().numpy())
+
+
+def test_trained_network_gains_over_the_solver_alone(B):
+    """What the trained network adds to the solver: on a cluster of nearby
+    sources it predicts held-out traces far better than the same network
+    untrained, its error head accepts part of them at a tolerance, and the
+    blend (accepted predictions plus solver runs for the rest) is faster than
+    the solver alone while every rejected sample is the solver's own answer."""
+    import time
+
+    import torch
+    from paper_1705_04874_amd import inputs
+    shape = (48, 48, 48)
+    m = inputs.layered(48, 48, 48, water_cells=8, seed=11)
+    dt, decim, T = 0.8e-3, 2, 256
+    rec = inputs.receiver_line_x(12, 36, 24, 8)              # 24 receivers on the seabed
+    solver = B.Solver(m.vp, m.vs, m.rho, (10.0, 10.0, 10.0), dt, pml=8, rec=rec)
+    rng = np.random.default_rng(12)
+    n_tr, n_te = 96, 32
+    ctr = np.array([24.0, 24.0, 30.0])
+    pos = np.floor(inputs.latin_hypercube(n_tr + n_te, ctr - 1.5, ctr + 1.5, rng)).astype(np.int32)
+    mts = np.stack([inputs.dc_plus_iso(rng, inputs.DV_UNIT_MOMENT) for _ in range(n_tr + n_te)])
+    wav = inputs.ricker(25.0, dt, decim * T)
+    solver.set_sources(np.arange(n_tr + n_te + 1, dtype=np.int32), pos, mts, np.repeat(wav[None], n_tr + n_te, 0))
+    Y = B.decimate(solver.run(decim * T), decim)
+    X = torch.tensor(np.concatenate([pos, mts], axis=1), dtype=torch.float32, device="cuda")
+    d = osno.Dims(four=inputs.sno_fourier_cycles(16, 2.0, 40.0), C=32, T=T, K=8, L=2, H=64, O=4 * rec.shape[0])
+    s = B.Surrogate(rec.shape[0], T, d.C, d.K, d.L, d.H, list(ctr) + [0.0] * 6, [1.5] * 3 + [1000.0] * 6,
+                    init(d, 13).astype(np.float32), four_cycles=d.four)
+    yt = Y[n_tr:].cpu().numpy().astype(np.float64)
+
+    def err(Yp):
+        yp = Yp.cpu().numpy().astype(np.float64)
+        return np.max(np.linalg.norm(yp - yt, axis=(2, 3)) / np.linalg.norm(yt, axis=(2, 3)), axis=1)
+
+    s.train(X[:n_tr], Y[:n_tr], 1, 16, 1e-30, seed=1, n_calib=0)
+    e0 = err(s.predict(X[n_tr:])[0])
+    curve = s.train(X[:n_tr], Y[:n_tr], 300, 16, 2e-3, seed=1, n_calib=24)
+    Yp, est = s.predict(X[n_tr:])
+    e1 = err(Yp)
+    est = est.cpu().numpy()
+    say("untrained median", np.median(e0), "trained median", np.median(e1), "loss", curve[0], curve[-1])
+    assert np.median(e1) < 0.5 * np.median(e0)
+    tol = float(np.quantile(est, 0.5))                       # a tolerance the head accepts half the samples at
+    acc = est <= tol
+    assert acc.any() and (~acc).any()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Yb, est_b, used = s.predict_or_solve(solver, X[n_tr:], pos[n_tr:], mts[n_tr:], wav, decim, tol, max_batch=32)
+    torch.cuda.synchronize()
+    t_blend = time.perf_counter() - t0
+    np.testing.assert_array_equal(used, ~acc)
+    yb = Yb.cpu().numpy()
+    np.testing.assert_array_equal(yb[acc], Yp.cpu().numpy()[acc])
+    # rejected samples are the solver's answer (a fresh run of those sources)
+    rej = np.flatnonzero(~acc)
+    solver.set_sources(np.arange(rej.size + 1, dtype=np.int32), pos[n_tr:][rej], mts[n_tr:][rej],
+                       np.repeat(wav[None], rej.size, 0))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    direct = B.decimate(solver.run(decim * T), decim)
+    torch.cuda.synchronize()
+    t_rej = time.perf_counter() - t0
+    np.testing.assert_array_equal(yb[rej], direct.cpu().numpy())
+    # the solver alone would answer all n_te samples: about n_te / rej.size times t_rej
+    t_solver_all = t_rej * n_te / rej.size
+    say("blend", t_blend, "solver alone (scaled)", t_solver_all, "accepted", int(acc.sum()))
+    assert t_blend < t_solver_all

@@ -5,7 +5,10 @@
  * the hand-written gradient equals central finite differences of the loss
    for every parameter block (FP64);
  * gelu's derivative equals finite differences;
- * Adam's first step moves every weight by lr * sign(g) (bias correction).
+ * Adam's first step moves every weight by lr * sign(g) (bias correction);
+ * the output is linear in the moment-tensor features (the elastic system is
+   linear in its source, eq. 2) and does not depend on them otherwise;
+ * the Fourier time features are the modes numpy's FFT finds in them.
 """
 import math
 
@@ -15,7 +18,11 @@ import pytest
 from oracle import osno
 from paper_1705_04874_amd import inputs
 
-D = osno.Dims(n_in=3, C=4, T=32, K=5, L=2, H=6, O=5)
+D = osno.Dims(n_pos=3, n_mt=6, four=(3.0, 7.5), C=4, T=32, K=5, L=2, H=6, O=5)
+
+
+def init(d, seed):
+    return inputs.sno_init_params(d.C, d.K, d.L, d.H, d.O, osno.n_lift(d), seed, d.n_mt)
 
 
 def test_truncated_dft_matches_numpy_fft():
@@ -42,9 +49,9 @@ def test_gelu_derivative():
 
 def test_gradient_matches_finite_differences():
     rng = np.random.default_rng(1)
-    theta = inputs.sno_init_params(D.C, D.K, D.L, D.H, D.O, 3, D.n_in)
+    theta = init(D, 3)
     theta += 0.05 * rng.standard_normal(theta.size)        # break the zero biases / positive R
-    src = rng.standard_normal((2, D.n_in))
+    src = rng.standard_normal((2, D.n_pos + D.n_mt))
     y = rng.standard_normal((2, D.O, D.T))
     g = osno.grad(theta, src, y, D)
     o = 0
@@ -68,3 +75,23 @@ def test_adam_first_step():
     g = np.array([0.3, -1e-3, 2.0])
     t, m, v = osno.adam(theta, g, np.zeros(3), np.zeros(3), 1, 0.01)
     assert np.allclose(t, theta - 0.01 * np.sign(g), atol=1e-7)
+
+
+def test_output_is_linear_in_the_moment_tensor():
+    rng = np.random.default_rng(4)
+    theta = init(D, 5) + 0.05 * rng.standard_normal(osno.n_params(D))
+    pos = rng.standard_normal((1, D.n_pos))
+    m1, m2 = rng.standard_normal((2, D.n_mt))
+    y = lambda m: osno.forward(theta, np.concatenate([pos, m[None]], axis=1), D)
+    np.testing.assert_allclose(y(2.0 * m1 - 0.5 * m2), 2.0 * y(m1) - 0.5 * y(m2), rtol=1e-12, atol=1e-12)
+    assert np.abs(y(np.zeros(D.n_mt))).max() == 0.0
+
+
+def test_fourier_features_have_their_frequencies():
+    d = osno.Dims(four=(4.0, 11.0), T=64)
+    A = osno.features(np.zeros((1, 9)), d)[0]
+    for f, c in enumerate(d.four):
+        sp = np.fft.rfft(A[d.n_pos + 1 + 2 * f])
+        assert np.argmax(np.abs(sp)) == int(c) and abs(sp[int(c)].real - d.T / 2) < 1e-9
+        sp = np.fft.rfft(A[d.n_pos + 2 + 2 * f])
+        assert np.argmax(np.abs(sp)) == int(c) and abs(sp[int(c)].imag + d.T / 2) < 1e-9
