@@ -74,7 +74,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5, help="timed shots")
     ap.add_argument("--warmup", type=int, default=1, help="untimed shots")
     ap.add_argument("--nt", type=int, default=2000, help="time steps per shot")
-    ap.add_argument("--workload", default="layered128", choices=["layered128", "layered384"])
+    ap.add_argument("--workload", default="layered128", choices=["layered128", "layered384", "paper125x75x300"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle sample time")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -96,7 +96,8 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
-    w = inputs.layered128_workload(nt=args.nt) if args.workload == "layered128" else inputs.layered384_workload(nt=args.nt)
+    w = {"layered128": inputs.layered128_workload, "layered384": inputs.layered384_workload,
+         "paper125x75x300": inputs.paper_shaped_workload}[args.workload](nt=args.nt)
     nz, ny, nx = w.model.shape
     cells = nx * ny * nz
     s = binding.Solver.from_workload(w)

@@ -151,7 +151,8 @@ int pstd3d_profile_read(const pstd3d_ctx *c, int kind, double *total_ms, long *l
 /* Autotuner.  Four launch-shape knobs of a time step:
  *   PSTD_TUNE_Y, PSTD_TUNE_Z  the y and z transforms work on tiles of this
  *        many adjacent pencils (8, 16, 32 or 64, where the tile fits the LDS
- *        and register budget of its length);
+ *        and register budget of its length; y tiles of 8 only where 16 does
+ *        not fit);
  *   PSTD_TUNE_VEL, PSTD_TUNE_STR  threads per block of the velocity and the
  *        stress update kernels (x transforms fused with the split-PML
  *        updates): 128, 256 or 512, at most the cells of a block.

@@ -87,12 +87,13 @@ constexpr int rows_for(int nx) { return nx <= 32 ? 16 : nx <= 64 ? 8 : nx <= 160
 // Column-tile widths of the y and z kernels that the library is built with:
 // a tile of TX pencils of length N stages N (TX + 1) complex values in LDS
 // (at most 64 KB) and, in the z kernel, keeps N TX / NT of them per thread in
-// registers twice (spectrum and one derivative), at most 16 each.  Width 8 is
-// built only where 16 does not fit.
+// registers twice (spectrum and one derivative), at most 16 each.  y: width 8
+// only where 16 does not fit; z: width 8 always (half the LDS of 16, so twice
+// the blocks per CU, against 64-byte instead of 128-byte row segments).
 constexpr bool y_tile_ok(int n, int tx) { return (long)n * (tx + 1) * 8 + n * 8 <= 65536; }
 constexpr bool z_tile_ok(int n, int tx) { return n * tx <= 16 * 256 && (long)n * (tx + 1) * 8 + 3L * n * 8 <= 65536; }
 constexpr bool y_tile_built(int n, int tx) { return y_tile_ok(n, tx) && (tx != 8 || !y_tile_ok(n, 16)); }
-constexpr bool z_tile_built(int n, int tx) { return z_tile_ok(n, tx) && (tx != 8 || !z_tile_ok(n, 16)); }
+constexpr bool z_tile_built(int n, int tx) { return z_tile_ok(n, tx); }
 
 
 // index of spectrum element (row, kx) within one field's spectrum

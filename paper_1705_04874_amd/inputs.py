@@ -380,3 +380,24 @@ def sno_init_params(C: int, K: int, L: int, H: int, O: int, n_lift: int, seed: i
 def sno_fourier_cycles(n: int, lo: float, hi: float) -> tuple:
     """n Fourier feature frequencies (cycles per window) evenly spaced in [lo, hi]."""
     return tuple(float(v) for v in np.linspace(lo, hi, n)) if n > 0 else ()
+
+
+def paper_shaped_workload(nt=2000, seed_model=0) -> Workload:
+    """The paper's simulation shape (Sec. III-A): 125 x 75 x 300 cells (the paper's
+    301 rounded to a 2-3-5 length), dx = dy = 12.5 m, dz = 10 m, dt = 0.5 ms,
+    2000 steps, 10-cell PML; water over the top 57 cells, 6 perturbed sediment
+    layers below; one explosive source of initial pressure 1 Pa (Sec. III-A,
+    as a one-sample moment-rate wavelet w[0] = 1/dt with M = 1 Pa x dx dy dz);
+    four-component receivers at every (x, y) of the seabed plane z = 57
+    (9375 receivers)."""
+    nx, ny, nz, water = 125, 75, 300, 57
+    m = layered(nx, ny, nz, water_cells=water, seed=seed_model)
+    d = (12.5, 12.5, 10.0)
+    dt = 0.5e-3
+    rec = receiver_block(0, nx, 0, ny, water)
+    dv = d[0] * d[1] * d[2]
+    w = np.zeros((1, nt))
+    w[0, 0] = 1.0 / dt
+    return Workload("paper_shaped_125x75x300", m, d, dt, nt, 10, 2.0, 1, 0.0, rec,
+                    np.array([[nx // 2, ny // 2, 200]], np.int32), explosive(dv)[None, :],
+                    np.array([0, 1], np.int32), w)

@@ -132,3 +132,29 @@ def test_batch_of_64_shots_matches_single_shots(B):
         one = s1.run(nt).cpu().numpy()[0]
         s1.close()
         np.testing.assert_array_equal(batch[k], one)
+
+
+def test_ragged_batch_of_24_models_in_one_graph(B):
+    """The 24 uneven models of the ragged batch (64^3 ... 160x160x128, 29 M
+    cells in all) advanced together in one graph per step pair equal the same
+    models advanced one at a time with the same launch shapes."""
+    nt = 100
+    ws = inputs.ragged_models(24, nt=nt)
+    say("ragged", len(ws), sum(w.cells for w in ws))
+    ss = []
+    for w in ws:
+        s = B.Solver.from_workload(w)
+        s.set_workload_sources(w)
+        ss.append(s)
+    outs = [o.cpu().numpy() for o in B.run_many(ss, nt)]
+    for o in outs:
+        assert np.isfinite(o).all() and np.abs(o).max() > 0
+    for k in [0, 1, 13]:
+        w = ws[k]
+        s1 = B.Solver.from_workload(w)
+        s1.set_tuning(**ss[k].tuning_values())
+        s1.set_workload_sources(w)
+        np.testing.assert_array_equal(s1.run(nt).cpu().numpy(), outs[k], err_msg=w.name)
+        s1.close()
+    for s in ss:
+        s.close()
