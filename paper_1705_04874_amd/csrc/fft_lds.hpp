@@ -236,6 +236,20 @@ __host__ __device__ constexpr int plan_ns_rev(int n, int p)
     return ns;
 }
 
+// Loaders that split into fetch (loads only) and finish (arithmetic on the
+// loaded values) declare TWO_PHASE; a pass then issues all of a butterfly's
+// loads before any of the arithmetic.
+template <class Ld, class = void>
+struct TwoPhase {
+    static constexpr bool value = false;
+};
+template <class Ld>
+struct TwoPhase<Ld, decltype((void)Ld::TWO_PHASE)> {
+    static constexpr bool value = Ld::TWO_PHASE;
+};
+template <class Ld>
+__host__ __device__ constexpr bool two_phase() { return TwoPhase<Ld>::value; }
+
 // Element (pencil, i) of the LDS batch lives at s[pencil * PS + i * IS].
 // COLMAJOR: consecutive threads take consecutive pencils (use when PS == 1,
 // i.e. pencils interleaved column-wise); otherwise consecutive elements.
@@ -262,10 +276,20 @@ __device__ __forceinline__ void fft_pass(float2* s, const float2* tw, const Ld& 
             const int pen = COLMAJOR ? b % NPEN : b / M;
             const int j = COLMAJOR ? b / NPEN : b - pen * M;
             const int k = j % NS;
+            if constexpr (FROM_G && two_phase<Ld>()) {
+                // every load of the butterfly first, then the arithmetic on them
+                typename Ld::Raw raw[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if constexpr (FROM_G) a[q][r] = ld(pen, j + r * M);
-                else a[q][r] = s[pen * PS + lidx<PAD>(j + r * M) * IS];
+                for (int r = 0; r < R; ++r) raw[r] = ld.fetch(pen, j + r * M);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int r = 0; r < R; ++r) a[q][r] = ld.finish(raw[r], j + r * M);
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if constexpr (FROM_G) a[q][r] = ld(pen, j + r * M);
+                    else a[q][r] = s[pen * PS + lidx<PAD>(j + r * M) * IS];
+                }
             }
             if (NS > 1) {
 #pragma unroll

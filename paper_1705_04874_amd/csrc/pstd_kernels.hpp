@@ -84,6 +84,21 @@ struct ZDesc {
 
 constexpr int rows_for(int nx) { return nx <= 32 ? 16 : nx <= 64 ? 8 : nx <= 160 ? 4 : 2; }
 
+// Load through a pointer that addresses global memory.  Pointers read from a
+// device-resident descriptor are generic to the compiler, and a generic load
+// also holds the LDS wait counter, so every LDS wait after it would wait for
+// the memory load as well.
+__device__ __forceinline__ float gld(const float* p)
+{
+    return *(const __attribute__((address_space(1))) float*)p;
+}
+__device__ __forceinline__ float2 gld(const float2* p)
+{
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    const f2v v = *(const __attribute__((address_space(1))) f2v*)p;
+    return make_float2(v.x, v.y);
+}
+
 // Column-tile widths of the y and z kernels that the library is built with:
 // a tile of TX pencils of length N stages N (TX + 1) complex values in LDS
 // (at most 64 KB) and, in the z kernel, keeps N TX / NT of them per thread in
@@ -102,13 +117,16 @@ __device__ __forceinline__ long spec_idx(const Geo& g, int row, int k)
     return k < g.nxm ? (long)row * g.ldx + k : g.nqoff + row;
 }
 
-// value of real pencil p (= field * ROWS + local row) of a spectrum row
+// value of real pencil p (= field * ROWS + local row) of a spectrum row.  Rows
+// past the grid (only in the last block of a ragged row count) read the last
+// row instead: their pencils are transformed on their own and never stored,
+// and no branch separates the loads of a pass, so all of them are issued
+// before the first wait
 __device__ __forceinline__ float2 spec_at(const float2* __restrict__ base, const Geo& g, int rows,
                                           int row0, int p, int k)
 {
     const int f = p / rows, r = p - f * rows;
-    const int row = row0 + r;
-    if (row >= g.nrows) return make_float2(0.f, 0.f);
+    const int row = min(row0 + r, g.nrows - 1);
     return base[f * g.nspec + spec_idx(g, row, k)];
 }
 
@@ -121,15 +139,27 @@ struct HermLoader {
     const float2* __restrict__ src;
     Geo g;
     int row0;
-    __device__ float2 operator()(int q, int i) const
+    // Two phases, so that a pass issues the loads of all its elements before
+    // the first wait: fetch() loads the two half-spectrum values at
+    // k = min(i, NX - i); finish() combines them branch free with
+    // w = sign(2 i - NX) (0 at DC and at the Nyquist bin):
+    // Z_i = (a.x + w b.y) + i (b.x - w a.y)
+    static constexpr bool TWO_PHASE = true;
+    using Raw = float4;
+    __device__ float4 fetch(int q, int i) const
     {
-        const bool hi = 2 * i > NX;
-        const int k = hi ? NX - i : i;
+        const int k = min(i, NX - i);
         const float2 a = spec_at(src, g, ROWS, row0, 2 * q, k);
         const float2 b = spec_at(src, g, ROWS, row0, 2 * q + 1, k);
-        if (k == 0 || 2 * k == NX) return make_float2(a.x, b.x);
-        return hi ? make_float2(a.x + b.y, b.x - a.y) : make_float2(a.x - b.y, a.y + b.x);
+        return make_float4(a.x, a.y, b.x, b.y);
     }
+    __device__ float2 finish(float4 v, int i) const
+    {
+        const int sg = (2 * i > NX) - (2 * i < NX);
+        const float w = (float)(i == 0 ? 0 : sg);
+        return make_float2(fmaf(w, v.w, v.x), fmaf(-w, v.y, v.z));
+    }
+    __device__ float2 operator()(int q, int i) const { return finish(fetch(q, i), i); }
 };
 
 // Unpack NPO complex forward transforms of paired real rows into half spectra.
@@ -311,7 +341,9 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
     for (int i = threadIdx.x; i < NX; i += NT) tw[i] = twx[i];
     fft_ld<NX, NPI, NT, +1, PS, 1, false, false, HermLoader<NX, ROWS>, NoSt, true>(s, tw, HermLoader<NX, ROWS>{D9, g, row0}, NoSt{});
 
-    float ssum[CPT][6];
+    // the loads of every cell of this thread before any store (the split parts
+    // share one base pointer, so a store would serialise later loads)
+    float sp[CPT][15], mt[CPT][5];
     bool ok[CPT];
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
@@ -319,17 +351,30 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
         const int r = c / NX, x = c - r * NX;
         const int row = row0 + r;
         ok[i] = c < ROWS * NX && row < g.nrows;
+        const long cell = (long)(ok[i] ? row : row0) * NX + x;
+#pragma unroll
+        for (int q = 0; q < 15; ++q) sp[i][q] = F[(long)q * g.n + cell];
+        mt[i][0] = m.dlam[cell];
+        mt[i][1] = m.dmu2[cell];
+        mt[i][2] = m.dmus[0][cell];
+        mt[i][3] = m.dmus[1][cell];
+        mt[i][4] = m.dmus[2][cell];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+
+    float ssum[CPT][6];
+#pragma unroll
+    for (int i = 0; i < CPT; ++i) {
+        const int c = threadIdx.x + i * NT;
+        const int r = c / NX, x = c - r * NX;
+        const int row = row0 + r;
 #pragma unroll
         for (int q = 0; q < 6; ++q) ssum[i][q] = 0.f;
         if (!ok[i]) continue;
         const int y = row % g.ny, z = row / g.ny;
         const long cell = (long)row * NX + x;
-        // this cell's loads first (the split parts share one base pointer)
-        float sp[15];
-#pragma unroll
-        for (int q = 0; q < 15; ++q) sp[q] = F[(long)q * g.n + cell];
-        const float dlam = m.dlam[cell], dmu2 = m.dmu2[cell];
-        const float mxy = m.dmus[0][cell], mxz = m.dmus[1][cell], myz = m.dmus[2][cell];
+        const float dlam = mt[i][0], dmu2 = mt[i][1];
+        const float mxy = mt[i][2], mxz = mt[i][3], myz = mt[i][4];
         const float bxi = pm.bi[0][x], bxh = pm.bh[0][x];
         const float byi = pm.bi[1][y], byh = pm.bh[1][y];
         const float bzi = pm.bi[2][z], bzh = pm.bh[2][z];
@@ -344,22 +389,22 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
         float e[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) e[q] = pencil_val<PS>(s, q * ROWS + r, x);
-        // normal parts sp[3c + d] (component c, axis d)
+        // normal parts sp[i][3c + d] (component c, axis d)
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const float coef = cc == d ? dlam + dmu2 : dlam;
-                sp[3 * cc + d] = ai[d] * (ai[d] * sp[3 * cc + d] + coef * e[d]);
+                sp[i][3 * cc + d] = ai[d] * (ai[d] * sp[i][3 * cc + d] + coef * e[d]);
             }
         // shear parts: 9 sxy(x) <- Dx+ vy, 10 sxy(y) <- Dy+ vx, 11 sxz(x) <- Dx+ vz,
         //              12 sxz(z) <- Dz+ vx, 13 syz(y) <- Dy+ vz, 14 syz(z) <- Dz+ vy
-        sp[9] = axy_x * (axy_x * sp[9] + mxy * e[4]);
-        sp[10] = axy_y * (axy_y * sp[10] + mxy * e[3]);
-        sp[11] = axz_x * (axz_x * sp[11] + mxz * e[6]);
-        sp[12] = axz_z * (axz_z * sp[12] + mxz * e[5]);
-        sp[13] = ayz_y * (ayz_y * sp[13] + myz * e[8]);
-        sp[14] = ayz_z * (ayz_z * sp[14] + myz * e[7]);
+        sp[i][9] = axy_x * (axy_x * sp[i][9] + mxy * e[4]);
+        sp[i][10] = axy_y * (axy_y * sp[i][10] + mxy * e[3]);
+        sp[i][11] = axz_x * (axz_x * sp[i][11] + mxz * e[6]);
+        sp[i][12] = axz_z * (axz_z * sp[i][12] + mxz * e[5]);
+        sp[i][13] = ayz_y * (ayz_y * sp[i][13] + myz * e[8]);
+        sp[i][14] = ayz_z * (ayz_z * sp[i][14] + myz * e[7]);
         // point sources of this shot in this row
         const int j0 = iptr[row], j1 = iptr[row + 1];
         if (j0 != j1 && step < inj.nt_w) {
@@ -369,17 +414,17 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
                 const float val = __int_as_float(q.z) * inj.wav[(long)q.w * inj.nt_w + step];
 #pragma unroll
                 for (int f = 0; f < 15; ++f)
-                    if (q.y == f) sp[f] += val;
+                    if (q.y == f) sp[i][f] += val;
             }
         }
 #pragma unroll
-        for (int q = 0; q < 15; ++q) F[(long)q * g.n + cell] = sp[q];
-        ssum[i][0] = sp[0] + sp[1] + sp[2];
-        ssum[i][1] = sp[3] + sp[4] + sp[5];
-        ssum[i][2] = sp[6] + sp[7] + sp[8];
-        ssum[i][3] = sp[9] + sp[10];
-        ssum[i][4] = sp[11] + sp[12];
-        ssum[i][5] = sp[13] + sp[14];
+        for (int q = 0; q < 15; ++q) F[(long)q * g.n + cell] = sp[i][q];
+        ssum[i][0] = sp[i][0] + sp[i][1] + sp[i][2];
+        ssum[i][1] = sp[i][3] + sp[i][4] + sp[i][5];
+        ssum[i][2] = sp[i][6] + sp[i][7] + sp[i][8];
+        ssum[i][3] = sp[i][9] + sp[i][10];
+        ssum[i][4] = sp[i][11] + sp[i][12];
+        ssum[i][5] = sp[i][13] + sp[i][14];
     }
     __syncthreads();
 #pragma unroll
@@ -479,9 +524,12 @@ struct Tile {
     float2* __restrict__ base;
     long cs, is;
     int ncol;
+    // columns past the array read the last column (unconditional load, no
+    // branch between the loads of a pass) and give zero
     __device__ float2 operator()(int c, int i) const
     {
-        return c < ncol ? base[c * cs + i * is] : make_float2(0.f, 0.f);
+        const float2 v = base[min(c, ncol - 1) * cs + i * is];
+        return c < ncol ? v : make_float2(0.f, 0.f);
     }
     __device__ void operator()(int c, int i, float2 v) const
     {
@@ -535,6 +583,7 @@ __global__ __launch_bounds__(NT) void k_z(Geo g, const float2* __restrict__ twz,
     __shared__ float2 s[NZ * IS];
     __shared__ float2 tw[NZ];
     __shared__ float2 symz[2][NZ];
+    __shared__ float2 symc[2][2][TX];
     const int tmain = (g.nxm + TX - 1) / TX;
     const int shot = blockIdx.z / ph.nin, fi = blockIdx.z % ph.nin;
     long off, zs;
@@ -562,8 +611,14 @@ __global__ __launch_bounds__(NT) void k_z(Geo g, const float2* __restrict__ twz,
     }
     for (int i = threadIdx.x; i < NZ; i += NT) {
         tw[i] = twz[i];
-        symz[0][i] = ops.sym[2][0][i];
-        symz[1][i] = ops.sym[2][1][i];
+        symz[0][i] = gld(ops.sym[2][0] + i);
+        symz[1][i] = gld(ops.sym[2][1] + i);
+    }
+    // x and y symbols of this tile's columns (main tiles: kx0 + c and ky0;
+    // Nyquist tile: nx/2 and ky0 + c), so that the multiply loop reads LDS only
+    for (int i = threadIdx.x; i < 4 * TX; i += NT) {
+        const int ax = i / (2 * TX), pl = (i / TX) & 1, c = min(i % TX, ncol - 1);
+        symc[ax][pl][i % TX] = gld(ops.sym[ax][pl] + (ax == 0 ? kx0 + kxc * c : ky0 + kyc * c));
     }
     __syncthreads();
     // kappa of the elements this thread multiplies (issued before the forward FFT)
@@ -574,7 +629,10 @@ __global__ __launch_bounds__(NT) void k_z(Geo g, const float2* __restrict__ twz,
         for (int r = 0; r < RL; ++r) {
             int c, z;
             const bool ok = reg_coords<NZ, RL, TX, NT, true>(q, r, c, z);
-            kr[q][r] = (ok && c < ncol) ? kap[z * zs + c] : 0.f;
+            // unconditional load (no branch between the loads) at a valid
+            // element: slots past the last butterfly (ok false) carry z >= NZ
+            const float kv = gld(kap + (ok ? z : 0) * zs + min(c, ncol - 1));
+            kr[q][r] = (ok && c < ncol) ? kv : 0.f;
         }
     float2* __restrict__ sb = spec + (long)shot * g.sstride;
     const Tile in{sb + (long)(in0 + fi) * g.nspec + off, 1, zs, ncol};
@@ -582,7 +640,9 @@ __global__ __launch_bounds__(NT) void k_z(Geo g, const float2* __restrict__ twz,
     fft_g2r<NZ, TX, NT, -1, 1, IS, true>(s, tw, in, X);
     for (int o = 0; o < ph.nout[fi]; ++o) {
         const int axis = ph.axis[fi][o], plus = ph.plus[fi][o];
-        const float2* __restrict__ sym = ops.sym[axis][plus];
+        // symbol table of this output: along z indexed by z, along x or y by column
+        const float2* tab = axis == 2 ? symz[plus] : symc[axis][plus];
+        const bool byz = axis == 2;
         float2 Y[QL][RL];
 #pragma unroll
         for (int q = 0; q < QL; ++q)
@@ -590,10 +650,7 @@ __global__ __launch_bounds__(NT) void k_z(Geo g, const float2* __restrict__ twz,
             for (int r = 0; r < RL; ++r) {
                 int c, z;
                 reg_coords<NZ, RL, TX, NT, true>(q, r, c, z);
-                float2 sv;
-                if (axis == 2) sv = symz[plus][z];
-                else if (axis == 0) sv = sym[kx0 + kxc * min(c, ncol - 1)];
-                else sv = sym[ky0 + kyc * min(c, ncol - 1)];
+                const float2 sv = tab[byz ? z : c];
                 Y[q][r] = c_scale(c_mul(sv, X[q][r]), kr[q][r]);
             }
         __syncthreads();   // s was read by the previous pass
