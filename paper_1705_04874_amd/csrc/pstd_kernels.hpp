@@ -341,9 +341,11 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
     for (int i = threadIdx.x; i < NX; i += NT) tw[i] = twx[i];
     fft_ld<NX, NPI, NT, +1, PS, 1, false, false, HermLoader<NX, ROWS>, NoSt, true>(s, tw, HermLoader<NX, ROWS>{D9, g, row0}, NoSt{});
 
-    // the loads of every cell of this thread before any store (the split parts
-    // share one base pointer, so a store would serialise later loads)
-    float sp[CPT][15], mt[CPT][5];
+    // every load of every cell of this thread before any arithmetic or store
+    // (the split parts share one base pointer, so a store would serialise
+    // later loads): split parts, materials, PML factors, source rows
+    float sp[CPT][15], mt[CPT][5], fa[CPT][9];
+    int jr[CPT][2];
     bool ok[CPT];
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
@@ -351,7 +353,9 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
         const int r = c / NX, x = c - r * NX;
         const int row = row0 + r;
         ok[i] = c < ROWS * NX && row < g.nrows;
-        const long cell = (long)(ok[i] ? row : row0) * NX + x;
+        const int rr = ok[i] ? row : row0;
+        const int y = rr % g.ny, z = rr / g.ny;
+        const long cell = (long)rr * NX + x;
 #pragma unroll
         for (int q = 0; q < 15; ++q) sp[i][q] = F[(long)q * g.n + cell];
         mt[i][0] = m.dlam[cell];
@@ -359,6 +363,22 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
         mt[i][2] = m.dmus[0][cell];
         mt[i][3] = m.dmus[1][cell];
         mt[i][4] = m.dmus[2][cell];
+        const float bxi = pm.bi[0][x], bxh = pm.bh[0][x];
+        const float byi = pm.bi[1][y], byh = pm.bh[1][y];
+        const float bzi = pm.bi[2][z], bzh = pm.bh[2][z];
+        // normal parts (centre nodes): a_d times b of the other two axes
+        fa[i][0] = pm.ai[0][x] * byi * bzi;
+        fa[i][1] = pm.ai[1][y] * bxi * bzi;
+        fa[i][2] = pm.ai[2][z] * bxi * byi;
+        // shear parts at their nodes: xy (h,h,i), xz (h,i,h), yz (i,h,h)
+        fa[i][3] = pm.ah[0][x] * byh * bzi;   // xy, x part
+        fa[i][4] = pm.ah[1][y] * bxh * bzi;   // xy, y part
+        fa[i][5] = pm.ah[0][x] * byi * bzh;   // xz, x part
+        fa[i][6] = pm.ah[2][z] * bxh * byi;   // xz, z part
+        fa[i][7] = pm.ah[1][y] * bxi * bzh;   // yz, y part
+        fa[i][8] = pm.ah[2][z] * bxi * byh;   // yz, z part
+        jr[i][0] = iptr[rr];
+        jr[i][1] = iptr[rr + 1];
     }
     __builtin_amdgcn_sched_barrier(0);
 
@@ -371,19 +391,12 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
 #pragma unroll
         for (int q = 0; q < 6; ++q) ssum[i][q] = 0.f;
         if (!ok[i]) continue;
-        const int y = row % g.ny, z = row / g.ny;
         const long cell = (long)row * NX + x;
         const float dlam = mt[i][0], dmu2 = mt[i][1];
         const float mxy = mt[i][2], mxz = mt[i][3], myz = mt[i][4];
-        const float bxi = pm.bi[0][x], bxh = pm.bh[0][x];
-        const float byi = pm.bi[1][y], byh = pm.bh[1][y];
-        const float bzi = pm.bi[2][z], bzh = pm.bh[2][z];
-        // normal parts (centre nodes): a_d times b of the other two axes
-        const float ai[3] = {pm.ai[0][x] * byi * bzi, pm.ai[1][y] * bxi * bzi, pm.ai[2][z] * bxi * byi};
-        // shear parts at their nodes: xy (h,h,i), xz (h,i,h), yz (i,h,h)
-        const float axy_x = pm.ah[0][x] * byh * bzi, axy_y = pm.ah[1][y] * bxh * bzi;
-        const float axz_x = pm.ah[0][x] * byi * bzh, axz_z = pm.ah[2][z] * bxh * byi;
-        const float ayz_y = pm.ah[1][y] * bxi * bzh, ayz_z = pm.ah[2][z] * bxi * byh;
+        const float ai[3] = {fa[i][0], fa[i][1], fa[i][2]};
+        const float axy_x = fa[i][3], axy_y = fa[i][4], axz_x = fa[i][5], axz_z = fa[i][6];
+        const float ayz_y = fa[i][7], ayz_z = fa[i][8];
         // derivatives: e0..e2 = D_d^- v_d, e3 = Dy+ vx, e4 = Dx+ vy, e5 = Dz+ vx,
         //              e6 = Dx+ vz, e7 = Dz+ vy, e8 = Dy+ vz
         float e[9];
@@ -406,7 +419,7 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
         sp[i][13] = ayz_y * (ayz_y * sp[i][13] + myz * e[8]);
         sp[i][14] = ayz_z * (ayz_z * sp[i][14] + myz * e[7]);
         // point sources of this shot in this row
-        const int j0 = iptr[row], j1 = iptr[row + 1];
+        const int j0 = jr[i][0], j1 = jr[i][1];
         if (j0 != j1 && step < inj.nt_w) {
             for (int j = j0; j < j1; ++j) {
                 const int4 q = inj.ent[j];
