@@ -94,6 +94,18 @@ int pstd3d_create(const pstd3d_model *m, const double d[3], double dt, const pst
 int pstd3d_set_sources(pstd3d_ctx *c, int n_shots, const int32_t *shot_ofs, const int32_t *src_ijk,
                        const double *m6, const double *wavelet, int nt_w);
 
+/* Source smoothing for the following pstd3d_set_sources calls (Sec. II-A: the
+ * point source's delta is smoothed with a Blackman window in the
+ * spatial-frequency domain to limit the oscillations a discrete delta causes
+ * with Fourier derivatives).  PSTD_SMOOTH_BLACKMAN applies on every axis the
+ * window W(k) = 0.42 + 0.5 cos(k h) + 0.08 cos(2 k h) over [-pi/h, pi/h]
+ * (zero at the edges, W(0) = 1 so the moment is kept); in space it is the
+ * separable stencil (0.04, 0.25, 0.42, 0.25, 0.04) around the source cell,
+ * periodic at the grid edges: 125 point sources of weights summing to 1. */
+#define PSTD_SMOOTH_NONE 0
+#define PSTD_SMOOTH_BLACKMAN 1
+int pstd3d_set_source_smoothing(pstd3d_ctx *c, int window);
+
 /* Advance every shot by nt steps on `hip_stream` (a hipStream_t, may be
  * NULL for the null stream) and write the receiver traces of those steps to
  * the caller-owned device buffer traces_dev [n_shots][4][n_rec][nt].

@@ -30,6 +30,12 @@
  *  - a source adds -dt w[n] M_cd / dV to each stress component, split equally
  *    over the split parts; shear parts are spread 1/4 to each of the 4 shear
  *    nodes around the cell centre;
+ *  - optional source smoothing (Sec. II-A: the delta is smoothed with a
+ *    Blackman window in the spatial-frequency domain): the point source's
+ *    delta is transformed, multiplied by W(k) = prod_d [0.42 + 0.5 cos(k_d h_d)
+ *    + 0.08 cos(2 k_d h_d)] (a Blackman window over [-pi/h_d, pi/h_d] on each
+ *    axis, zero at the edges) and transformed back; every cell of the result
+ *    (up to round-off) then carries a point source of that weight;
  *  - v is recorded at time (n + 1/2) dt, p at (n + 1) dt.
  *
  * Everything is evaluated plainly: each derivative is a full complex 3-D FFT of
@@ -68,6 +74,11 @@ struct ostate {
     int n_src, nt_w;
     int *src;
     double *m6, *wav;
+    /* source smoothing (0 off, 1 Blackman window in k-space): per source the
+     * cells [sm_ofs[q], sm_ofs[q+1]) of sm_ijk / sm_w carry weight sm_w */
+    int smooth;
+    int *sm_ofs, *sm_ijk;
+    double *sm_w;
     int n_rec;
     int *rec;
     long step;
@@ -124,6 +135,9 @@ static void free_state(ostate *s)
     free(s->src);
     free(s->m6);
     free(s->wav);
+    free(s->sm_ofs);
+    free(s->sm_ijk);
+    free(s->sm_w);
     free(s->rec);
     free(s);
 }
@@ -275,6 +289,92 @@ ostate *opstd_create(int nx, int ny, int nz, const double *vp, const double *vs,
     return s;
 }
 
+int opstd_set_source_smoothing(ostate *s, int window)
+{
+    if (window != 0 && window != 1) return ORC_EINVAL;
+    s->smooth = window;
+    return ORC_OK;
+}
+
+/* wavenumber of index m on an axis of n cells of size h */
+static double kwave(int m, int n, double h)
+{
+    int mm = m <= n / 2 ? m : m - n;
+    return 2.0 * M_PI * mm / (n * h);
+}
+
+/* Smoothed delta of every source: FFT of the delta, times the separable
+ * Blackman window, inverse FFT; cells whose weight is round-off (below 1e-12)
+ * are dropped. */
+static int build_smoothing(ostate *s)
+{
+    free(s->sm_ofs);
+    free(s->sm_ijk);
+    free(s->sm_w);
+    s->sm_ofs = NULL;
+    s->sm_ijk = NULL;
+    s->sm_w = NULL;
+    if (!s->smooth) return ORC_OK;
+    int nx = s->nx, ny = s->ny, nz = s->nz;
+    long cap = 256, cnt = 0;
+    s->sm_ofs = malloc(sizeof(int) * (s->n_src + 1));
+    s->sm_ijk = malloc(sizeof(int) * 3 * cap);
+    s->sm_w = malloc(sizeof(double) * cap);
+    if (!s->sm_ofs || !s->sm_ijk || !s->sm_w) return ORC_ENOMEM;
+    double *wx = malloc(sizeof(double) * nx), *wy = malloc(sizeof(double) * ny), *wz = malloc(sizeof(double) * nz);
+    const int N[3] = {nx, ny, nz};
+    double *W[3] = {wx, wy, wz};
+    for (int d = 0; d < 3; ++d)
+        for (int m = 0; m < N[d]; ++m) {
+            double kh = kwave(m, N[d], s->h[d]) * s->h[d];
+            W[d][m] = 0.42 + 0.5 * cos(kh) + 0.08 * cos(2.0 * kh);
+        }
+    for (int q = 0; q < s->n_src; ++q) {
+        s->sm_ofs[q] = (int)cnt;
+        const int *p = s->src + 3 * q;
+        memset(s->A, 0, sizeof(double complex) * s->n);
+        s->A[IDX(s, p[0], p[1], p[2])] = 1.0;
+        offt_3d(s->A, nx, ny, nz, -1);
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) s->A[IDX(s, i, j, k)] *= wx[i] * wy[j] * wz[k];
+        offt_3d(s->A, nx, ny, nz, +1);
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    double w = creal(s->A[IDX(s, i, j, k)]);
+                    if (fabs(w) < 1e-12) continue;
+                    if (cnt == cap) {
+                        cap *= 2;
+                        s->sm_ijk = realloc(s->sm_ijk, sizeof(int) * 3 * cap);
+                        s->sm_w = realloc(s->sm_w, sizeof(double) * cap);
+                        if (!s->sm_ijk || !s->sm_w) return ORC_ENOMEM;
+                    }
+                    s->sm_ijk[3 * cnt] = i;
+                    s->sm_ijk[3 * cnt + 1] = j;
+                    s->sm_ijk[3 * cnt + 2] = k;
+                    s->sm_w[cnt] = w;
+                    ++cnt;
+                }
+    }
+    s->sm_ofs[s->n_src] = (int)cnt;
+    free(wx);
+    free(wy);
+    free(wz);
+    return ORC_OK;
+}
+
+int opstd_smoothed_source(ostate *s, int q, int max, int *ijk, double *w)
+{
+    if (!s->smooth || q < 0 || q >= s->n_src) return ORC_EINVAL;
+    int n = s->sm_ofs[q + 1] - s->sm_ofs[q];
+    for (int e = 0; e < n && e < max; ++e) {
+        for (int a = 0; a < 3; ++a) ijk[3 * e + a] = s->sm_ijk[3 * (s->sm_ofs[q] + e) + a];
+        w[e] = s->sm_w[s->sm_ofs[q] + e];
+    }
+    return n;
+}
+
 int opstd_set_sources(ostate *s, int n_src, const int *src_ijk, const double *m6,
                       const double *wavelet, int nt_w)
 {
@@ -297,6 +397,8 @@ int opstd_set_sources(ostate *s, int n_src, const int *src_ijk, const double *m6
         memcpy(s->m6, m6, sizeof(double) * 6 * n_src);
         memcpy(s->wav, wavelet, sizeof(double) * (long)n_src * nt_w);
     }
+    int rc = build_smoothing(s);
+    if (rc != ORC_OK) return rc;
     for (int c = 0; c < 3; ++c)
         for (int d = 0; d < 3; ++d) {
             memset(s->v[c][d], 0, sizeof(double) * s->n);
@@ -527,36 +629,45 @@ static void stress_step(ostate *s)
     free(g21);
 }
 
-static void inject(ostate *s)
+/* point source of moment weight * M at cell p */
+static void inject_point(ostate *s, const int *p, const double *m, double weight, double w)
 {
-    if (s->step >= s->nt_w) return;
     double dv = s->h[0] * s->h[1] * s->h[2];
     int nx = s->nx, ny = s->ny, nz = s->nz;
     static const int pair_axes[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    long c = IDX(s, p[0], p[1], p[2]);
+    for (int comp = 0; comp < 3; ++comp) {
+        double val = -s->dt * w * weight * m[comp] / dv;
+        for (int d = 0; d < 3; ++d) s->sn[comp][d][c] += val / 3.0;
+    }
+    /* shear pair p sits half a cell up along both of its axes: the four
+     * nodes around the centre are offsets {-1, 0} along those two axes */
+    for (int pr = 0; pr < 3; ++pr) {
+        double val = -s->dt * w * weight * m[3 + pr] / dv;
+        int a0 = pair_axes[pr][0], a1 = pair_axes[pr][1];
+        for (int o0 = -1; o0 <= 0; ++o0)
+            for (int o1 = -1; o1 <= 0; ++o1) {
+                int ix[3] = {p[0], p[1], p[2]};
+                int N[3] = {nx, ny, nz};
+                ix[a0] = (ix[a0] + o0 + N[a0]) % N[a0];
+                ix[a1] = (ix[a1] + o1 + N[a1]) % N[a1];
+                long cc = IDX(s, ix[0], ix[1], ix[2]);
+                s->ss[pr][0][cc] += val / 8.0;
+                s->ss[pr][1][cc] += val / 8.0;
+            }
+    }
+}
+
+static void inject(ostate *s)
+{
+    if (s->step >= s->nt_w) return;
     for (int q = 0; q < s->n_src; ++q) {
-        const int *p = s->src + 3 * q;
         const double *m = s->m6 + 6 * q;
         double w = s->wav[(long)q * s->nt_w + s->step];
-        long c = IDX(s, p[0], p[1], p[2]);
-        for (int comp = 0; comp < 3; ++comp) {
-            double val = -s->dt * w * m[comp] / dv;
-            for (int d = 0; d < 3; ++d) s->sn[comp][d][c] += val / 3.0;
-        }
-        /* shear pair p sits half a cell up along both of its axes: the four
-         * nodes around the centre are offsets {-1, 0} along those two axes */
-        for (int pr = 0; pr < 3; ++pr) {
-            double val = -s->dt * w * m[3 + pr] / dv;
-            int a0 = pair_axes[pr][0], a1 = pair_axes[pr][1];
-            for (int o0 = -1; o0 <= 0; ++o0)
-                for (int o1 = -1; o1 <= 0; ++o1) {
-                    int ix[3] = {p[0], p[1], p[2]};
-                    int N[3] = {nx, ny, nz};
-                    ix[a0] = (ix[a0] + o0 + N[a0]) % N[a0];
-                    ix[a1] = (ix[a1] + o1 + N[a1]) % N[a1];
-                    long cc = IDX(s, ix[0], ix[1], ix[2]);
-                    s->ss[pr][0][cc] += val / 8.0;
-                    s->ss[pr][1][cc] += val / 8.0;
-                }
+        if (!s->smooth) {
+            inject_point(s, s->src + 3 * q, m, 1.0, w);
+        } else {
+            for (int e = s->sm_ofs[q]; e < s->sm_ofs[q + 1]; ++e) inject_point(s, s->sm_ijk + 3 * e, m, s->sm_w[e], w);
         }
     }
 }

@@ -31,6 +31,10 @@ ostate *opstd_create(int nx, int ny, int nz, const double *vp, const double *vs,
 int opstd_set_sources(ostate *s, int n_src, const int *src_ijk, const double *m6,
                       const double *wavelet, int nt_w);
 int opstd_run(ostate *s, int nt, double *traces);
+/* Source smoothing for the next opstd_set_sources: 0 off, 1 Blackman window in k-space. */
+int opstd_set_source_smoothing(ostate *s, int window);
+/* Cells (ijk, up to max) and weights of source q's smoothed delta; returns the count. */
+int opstd_smoothed_source(ostate *s, int q, int max, int *ijk, double *w);
 void opstd_get_state(const ostate *s, double *fields);
 void opstd_set_state(ostate *s, const double *fields);
 long opstd_step_index(const ostate *s);

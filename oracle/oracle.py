@@ -41,6 +41,8 @@ def lib():
                                    C.c_double, C.c_int, ip, ip]
         L.opstd_set_sources.argtypes = [C.c_void_p, C.c_int, ip, dp, dp, C.c_int]
         L.opstd_run.argtypes = [C.c_void_p, C.c_int, dp]
+        L.opstd_set_source_smoothing.argtypes = [C.c_void_p, C.c_int]
+        L.opstd_smoothed_source.argtypes = [C.c_void_p, C.c_int, C.c_int, ip, dp]
         L.opstd_get_state.argtypes = [C.c_void_p, dp]
         L.opstd_set_state.argtypes = [C.c_void_p, dp]
         L.opstd_step_index.argtypes = [C.c_void_p]
@@ -129,7 +131,25 @@ class Solver:
         kw = dict(d=w.d, dt=w.dt, pml=w.pml, pml_A=w.pml_A, pml_p=w.pml_p, kspace=w.kspace, c_ref=w.c_ref,
                   rec=w.rec)
         kw.update(over)
-        return cls(w.model.vp, w.model.vs, w.model.rho, **kw)
+        s = cls(w.model.vp, w.model.vs, w.model.rho, **kw)
+        if getattr(w, "smooth", 0):
+            s.set_source_smoothing(w.smooth)
+        return s
+
+    def set_source_smoothing(self, window):
+        """0: point sources; 1: Blackman window in k-space (next set_sources)."""
+        rc = lib().opstd_set_source_smoothing(self._h, int(window))
+        if rc:
+            raise OracleError(rc, "set_source_smoothing")
+
+    def smoothed_source(self, q, max_cells=4096):
+        """(ijk [n][3], weights [n]) of source q's smoothed delta."""
+        ijk = np.zeros((max_cells, 3), np.int32)
+        w = np.zeros(max_cells)
+        n = lib().opstd_smoothed_source(self._h, int(q), max_cells, _ip(ijk), _dp(w))
+        if n < 0:
+            raise OracleError(n, "smoothed_source")
+        return ijk[:n], w[:n]
 
     def set_sources(self, src_ijk, m6, wavelet):
         src = _i32(src_ijk).reshape(-1, 3)

@@ -50,6 +50,7 @@ _L.pstd3d_derivs.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_vo
 _L.pstd3d_reset.argtypes = [C.c_void_p, C.c_void_p]
 _L.pstd3d_profile.argtypes = [C.c_void_p, C.c_int]
 _L.pstd3d_profile_read.argtypes = [C.c_void_p, C.c_int, _dp, C.POINTER(C.c_long)]
+_L.pstd3d_set_source_smoothing.argtypes = [C.c_void_p, C.c_int]
 _L.pstd3d_set_tuning.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
 _L.pstd3d_get_tuning.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _fp, C.c_int]
 TUNE_KNOBS = ("y_tile", "z_tile", "vel_threads", "str_threads")
@@ -111,7 +112,14 @@ class Solver:
         kw = dict(d=w.d, dt=w.dt, pml=w.pml, pml_A=w.pml_A, pml_p=w.pml_p, kspace=w.kspace, c_ref=w.c_ref,
                   rec=w.rec)
         kw.update(over)
-        return cls(w.model.vp, w.model.vs, w.model.rho, **kw)
+        s = cls(w.model.vp, w.model.vs, w.model.rho, **kw)
+        if getattr(w, "smooth", 0):
+            s.set_source_smoothing(w.smooth)
+        return s
+
+    def set_source_smoothing(self, window):
+        """0: point sources; 1: Blackman window in k-space (for later set_sources)."""
+        _check(_L.pstd3d_set_source_smoothing(self._h, int(window)), "pstd3d_set_source_smoothing")
 
     def set_tuning(self, y_tile=0, z_tile=0, vel_threads=0, str_threads=0):
         """Force launch-shape knobs (0: autotuned at the next set_sources)."""

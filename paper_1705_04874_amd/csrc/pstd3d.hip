@@ -306,6 +306,7 @@ struct pstd3d_ctx {
     int force[PSTD_TUNE_COUNT] = {0, 0, 0, 0};
     int sel[PSTD_TUNE_COUNT] = {0, 0, 0, 0};
     bool tuned = false;
+    int smooth = 0;            // source smoothing for the next set_sources (0 off, 1 Blackman)
     float tune_us[PSTD_TUNE_COUNT][MAX_VARIANTS] = {};   // measured us per launch of each variant
     YFns yf{};                 // the chosen variants
     ZFns zf{};
@@ -866,12 +867,14 @@ int pstd3d_set_sources(pstd3d_ctx* c, int n_shots, const int32_t* shot_ofs, cons
     static const int pair_axes[3][2] = {{0, 1}, {0, 2}, {1, 2}};
     for (int s = 0; s < n_shots; ++s) {
         std::vector<std::pair<long, int4>> es;   // (row, entry)
-        for (int q = shot_ofs[s]; q < shot_ofs[s + 1]; ++q) {
-            const int32_t* p = src_ijk + 3 * q;
-            const double* M = m6 + 6 * q;
+        const int N[3] = {nx, ny, nz};
+        // point source of moment weight * M at cell p: normal components split
+        // 1/3 over their split parts, shear components 1/4 on the 4 shear nodes
+        // around the centre, 1/2 on each of their two split parts
+        auto point = [&](const int* p, const double* M, double weight, int q) {
             for (int cc = 0; cc < 3; ++cc) {
                 if (M[cc] == 0.0) continue;
-                const float coef = (float)(-c->dt * M[cc] / dV / 3.0);
+                const float coef = (float)(-c->dt * weight * M[cc] / dV / 3.0);
                 for (int d = 0; d < 3; ++d) {
                     int4 e = make_int4(p[0], 3 * cc + d, __builtin_bit_cast(int, coef), q);
                     es.push_back({(long)p[1] + (long)ny * p[2], e});
@@ -879,9 +882,8 @@ int pstd3d_set_sources(pstd3d_ctx* c, int n_shots, const int32_t* shot_ofs, cons
             }
             for (int pr = 0; pr < 3; ++pr) {
                 if (M[3 + pr] == 0.0) continue;
-                const float coef = (float)(-c->dt * M[3 + pr] / dV / 8.0);
+                const float coef = (float)(-c->dt * weight * M[3 + pr] / dV / 8.0);
                 const int a0 = pair_axes[pr][0], a1 = pair_axes[pr][1];
-                const int N[3] = {nx, ny, nz};
                 for (int o0 = -1; o0 <= 0; ++o0)
                     for (int o1 = -1; o1 <= 0; ++o1) {
                         int ix[3] = {p[0], p[1], p[2]};
@@ -893,6 +895,27 @@ int pstd3d_set_sources(pstd3d_ctx* c, int n_shots, const int32_t* shot_ofs, cons
                         }
                     }
             }
+        };
+        // Blackman window over [-pi/h, pi/h] on each axis, W(k) = a0 + a1 cos(k h)
+        // + a2 cos(2 k h) with (a0, a1, a2) = (0.42, 0.5, 0.08): cos(k h) shifts
+        // by one cell, so the smoothed delta is the separable stencil
+        // (a2/2, a1/2, a0, a1/2, a2/2) on every axis, periodic at the edges
+        const double a0 = 0.42, a1 = 0.5, a2 = 0.08;
+        const double st[5] = {a2 / 2, a1 / 2, a0, a1 / 2, a2 / 2};
+        for (int q = shot_ofs[s]; q < shot_ofs[s + 1]; ++q) {
+            const int32_t* p = src_ijk + 3 * q;
+            const double* M = m6 + 6 * q;
+            if (!c->smooth) {
+                point(p, M, 1.0, q);
+                continue;
+            }
+            for (int dz = -2; dz <= 2; ++dz)
+                for (int dy = -2; dy <= 2; ++dy)
+                    for (int dx = -2; dx <= 2; ++dx) {
+                        const int pp[3] = {((p[0] + dx) % nx + nx) % nx, ((p[1] + dy) % ny + ny) % ny,
+                                           ((p[2] + dz) % nz + nz) % nz};
+                        point(pp, M, st[dx + 2] * st[dy + 2] * st[dz + 2], q);
+                    }
         }
         std::stable_sort(es.begin(), es.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
         int* sp = &ptr[(size_t)s * (nrows + 1)];
@@ -1177,6 +1200,13 @@ int pstd3d_derivs(pstd3d_ctx* c, int phase, const float* in_dev, float* out_dev,
     enqueue_restore_spectra(c, st);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
+    return PSTD_OK;
+}
+
+int pstd3d_set_source_smoothing(pstd3d_ctx* c, int window)
+{
+    if (!c || (window != PSTD_SMOOTH_NONE && window != PSTD_SMOOTH_BLACKMAN)) return fail(PSTD_EINVAL, "bad arguments");
+    c->smooth = window;
     return PSTD_OK;
 }
 

@@ -249,6 +249,7 @@ class Workload:
     wavelet: np.ndarray          # float64 [n_src_total][nt_w]
     meta: dict = field(default_factory=dict)
     pml_p: float = 0.1           # multi-axial PML ratio
+    smooth: int = 0              # source smoothing: 0 point sources, 1 Blackman window in k-space
 
     @property
     def n_shots(self):
@@ -387,7 +388,8 @@ def paper_shaped_workload(nt=2000, seed_model=0) -> Workload:
     301 rounded to a 2-3-5 length), dx = dy = 12.5 m, dz = 10 m, dt = 0.5 ms,
     2000 steps, 10-cell PML; water over the top 57 cells, 6 perturbed sediment
     layers below; one explosive source of initial pressure 1 Pa (Sec. III-A,
-    as a one-sample moment-rate wavelet w[0] = 1/dt with M = 1 Pa x dx dy dz);
+    as a one-sample moment-rate wavelet w[0] = 1/dt with M = 1 Pa x dx dy dz,
+    smoothed by the Blackman window in k-space as in Sec. II-A);
     four-component receivers at every (x, y) of the seabed plane z = 57
     (9375 receivers)."""
     nx, ny, nz, water = 125, 75, 300, 57
@@ -400,4 +402,4 @@ def paper_shaped_workload(nt=2000, seed_model=0) -> Workload:
     w[0, 0] = 1.0 / dt
     return Workload("paper_shaped_125x75x300", m, d, dt, nt, 10, 2.0, 1, 0.0, rec,
                     np.array([[nx // 2, ny // 2, 200]], np.int32), explosive(dv)[None, :],
-                    np.array([0, 1], np.int32), w)
+                    np.array([0, 1], np.int32), w, smooth=1)

@@ -347,3 +347,31 @@ def test_multiaxial_pml_stabilises_fluid_solid_seam():
         peaks[p] = (tr[:250].max(), tr[-250:].max())
     assert peaks[0.1][1] < 0.1 * peaks[0.1][0]
     assert peaks[0.0][1] > 1e3 * peaks[0.0][0]
+
+
+def test_blackman_smoothing_is_a_five_point_stencil():
+    """The oracle smooths a source's delta with the Blackman window in k-space
+    (FFT, multiply, inverse FFT).  On each axis W(k) = 0.42 + 0.5 cos(k h) +
+    0.08 cos(2 k h) and cos(k h) shifts by one cell, so the result must be the
+    tensor product of (0.04, 0.25, 0.42, 0.25, 0.04), wrapping at the edges
+    (closed form), with weights summing to W(0) = 1."""
+    shape = (20, 18, 15)                      # [z][y][x]; odd x length
+    vp, vs, rho = [np.full(shape, v) for v in (3000.0, 1700.0, 2300.0)]
+    s = oracle.Solver(vp, vs, rho, (10.0, 12.5, 8.0), 1e-3, pml=0, kspace=1)
+    s.set_source_smoothing(1)
+    src = np.array([[1, 9, 19], [7, 0, 10]])
+    s.set_sources(src, np.array([[1.0, 1, 1, 0, 0, 0]] * 2), np.zeros((2, 4)))
+    st = np.array([0.04, 0.25, 0.42, 0.25, 0.04])
+    for q, (i0, j0, k0) in enumerate(src):
+        ijk, wgt = s.smoothed_source(q)
+        got = {tuple(int(v) for v in c): x for c, x in zip(ijk, wgt)}
+        ref = {}
+        for a in range(5):
+            for b in range(5):
+                for c in range(5):
+                    key = ((i0 + a - 2) % 15, (j0 + b - 2) % 18, (k0 + c - 2) % 20)
+                    ref[key] = ref.get(key, 0.0) + st[a] * st[b] * st[c]
+        assert set(got) == set(ref)
+        assert max(abs(got[k] - ref[k]) for k in ref) < 1e-14
+        assert abs(sum(wgt) - 1.0) < 1e-12
+    s.close()
