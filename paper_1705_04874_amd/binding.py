@@ -400,3 +400,72 @@ def decimate(traces, decim, stream=None):
     out = torch.empty((n, 4, n_rec, nt // decim), dtype=torch.float32, device=traces.device)
     _scheck(_L.sno_decimate(_dev(traces), n, n_rec, nt, int(decim), _dev(out), _stream_handle(stream)), "sno_decimate")
     return out
+
+
+# ---------------------------------------------------------------------------
+# clustered event catalogue (include/seis_catalog.h)
+_L.seis_laplacian.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
+_L.seis_pick_interfaces.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, _ip, C.c_int, C.c_float, _ip, C.c_void_p]
+_L.seis_kmeans.argtypes = [_dp, C.c_int, C.c_int, C.c_int, _ip, C.c_int, _ip, _dp, _dp]
+_L.seis_cluster_catalogue.argtypes = [_ip, _dp, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, _dp,
+                                      C.c_double, C.c_double, _dp, _dp, _dp, _ip]
+_L.seis_catalog_last_error.restype = C.c_char_p
+
+
+def _ccheck(rc, what):
+    if rc < 0:
+        msg = _L.seis_catalog_last_error().decode(errors="replace")
+        err = PstdError.__new__(PstdError)
+        RuntimeError.__init__(err, f"{what} failed with code {rc}: {msg}")
+        err.code = rc
+        raise err
+    return rc
+
+
+def laplacian(rho, stream=None):
+    """Laplacian of the density (eq. 8) of a float32 device tensor [nz][ny][nx]."""
+    import torch
+    nz, ny, nx = rho.shape
+    out = torch.empty_like(rho)
+    _ccheck(_L.seis_laplacian(_dev(rho), nx, ny, nz, _dev(out), _stream_handle(stream)), "seis_laplacian")
+    return out
+
+
+def pick_interfaces(lap, cand_ijk, threshold, stream=None):
+    """Host int32 mask of the candidates (i, j, k) where |L| > threshold."""
+    nz, ny, nx = lap.shape
+    c = _i32(cand_ijk).reshape(-1, 3)
+    keep = np.zeros(c.shape[0], np.int32)
+    _ccheck(_L.seis_pick_interfaces(_dev(lap), nx, ny, nz, c.ctypes.data_as(_ip), c.shape[0], float(threshold),
+                                    keep.ctypes.data_as(_ip), _stream_handle(stream)), "seis_pick_interfaces")
+    return keep
+
+
+def kmeans(pts, k, init_idx, max_iter=100):
+    """(labels, centroids, sse) of the library's best-of-runs k-means."""
+    p = _f64(pts).reshape(-1, 3)
+    init = _i32(init_idx).reshape(-1, k)
+    lab = np.zeros(p.shape[0], np.int32)
+    cen = np.zeros((k, 3))
+    sse = C.c_double()
+    _ccheck(_L.seis_kmeans(p.ctypes.data_as(_dp), p.shape[0], int(k), init.shape[0], init.ctypes.data_as(_ip),
+                           int(max_iter), lab.ctypes.data_as(_ip), cen.ctypes.data_as(_dp), C.byref(sse)),
+            "seis_kmeans")
+    return lab, cen, sse.value
+
+
+def cluster_catalogue(labels, depth, k, t_first, dt_between, sigma, gauss, lo, hi, unif):
+    """(t_origin, amp, rank) of the cluster timing rules of Sec. VI-A."""
+    lab = _i32(labels)
+    dep = _f64(depth)
+    g = _f64(gauss)
+    u = _f64(unif)
+    n = lab.size
+    t = np.zeros(n)
+    a = np.zeros(n)
+    r = np.zeros(n, np.int32)
+    _ccheck(_L.seis_cluster_catalogue(lab.ctypes.data_as(_ip), dep.ctypes.data_as(_dp), n, int(k), float(t_first),
+                                      float(dt_between), float(sigma), g.ctypes.data_as(_dp), float(lo), float(hi),
+                                      u.ctypes.data_as(_dp), t.ctypes.data_as(_dp), a.ctypes.data_as(_dp),
+                                      r.ctypes.data_as(_ip)), "seis_cluster_catalogue")
+    return t, a, r

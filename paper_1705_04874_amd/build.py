@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpstd3d.so")
-SOURCES = ["pstd3d.hip", "combine.hip", "sno.hip"]
+SOURCES = ["pstd3d.hip", "combine.hip", "sno.hip", "catalog.hip"]
 
 # Packed FP32 instructions are disabled for every HIP translation unit.
 HIPFLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -403,3 +403,12 @@ def paper_shaped_workload(nt=2000, seed_model=0) -> Workload:
     return Workload("paper_shaped_125x75x300", m, d, dt, nt, 10, 2.0, 1, 0.0, rec,
                     np.array([[nx // 2, ny // 2, 200]], np.int32), explosive(dv)[None, :],
                     np.array([0, 1], np.int32), w, smooth=1)
+
+
+def cluster_draws(n: int, k: int, runs: int, seed: int):
+    """Random numbers of the clustered catalogue: k distinct initial-centroid
+    indices per k-means run (int32 [runs][k]), standard normals and U[0, 1)
+    draws per event."""
+    rng = np.random.default_rng(seed)
+    init = np.stack([rng.choice(n, size=k, replace=False) for _ in range(runs)]).astype(np.int32)
+    return init, rng.standard_normal(n), rng.uniform(size=n)
