@@ -70,6 +70,12 @@ struct ostate {
     double *kappa;
     /* state: v[c][d] (9), sn[c][d] (9 normal), ss[p][2] (shear xy:(x,y) xz:(x,z) yz:(y,z)) */
     double *v[3][3], *sn[3][3], *ss[3][2];
+    /* Kelvin-Voigt viscosity (eq. 1-2): chi, eta at centres, eta at the shear
+     * nodes; ep: the nine velocity derivatives of the previous step (order
+     * D-_x vx, D-_y vy, D-_z vz, then the shear pieces xy(x), xy(y), xz(x),
+     * xz(z), yz(y), yz(z)); NULL when lossless */
+    double *chi, *eta, *eta_s[3];
+    double *ep[9];
     /* sources / receivers */
     int n_src, nt_w;
     int *src;
@@ -138,6 +144,10 @@ static void free_state(ostate *s)
     free(s->sm_ofs);
     free(s->sm_ijk);
     free(s->sm_w);
+    free(s->chi);
+    free(s->eta);
+    for (int d = 0; d < 3; ++d) free(s->eta_s[d]);
+    for (int t = 0; t < 9; ++t) free(s->ep[t]);
     free(s->rec);
     free(s);
 }
@@ -289,6 +299,63 @@ ostate *opstd_create(int nx, int ny, int nz, const double *vp, const double *vs,
     return s;
 }
 
+/* Kelvin-Voigt viscosity (eq. 1-2): chi and eta per cell (host [n]); NULL
+ * for both restores the lossless medium.  eta at the shear nodes is the
+ * harmonic mean of the four surrounding centres, 0 if any of them is 0 (the
+ * reading taken for mu).  The previous-step derivatives start at zero. */
+int opstd_set_viscosity(ostate *s, const double *chi, const double *eta)
+{
+    free(s->chi);
+    free(s->eta);
+    s->chi = s->eta = NULL;
+    for (int d = 0; d < 3; ++d) {
+        free(s->eta_s[d]);
+        s->eta_s[d] = NULL;
+    }
+    for (int t = 0; t < 9; ++t) {
+        free(s->ep[t]);
+        s->ep[t] = NULL;
+    }
+    if (!chi && !eta) return ORC_OK;
+    if (!chi || !eta) return ORC_EINVAL;
+    long n = s->n;
+    for (long c = 0; c < n; ++c)
+        if (!(chi[c] >= 0) || !(eta[c] >= 0) || !isfinite(chi[c]) || !isfinite(eta[c])) return ORC_EINVAL;
+    s->chi = malloc(sizeof(double) * n);
+    s->eta = malloc(sizeof(double) * n);
+    for (int d = 0; d < 3; ++d) s->eta_s[d] = malloc(sizeof(double) * n);
+    for (int t = 0; t < 9; ++t) s->ep[t] = calloc(n, sizeof(double));
+    if (!s->chi || !s->eta || !s->eta_s[2] || !s->ep[8]) return ORC_ENOMEM;
+    memcpy(s->chi, chi, sizeof(double) * n);
+    memcpy(s->eta, eta, sizeof(double) * n);
+    int nx = s->nx, ny = s->ny, nz = s->nz;
+    for (int kk = 0; kk < nz; ++kk)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                long c = IDX(s, i, j, kk);
+                int ip = i + 1 < nx ? i + 1 : nx - 1;
+                int jp = j + 1 < ny ? j + 1 : ny - 1;
+                int kp = kk + 1 < nz ? kk + 1 : nz - 1;
+                long q[3][4] = {
+                    {c, IDX(s, ip, j, kk), IDX(s, i, jp, kk), IDX(s, ip, jp, kk)},
+                    {c, IDX(s, ip, j, kk), IDX(s, i, j, kp), IDX(s, ip, j, kp)},
+                    {c, IDX(s, i, jp, kk), IDX(s, i, j, kp), IDX(s, i, jp, kp)}};
+                for (int p = 0; p < 3; ++p) {
+                    double inv = 0;
+                    int zero = 0;
+                    for (int t = 0; t < 4; ++t) {
+                        double m = eta[q[p][t]];
+                        if (m == 0) zero = 1;
+                        else inv += 1.0 / m;
+                    }
+                    s->eta_s[p][c] = zero ? 0.0 : 4.0 / inv;
+                }
+            }
+    return ORC_OK;
+}
+
+int opstd_n_state(const ostate *s) { return s->chi ? 33 : 24; }
+
 int opstd_set_source_smoothing(ostate *s, int window)
 {
     if (window != 0 && window != 1) return ORC_EINVAL;
@@ -408,6 +475,8 @@ int opstd_set_sources(ostate *s, int n_src, const int *src_ijk, const double *m6
         memset(s->ss[p][0], 0, sizeof(double) * s->n);
         memset(s->ss[p][1], 0, sizeof(double) * s->n);
     }
+    if (s->chi)
+        for (int t = 0; t < 9; ++t) memset(s->ep[t], 0, sizeof(double) * s->n);
     s->step = 0;
     return ORC_OK;
 }
@@ -613,7 +682,14 @@ static void stress_step(ostate *s)
                         double a = afac(s, d, pos, centre);
                         double coef = lam + (comp == d ? 2.0 * mu : 0.0);
                         double *f = s->sn[comp][d];
-                        f[c] = a * (a * f[c] + dt * coef * e[d][c]);
+                        double rhs = dt * coef * e[d][c];
+                        if (s->chi) {
+                            /* chi delta_ij d/dt(dv_k/dx_k) + 2 eta d/dt(dv_i/dx_i):
+                             * backward difference of the derivative over the step */
+                            double vcoef = s->chi[c] + (comp == d ? 2.0 * s->eta[c] : 0.0);
+                            rhs += vcoef * (e[d][c] - s->ep[d][c]);
+                        }
+                        f[c] = a * (a * f[c] + rhs);
                     }
                 for (int p = 0; p < 3; ++p)
                     for (int t = 0; t < 2; ++t) {
@@ -623,9 +699,16 @@ static void stress_step(ostate *s)
                         half[pair_axes[p][1]] = 1;
                         double a = afac(s, d, pos, half);
                         double *f = s->ss[p][t];
-                        f[c] = a * (a * f[c] + dt * s->mu_s[p][c] * g[p][t][c]);
+                        double rhs = dt * s->mu_s[p][c] * g[p][t][c];
+                        if (s->chi) rhs += s->eta_s[p][c] * (g[p][t][c] - s->ep[3 + 2 * p + t][c]);
+                        f[c] = a * (a * f[c] + rhs);
                     }
             }
+    if (s->chi) {
+        for (int d = 0; d < 3; ++d) memcpy(s->ep[d], e[d], sizeof(double) * s->n);
+        for (int p = 0; p < 3; ++p)
+            for (int t = 0; t < 2; ++t) memcpy(s->ep[3 + 2 * p + t], g[p][t], sizeof(double) * s->n);
+    }
     free(g21);
 }
 
@@ -705,7 +788,8 @@ int opstd_run(ostate *s, int nt, double *traces)
     return ORC_OK;
 }
 
-/* state order: v[c][d] (9), sn[c][d] (9), ss xy(x,y) xz(x,z) yz(y,z) (6) */
+/* state order: v[c][d] (9), sn[c][d] (9), ss xy(x,y) xz(x,z) yz(y,z) (6), and
+ * with viscosity the nine previous velocity derivatives (9) */
 void opstd_get_state(const ostate *s, double *fields)
 {
     long n = s->n;
@@ -716,6 +800,8 @@ void opstd_get_state(const ostate *s, double *fields)
         for (int d = 0; d < 3; ++d) memcpy(fields + n * f++, s->sn[c][d], sizeof(double) * n);
     for (int p = 0; p < 3; ++p)
         for (int t = 0; t < 2; ++t) memcpy(fields + n * f++, s->ss[p][t], sizeof(double) * n);
+    if (s->chi)
+        for (int t = 0; t < 9; ++t) memcpy(fields + n * f++, s->ep[t], sizeof(double) * n);
 }
 
 void opstd_set_state(ostate *s, const double *fields)
@@ -728,4 +814,6 @@ void opstd_set_state(ostate *s, const double *fields)
         for (int d = 0; d < 3; ++d) memcpy(s->sn[c][d], fields + n * f++, sizeof(double) * n);
     for (int p = 0; p < 3; ++p)
         for (int t = 0; t < 2; ++t) memcpy(s->ss[p][t], fields + n * f++, sizeof(double) * n);
+    if (s->chi)
+        for (int t = 0; t < 9; ++t) memcpy(s->ep[t], fields + n * f++, sizeof(double) * n);
 }

@@ -31,6 +31,10 @@ ostate *opstd_create(int nx, int ny, int nz, const double *vp, const double *vs,
 int opstd_set_sources(ostate *s, int n_src, const int *src_ijk, const double *m6,
                       const double *wavelet, int nt_w);
 int opstd_run(ostate *s, int nt, double *traces);
+/* Kelvin-Voigt viscosity chi, eta per cell (NULL, NULL: lossless); clears the state. */
+int opstd_set_viscosity(ostate *s, const double *chi, const double *eta);
+/* Fields in opstd_get_state / opstd_set_state: 24, or 33 with viscosity. */
+int opstd_n_state(const ostate *s);
 /* Source smoothing for the next opstd_set_sources: 0 off, 1 Blackman window in k-space. */
 int opstd_set_source_smoothing(ostate *s, int window);
 /* Cells (ijk, up to max) and weights of source q's smoothed delta; returns the count. */

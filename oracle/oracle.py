@@ -42,6 +42,8 @@ def lib():
         L.opstd_set_sources.argtypes = [C.c_void_p, C.c_int, ip, dp, dp, C.c_int]
         L.opstd_run.argtypes = [C.c_void_p, C.c_int, dp]
         L.opstd_set_source_smoothing.argtypes = [C.c_void_p, C.c_int]
+        L.opstd_set_viscosity.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.opstd_n_state.argtypes = [C.c_void_p]
         L.opstd_smoothed_source.argtypes = [C.c_void_p, C.c_int, C.c_int, ip, dp]
         L.opstd_get_state.argtypes = [C.c_void_p, dp]
         L.opstd_set_state.argtypes = [C.c_void_p, dp]
@@ -134,7 +136,23 @@ class Solver:
         s = cls(w.model.vp, w.model.vs, w.model.rho, **kw)
         if getattr(w, "smooth", 0):
             s.set_source_smoothing(w.smooth)
+        if getattr(w, "chi", None) is not None:
+            s.set_viscosity(w.chi, w.eta)
         return s
+
+    def set_viscosity(self, chi, eta):
+        """Kelvin-Voigt viscosities per cell [nz][ny][nx] (None, None: lossless); clears the state."""
+        if chi is None and eta is None:
+            rc = lib().opstd_set_viscosity(self._h, None, None)
+        else:
+            self._chi, self._eta = _f64(chi), _f64(eta)
+            rc = lib().opstd_set_viscosity(self._h, self._chi.ctypes.data, self._eta.ctypes.data)
+        if rc:
+            raise OracleError(rc, "set_viscosity")
+
+    @property
+    def n_state(self):
+        return int(lib().opstd_n_state(self._h))
 
     def set_source_smoothing(self, window):
         """0: point sources; 1: Blackman window in k-space (next set_sources)."""
@@ -168,12 +186,12 @@ class Solver:
         return out
 
     def get_state(self):
-        out = np.empty((self.N_STATE,) + self.shape)
+        out = np.empty((self.n_state,) + self.shape)
         lib().opstd_get_state(self._h, _dp(out))
         return out
 
     def set_state(self, fields):
-        f = _f64(fields).reshape((self.N_STATE,) + self.shape)
+        f = _f64(fields).reshape((self.n_state,) + self.shape)
         lib().opstd_set_state(self._h, _dp(f))
 
     @property

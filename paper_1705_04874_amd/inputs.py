@@ -250,6 +250,8 @@ class Workload:
     meta: dict = field(default_factory=dict)
     pml_p: float = 0.1           # multi-axial PML ratio
     smooth: int = 0              # source smoothing: 0 point sources, 1 Blackman window in k-space
+    chi: np.ndarray = None       # Kelvin-Voigt viscosities per cell (None: lossless)
+    eta: np.ndarray = None
 
     @property
     def n_shots(self):

@@ -375,3 +375,77 @@ def test_blackman_smoothing_is_a_five_point_stencil():
         assert max(abs(got[k] - ref[k]) for k in ref) < 1e-14
         assert abs(sum(wgt) - 1.0) < 1e-12
     s.close()
+
+
+@pytest.mark.parametrize("kspace", [1, 0])
+@pytest.mark.parametrize("wave", ["P", "S"])
+def test_viscous_plane_wave_follows_the_discrete_dispersion_relation(kspace, wave):
+    """Kelvin-Voigt terms of eq. 2 with d/dt of the velocity derivative taken as
+    the backward difference over one step.  For a plane wave e^{i k x} along x
+    in a homogeneous periodic medium (PML off) the mode amplitudes obey
+        V' = V + (dt/rho) g S,  S' = S + dt M g V' + Xi g (V' - V),
+    g = i k kappa, so the growth per step z solves
+        z^2 + (a dt M + a Xi - 2) z + 1 - a Xi = 0,  a = dt k^2 kappa^2 / rho,
+    with M = lambda + 2 mu, Xi = chi + 2 eta for the P wave (v_x, sigma_xx) and
+    M = mu, Xi = eta for the S wave (v_y, sigma_xy: the shear viscosity at the
+    shear nodes and the stored shear derivative).  A mode started on the root
+    with |z| < 1 must decay and turn exactly as z^n; a control with a wrong
+    viscosity (factor 2 dropped for P, doubled for S) is far off."""
+    shape = (6, 5, 16)                     # [z][y][x]
+    h = (10.0, 10.0, 10.0)
+    vp, vs, rho, dt = 3000.0, 1700.0, 2300.0, 0.5e-3
+    chi, eta = 2.0e6, 1.5e6                # Pa s
+    lam, mu = rho * (vp * vp - 2 * vs * vs), rho * vs * vs
+    nx = shape[2]
+    m = 3
+    k = 2 * math.pi * m / (nx * h[0])
+    kap = math.sin(0.5 * vp * k * dt) / (0.5 * vp * k * dt) if kspace else 1.0
+    g = 1j * k * kap
+    a = dt * (k * kap) ** 2 / rho
+    M, xi, xi_wrong = (lam + 2 * mu, chi + 2 * eta, chi + eta) if wave == "P" else (mu, eta, 2 * eta)
+
+    def roots(x):
+        r = np.roots([1.0, a * dt * M + a * x - 2.0, 1.0 - a * x])
+        return r[np.argmin(r.imag)]        # the root travelling towards +x
+
+    z = roots(xi)
+    assert abs(z) < 1.0
+    s = oracle.Solver(np.full(shape, vp), np.full(shape, vs), np.full(shape, rho), h, dt, pml=0, kspace=kspace,
+                      c_ref=vp)
+    s.set_viscosity(np.full(shape, chi), np.full(shape, eta))
+    s.set_sources(np.zeros((0, 3)), np.zeros((0, 6)), np.zeros((0, 1)))
+    x_int = np.arange(nx) * h[0]
+    x_half = x_int + 0.5 * h[0]
+    V = 1e-3                               # velocity amplitude at step -1/2
+    S = (z - 1) * V * rho / (dt * g)        # stress amplitude at step 0
+    Syy = g * V * (dt * lam * z + chi * (z - 1)) / (z - 1)
+    # (state field of the velocity, of the stress, of the stored derivative; their x nodes)
+    if wave == "P":
+        fv, fs, fe, xv, xs = 0, 9, 24, x_half, x_int       # v_x (x part), sigma_xx (x part), D-_x v_x
+    else:
+        fv, fs, fe, xv, xs = 3, 18, 27, x_int, x_half      # v_y (x part), sigma_xy (x part), D+_x v_y
+
+    def fields(n, zz=z):
+        zn = zz ** n
+        st = np.zeros((33,) + shape)
+        st[fv] = np.real(zn * V * np.exp(1j * k * xv))
+        st[fs] = np.real(zn * S * np.exp(1j * k * xs))
+        st[fe] = np.real(zn * g * V * np.exp(1j * k * xs))
+        if wave == "P":
+            st[12] = np.real(zn * Syy * np.exp(1j * k * x_int))     # sigma_yy, x part
+            st[15] = st[12]                                          # sigma_zz, x part
+        return st
+
+    s.set_state(fields(0))
+    s.run(40)
+    got = s.get_state()
+    ref = fields(40)
+    for f in (fv, fs, fe) + ((12, 15) if wave == "P" else ()):
+        err = np.abs(got[f] - ref[f]).max() / np.abs(ref[f]).max()
+        assert err < 1e-9, (f, err)
+    rest = [f for f in range(33) if not ref[f].any()]
+    assert np.abs(got[rest]).max() < 1e-12 * np.abs(got).max()   # nothing else is excited
+    assert abs(z) ** 40 < 0.95                                 # the mode followed above decays
+    wrong = np.real(roots(xi_wrong) ** 40 * V * np.exp(1j * k * xv))
+    assert np.abs(got[fv] - wrong).max() > 1e-2 * np.abs(wrong).max()
+    s.close()
