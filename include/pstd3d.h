@@ -3,9 +3,10 @@
  * trace superposition.  Plain C ABI: host or device pointers and sizes only.
  *
  * Physics (arXiv 1705.04874, Das, Chen & Hobson):
- *  - lossless 3-D elastic first-order stress-velocity system (eq. 2 with the
- *    viscosities set to zero, Sec. II-A), Lame parameters from cp, cs, rho
- *    (eq. 4), hydrophone pressure p = -(sxx + syy + szz)/3 (eq. 3);
+ *  - 3-D elastic first-order stress-velocity system (eq. 1-2, Sec. II-A),
+ *    lossless by default, with optional Kelvin-Voigt viscosities chi, eta;
+ *    Lame parameters from cp, cs, rho (eq. 4), hydrophone pressure
+ *    p = -(sxx + syy + szz)/3 (eq. 3);
  *  - Fourier pseudo-spectral spatial derivatives, leapfrog time stepping on a
  *    grid staggered in space and time (Sec. II-A), with a k-space correction
  *    kappa = sinc(c_ref |k| dt / 2) on the derivative operator;
@@ -106,6 +107,23 @@ int pstd3d_set_sources(pstd3d_ctx *c, int n_shots, const int32_t *shot_ofs, cons
 #define PSTD_SMOOTH_BLACKMAN 1
 int pstd3d_set_source_smoothing(pstd3d_ctx *c, int window);
 
+/* Kelvin-Voigt viscosity (eq. 1-2): the stress rate gains
+ * chi delta_ij d/dt(div v) + eta d/dt(dv_i/dx_j + dv_j/dx_i).  chi, eta (Pa s)
+ * are host arrays [nz][ny][nx], finite and >= 0; eta at a shear node is the
+ * harmonic mean of the four surrounding cells (0 if any is 0), as for mu.
+ * Each time derivative is taken as the change of the velocity derivative over
+ * one step (backward difference), so every shot carries the nine derivatives
+ * of its previous step as 9 more state fields (33 in all); they start at zero.
+ * NULL for both restores the lossless medium.  The explicit viscous term is
+ * stable only while dt (pi/h)^2 (chi + 2 eta) / rho stays well below 1 on the
+ * finest axis; this call does not check it (a run that blows up returns
+ * PSTD_EUNSTABLE).  Clears the shots: call pstd3d_set_sources again (which
+ * retunes the stress kernel for the viscous variant). */
+int pstd3d_set_viscosity(pstd3d_ctx *c, const double *chi, const double *eta);
+
+/* State fields per shot: 24 (lossless) or 33 (viscous). */
+int pstd3d_state_fields(const pstd3d_ctx *c);
+
 /* Advance every shot by nt steps on `hip_stream` (a hipStream_t, may be
  * NULL for the null stream) and write the receiver traces of those steps to
  * the caller-owned device buffer traces_dev [n_shots][4][n_rec][nt].
@@ -119,9 +137,11 @@ int pstd3d_run(pstd3d_ctx *c, int nt, float *traces_dev, void *hip_stream);
  * device trace buffer.  All contexts must live on the current device. */
 int pstd3d_run_many(pstd3d_ctx *const *ctxs, int n, int nt, float *const *traces, void *hip_stream);
 
-/* Checkpoint: copy shot `shot`'s 24 split fields (float, host [24][nz][ny][nx],
- * order vx(x,y,z) vy(x,y,z) vz(x,y,z) sxx(x,y,z) syy(x,y,z) szz(x,y,z)
- * sxy(x,y) sxz(x,z) syz(y,z)) to host memory. */
+/* Checkpoint: copy shot `shot`'s state (float, host [F][nz][ny][nx] with
+ * F = pstd3d_state_fields: the 24 split fields in the order vx(x,y,z)
+ * vy(x,y,z) vz(x,y,z) sxx(x,y,z) syy(x,y,z) szz(x,y,z) sxy(x,y) sxz(x,z)
+ * syz(y,z), then with viscosity the previous step's D-x vx, D-y vy, D-z vz,
+ * Dx+ vy, Dy+ vx, Dx+ vz, Dz+ vx, Dy+ vz, Dz+ vy) to host memory. */
 int pstd3d_get_state(pstd3d_ctx *c, int shot, float *fields_host);
 /* Restore shot `shot`'s split fields from host memory and set the step index
  * of the context (the wavelet sample used by the next step). */

@@ -51,6 +51,8 @@ _L.pstd3d_reset.argtypes = [C.c_void_p, C.c_void_p]
 _L.pstd3d_profile.argtypes = [C.c_void_p, C.c_int]
 _L.pstd3d_profile_read.argtypes = [C.c_void_p, C.c_int, _dp, C.POINTER(C.c_long)]
 _L.pstd3d_set_source_smoothing.argtypes = [C.c_void_p, C.c_int]
+_L.pstd3d_set_viscosity.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+_L.pstd3d_state_fields.argtypes = [C.c_void_p]
 _L.pstd3d_set_tuning.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
 _L.pstd3d_get_tuning.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _fp, C.c_int]
 TUNE_KNOBS = ("y_tile", "z_tile", "vel_threads", "str_threads")
@@ -115,7 +117,26 @@ class Solver:
         s = cls(w.model.vp, w.model.vs, w.model.rho, **kw)
         if getattr(w, "smooth", 0):
             s.set_source_smoothing(w.smooth)
+        if getattr(w, "chi", None) is not None:
+            s.set_viscosity(w.chi, w.eta)
         return s
+
+    def set_viscosity(self, chi, eta):
+        """Kelvin-Voigt viscosities (Pa s) per cell [nz][ny][nx]; None, None: lossless.
+        Clears the shots (call set_sources again)."""
+        if chi is None and eta is None:
+            rc = _L.pstd3d_set_viscosity(self._h, None, None)
+        else:
+            c, e = _f64(chi), _f64(eta)
+            assert c.shape == self.shape and e.shape == self.shape
+            rc = _L.pstd3d_set_viscosity(self._h, c.ctypes.data, e.ctypes.data)
+        _check(rc, "pstd3d_set_viscosity")
+        self.n_shots = 0
+
+    @property
+    def n_state(self):
+        """State fields per shot: 24, or 33 with viscosity."""
+        return int(_L.pstd3d_state_fields(self._h))
 
     def set_source_smoothing(self, window):
         """0: point sources; 1: Blackman window in k-space (for later set_sources)."""
@@ -188,13 +209,13 @@ class Solver:
         return out
 
     def get_state(self, shot=0):
-        out = np.empty((24,) + self.shape, np.float32)
+        out = np.empty((self.n_state,) + self.shape, np.float32)
         _check(_L.pstd3d_get_state(self._h, shot, out.ctypes.data_as(_fp)), "pstd3d_get_state")
         return out
 
     def set_state(self, fields, step, shot=0):
         f = np.ascontiguousarray(fields, dtype=np.float32)
-        assert f.size == 24 * int(np.prod(self.shape))
+        assert f.size == self.n_state * int(np.prod(self.shape))
         _check(_L.pstd3d_set_state(self._h, shot, f.ctypes.data_as(_fp), int(step)), "pstd3d_set_state")
 
     @property

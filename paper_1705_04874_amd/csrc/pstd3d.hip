@@ -54,6 +54,7 @@ struct VelVar {
 };
 struct StrVar {
     StrFn fn;
+    StrFn visc;   // the Kelvin-Voigt variant
     int nt;
 };
 struct YFns {
@@ -106,6 +107,11 @@ struct LaunchX {
     {
         hipLaunchKernelGGL((k_str<N, T>), gr, dim3(T), 0, st, g, m, p, tw, f, s, r, in, tr, sp, n0, ldt);
     }
+    static void strv(dim3 gr, hipStream_t st, Geo g, Mat m, Pml p, const float2* tw, float* f, float2* s, Rec r,
+                     Inj in, float* tr, const int* sp, int n0, int ldt)
+    {
+        hipLaunchKernelGGL((k_str<N, T, true>), gr, dim3(T), 0, st, g, m, p, tw, f, s, r, in, tr, sp, n0, ldt);
+    }
 };
 
 template <int N, int I = 0>
@@ -115,7 +121,7 @@ void x_variants(VelVar* v, StrVar* s, int& n)
         constexpr int T = nt_candidate(N, I);
         if constexpr (T > 0) {
             v[n] = VelVar{LaunchX<N, T>::vel, T};
-            s[n] = StrVar{LaunchX<N, T>::str, T};
+            s[n] = StrVar{LaunchX<N, T>::str, LaunchX<N, T>::strv, T};
             ++n;
         }
         x_variants<N, I + 1>(v, s, n);
@@ -306,6 +312,7 @@ struct pstd3d_ctx {
     int force[PSTD_TUNE_COUNT] = {0, 0, 0, 0};
     int sel[PSTD_TUNE_COUNT] = {0, 0, 0, 0};
     bool tuned = false;
+    bool visc = false;         // Kelvin-Voigt viscosity set (33 state fields)
     int smooth = 0;            // source smoothing for the next set_sources (0 off, 1 Blackman)
     float tune_us[PSTD_TUNE_COUNT][MAX_VARIANTS] = {};   // measured us per launch of each variant
     YFns yf{};                 // the chosen variants
@@ -324,8 +331,10 @@ struct pstd3d_ctx {
         vel = velv[sel[PSTD_TUNE_VEL]];
         str = strv[sel[PSTD_TUNE_STR]];
     }
+    StrFn str_fn(const StrVar& v) const { return visc ? v.visc : v.fn; }
     // model-wide device tables
     float* mat = nullptr;      // 8 arrays of n
+    float* vmat = nullptr;     // viscous: chi, 2 eta, eta at the 3 shear nodes
     float* pmlb = nullptr;     // ai[3], ah[3] back to back
     float2* tw = nullptr;      // x, y, z twiddles
     float2* sym = nullptr;     // per axis D-, D+
@@ -416,6 +425,7 @@ struct pstd3d_ctx {
     void release_model()
     {
         (void)hipFree(mat);
+        (void)hipFree(vmat);
         (void)hipFree(pmlb);
         (void)hipFree(tw);
         (void)hipFree(sym);
@@ -633,7 +643,8 @@ void enqueue_step(pstd3d_ctx* c, hipStream_t st, float* traces, int n0, int ldt,
     c->yf.inv(dim3(tyn, g.nz, S * 9), st, g, c->twy, c->spec, 9, 9);
     c->ev_end(e, st);
     e = c->ev_begin(PSTD_K_STR, st);
-    c->str.fn(gx, st, g, c->M, c->P, c->twx, c->fields, c->spec, rec_of(c), inj_of(c), traces, cur, n0, ldt);
+    c->str_fn(c->str)(gx, st, g, c->M, c->P, c->twx, c->fields, c->spec, rec_of(c), inj_of(c), traces, cur, n0,
+                      ldt);
     c->ev_end(e, st);
 }
 
@@ -716,8 +727,9 @@ int autotune(pstd3d_ctx* c)
                                      c->stepd, c->stepd + 1, 0, 1); }, &c->tune_us[k][i]);
             } else {
                 const StrVar v = c->strv[i];
-                e = timed([&] { v.fn(gx, nullptr, g, c->M, c->P, c->twx, c->fields, c->spec, norec, noinj, nullptr,
-                                     c->stepd, 0, 1); }, &c->tune_us[k][i]);
+                const StrFn fn = c->str_fn(v);
+                e = timed([&] { fn(gx, nullptr, g, c->M, c->P, c->twx, c->fields, c->spec, norec, noinj, nullptr,
+                                   c->stepd, 0, 1); }, &c->tune_us[k][i]);
             }
             if (e != hipSuccess) {
                 cleanup();
@@ -1210,6 +1222,68 @@ int pstd3d_set_source_smoothing(pstd3d_ctx* c, int window)
     return PSTD_OK;
 }
 
+int pstd3d_set_viscosity(pstd3d_ctx* c, const double* chi, const double* eta)
+{
+    if (!c) return fail(PSTD_EINVAL, "null context");
+    if (!chi != !eta) return fail(PSTD_EINVAL, "chi and eta must both be given or both be NULL");
+    const int nx = c->nx, ny = c->ny, nz = c->nz;
+    const long n = (long)nx * ny * nz;
+    if (chi)
+        for (long q = 0; q < n; ++q)
+            if (!std::isfinite(chi[q]) || !std::isfinite(eta[q]) || chi[q] < 0 || eta[q] < 0)
+                return fail(PSTD_EINVAL, "viscosities must be finite and >= 0");
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipDeviceSynchronize());
+    c->release_shots();
+    c->step = 0;
+    (void)hipFree(c->vmat);
+    c->vmat = nullptr;
+    c->M.chi = c->M.eta2 = nullptr;
+    for (int p = 0; p < 3; ++p) c->M.etas[p] = nullptr;
+    c->visc = chi != nullptr;
+    c->g.fstride = (c->visc ? 33 : 24) * n;
+    // the stress knob is timed again on the variant that runs, unless every knob is pinned
+    bool pinned = true;
+    for (int k = 0; k < PSTD_TUNE_COUNT; ++k) pinned = pinned && c->force[k] != 0;
+    c->tuned = pinned;
+    if (!c->visc) return PSTD_OK;
+    auto at = [&](int i, int j, int k) { return (long)i + nx * ((long)j + (long)ny * k); };
+    std::vector<float> hv(5 * n);
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const long q = at(i, j, k);
+                const int ip = std::min(i + 1, nx - 1), jp = std::min(j + 1, ny - 1), kp = std::min(k + 1, nz - 1);
+                hv[q] = (float)chi[q];
+                hv[n + q] = (float)(2.0 * eta[q]);
+                const long nb[3][4] = {{q, at(ip, j, k), at(i, jp, k), at(ip, jp, k)},
+                                       {q, at(ip, j, k), at(i, j, kp), at(ip, j, kp)},
+                                       {q, at(i, jp, k), at(i, j, kp), at(i, jp, kp)}};
+                for (int p = 0; p < 3; ++p) {
+                    double inv = 0.0;
+                    bool zero = false;
+                    for (int t = 0; t < 4; ++t) {
+                        const double v = eta[nb[p][t]];
+                        if (v == 0.0) zero = true;
+                        else inv += 1.0 / v;
+                    }
+                    hv[(2 + p) * n + q] = zero ? 0.0f : (float)(4.0 / inv);
+                }
+            }
+    const int rc = dev_upload(&c->vmat, hv);
+    if (rc) {
+        c->visc = false;
+        c->g.fstride = 24 * n;
+        return rc;
+    }
+    c->M.chi = c->vmat;
+    c->M.eta2 = c->vmat + n;
+    for (int p = 0; p < 3; ++p) c->M.etas[p] = c->vmat + (2 + p) * n;
+    return PSTD_OK;
+}
+
+int pstd3d_state_fields(const pstd3d_ctx* c) { return c ? (c->visc ? 33 : 24) : PSTD_EINVAL; }
+
 int pstd3d_set_tuning(pstd3d_ctx* c, const int value[PSTD_TUNE_COUNT])
 {
     if (!c || !value) return fail(PSTD_EINVAL, "bad arguments");
@@ -1250,7 +1324,7 @@ int pstd3d_get_tuning(const pstd3d_ctx* c, int knob, int* chosen, int* values, f
 long pstd3d_device_bytes(const pstd3d_ctx* c)
 {
     if (!c) return 0;
-    return c->bytes + (long)c->n_shots * (c->g.fstride * 4 + c->g.sstride * 8);
+    return c->bytes + (c->visc ? 20L * c->g.n : 0L) + (long)c->n_shots * (c->g.fstride * 4 + c->g.sstride * 8);
 }
 
 void pstd3d_destroy(pstd3d_ctx* c)

@@ -35,6 +35,12 @@ struct Mat {
     const float* dlam;     // dt * lambda at centres
     const float* dmu2;     // 2 dt * mu at centres
     const float* dmus[3];  // dt * mu at xy, xz, yz shear nodes
+    // Kelvin-Voigt viscosity (eq. 1-2), only read by the viscous stress
+    // update: chi and 2 eta at centres, eta at the shear nodes (not times dt:
+    // they multiply the change of a velocity derivative over one step)
+    const float* chi;
+    const float* eta2;
+    const float* etas[3];
 };
 
 // PML factors a = exp(-alpha dt / 2) per axis, at integer and half nodes, and
@@ -316,7 +322,10 @@ __global__ __launch_bounds__(NT) void k_vel(Geo g, Mat m, Pml pm, const float2* 
 // S phase tail: inverse x FFT of the 9 velocity derivatives, stress split-PML
 // update (eq. 2 first line), source injection, receiver p (eq. 3), x FFT of
 // the 6 summed stresses.
-template <int NX, int NT>
+// slot of velocity derivative q (order of e[] in k_str) among the nine stored ones
+__host__ __device__ constexpr int ep_slot(int q) { return q < 3 ? q : ((q - 3) ^ 1) + 3; }
+
+template <int NX, int NT, bool VISC = false>
 __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* __restrict__ twx,
                                             float* __restrict__ fields, float2* __restrict__ spec,
                                             Rec rc, Inj inj, float* __restrict__ traces,
@@ -333,6 +342,10 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
     const int shot = blockIdx.y;
     const int row0 = blockIdx.x * ROWS;
     float* __restrict__ F = fields + (long)shot * g.fstride + 9 * g.n;   // 15 stress parts
+    // viscous: the nine velocity derivatives of the previous step, after the 24
+    // split parts, in the order D-x vx, D-y vy, D-z vz, Dx+ vy, Dy+ vx, Dx+ vz,
+    // Dz+ vx, Dy+ vz, Dz+ vy (e[] below swaps each shear pair)
+    float* __restrict__ EP = fields + (long)shot * g.fstride + 24 * g.n;
     const float2* __restrict__ D9 = spec + (long)shot * g.sstride + 9 * g.nspec;
     float2* __restrict__ S6 = spec + (long)shot * g.sstride;
     const int step = *stepp;
@@ -345,6 +358,7 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
     // (the split parts share one base pointer, so a store would serialise
     // later loads): split parts, materials, PML factors, source rows
     float sp[CPT][15], mt[CPT][5], fa[CPT][9];
+    float ep[VISC ? CPT : 1][9], vm[VISC ? CPT : 1][5];
     int jr[CPT][2];
     bool ok[CPT];
 #pragma unroll
@@ -379,6 +393,15 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
         fa[i][8] = pm.ah[2][z] * bxi * byh;   // yz, z part
         jr[i][0] = iptr[rr];
         jr[i][1] = iptr[rr + 1];
+        if constexpr (VISC) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) ep[i][q] = EP[(long)ep_slot(q) * g.n + cell];
+            vm[i][0] = m.chi[cell];
+            vm[i][1] = m.eta2[cell];
+            vm[i][2] = m.etas[0][cell];
+            vm[i][3] = m.etas[1][cell];
+            vm[i][4] = m.etas[2][cell];
+        }
     }
     __builtin_amdgcn_sched_barrier(0);
 
@@ -402,22 +425,44 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
         float e[9];
 #pragma unroll
         for (int q = 0; q < 9; ++q) e[q] = pencil_val<PS>(s, q * ROWS + r, x);
+        // viscous terms (eq. 2): chi delta_cd d/dt(div v) + eta d/dt(D v + (D v)^T),
+        // d/dt as the change of each derivative over the step
+        float de[9];
+        if constexpr (VISC) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) de[q] = e[q] - ep[i][q];
+        }
         // normal parts sp[i][3c + d] (component c, axis d)
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc)
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 const float coef = cc == d ? dlam + dmu2 : dlam;
-                sp[i][3 * cc + d] = ai[d] * (ai[d] * sp[i][3 * cc + d] + coef * e[d]);
+                float rhs = coef * e[d];
+                if constexpr (VISC) rhs += (cc == d ? vm[i][0] + vm[i][1] : vm[i][0]) * de[d];
+                sp[i][3 * cc + d] = ai[d] * (ai[d] * sp[i][3 * cc + d] + rhs);
             }
         // shear parts: 9 sxy(x) <- Dx+ vy, 10 sxy(y) <- Dy+ vx, 11 sxz(x) <- Dx+ vz,
         //              12 sxz(z) <- Dz+ vx, 13 syz(y) <- Dy+ vz, 14 syz(z) <- Dz+ vy
-        sp[i][9] = axy_x * (axy_x * sp[i][9] + mxy * e[4]);
-        sp[i][10] = axy_y * (axy_y * sp[i][10] + mxy * e[3]);
-        sp[i][11] = axz_x * (axz_x * sp[i][11] + mxz * e[6]);
-        sp[i][12] = axz_z * (axz_z * sp[i][12] + mxz * e[5]);
-        sp[i][13] = ayz_y * (ayz_y * sp[i][13] + myz * e[8]);
-        sp[i][14] = ayz_z * (ayz_z * sp[i][14] + myz * e[7]);
+        float sh[6] = {mxy * e[4], mxy * e[3], mxz * e[6], mxz * e[5], myz * e[8], myz * e[7]};
+        if constexpr (VISC) {
+            sh[0] += vm[i][2] * de[4];
+            sh[1] += vm[i][2] * de[3];
+            sh[2] += vm[i][3] * de[6];
+            sh[3] += vm[i][3] * de[5];
+            sh[4] += vm[i][4] * de[8];
+            sh[5] += vm[i][4] * de[7];
+        }
+        sp[i][9] = axy_x * (axy_x * sp[i][9] + sh[0]);
+        sp[i][10] = axy_y * (axy_y * sp[i][10] + sh[1]);
+        sp[i][11] = axz_x * (axz_x * sp[i][11] + sh[2]);
+        sp[i][12] = axz_z * (axz_z * sp[i][12] + sh[3]);
+        sp[i][13] = ayz_y * (ayz_y * sp[i][13] + sh[4]);
+        sp[i][14] = ayz_z * (ayz_z * sp[i][14] + sh[5]);
+        if constexpr (VISC) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) EP[(long)ep_slot(q) * g.n + cell] = e[q];
+        }
         // point sources of this shot in this row
         const int j0 = jr[i][0], j1 = jr[i][1];
         if (j0 != j1 && step < inj.nt_w) {

@@ -4,6 +4,7 @@ Bar (FP32 kernels vs FP64 oracle): relative L2 <= 1e-4 per trace component
 (p, vx, vy, vz) over all receivers and samples.  Derivative operators alone:
 <= 2e-5 relative (a few FP32 FFT round-offs).
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -317,3 +318,75 @@ def test_blackman_smoothed_sources_against_oracle(B):
             e = rel(g[k, c], refs[k][c])
             say(f"  shot {k} comp {c} rel-L2 {e:.3e}")
             assert e <= TOL
+
+
+# ---------------------------------------------------------------------------
+def viscous_workload(nt=150, shots=2, seed=21, kspace=1):
+    """The small heterogeneous workload with Kelvin-Voigt viscosities: chi and
+    eta random per cell, eta = 0 in the water layer (the harmonic mean then
+    gives zero shear viscosity on the nodes touching it).  chi + 2 eta stays
+    near 1e6 Pa s, where dt k_max^2 (chi + 2 eta) / rho ~ 0.2: stable, and at
+    the wavelet's frequencies the amplitude loss over the run is ~10 %."""
+    w = small_workload(nt=nt, shots=shots, seed=seed, kspace=kspace)
+    rng = np.random.default_rng(seed + 100)
+    shape = w.model.shape
+    w.chi = 2.0e5 + 3.0e5 * rng.random(shape)
+    w.eta = 1.5e5 + 2.5e5 * rng.random(shape)
+    w.eta[:5] = 0.0
+    return w
+
+
+@pytest.mark.parametrize("kspace", [1, 0])
+def test_kelvin_voigt_viscosity_against_oracle(B, kspace):
+    """Viscous stress update (eq. 1-2, backward difference of the velocity
+    derivatives) against the FP64 oracle, and the loss it causes is far above
+    the tolerance (the viscous terms are exercised)."""
+    w = viscous_workload(kspace=kspace)
+    say("viscous kspace", kspace, w.model.shape, w.n_shots)
+    g, refs = run_both(B, w, w.nt)
+    loss = dataclasses.replace(w, chi=None, eta=None)
+    lossless = B.Solver.from_workload(loss)
+    lossless.set_workload_sources(loss)
+    g0 = lossless.run(w.nt).cpu().numpy()
+    lossless.close()
+    for k in range(w.n_shots):
+        for c in range(4):
+            e = rel(g[k, c], refs[k][c])
+            d = rel(g0[k, c], refs[k][c])
+            say(f"  shot {k} comp {c} rel-L2 {e:.3e} (lossless differs by {d:.3e})")
+            assert e <= TOL
+            assert d > 100 * TOL
+        assert np.linalg.norm(g[k]) < np.linalg.norm(g0[k])
+
+
+def test_kelvin_voigt_state_matches_oracle_and_checkpoints(B):
+    """The 33 state fields (24 split parts + the previous step's nine velocity
+    derivatives in the documented order) agree with the oracle's after 40
+    steps, and a restored checkpoint continues bit-exactly."""
+    w = viscous_workload(nt=90, shots=1)
+    s = B.Solver.from_workload(w)
+    assert s.n_state == 33
+    s.set_workload_sources(w)
+    a = s.run(40).cpu().numpy()
+    st = s.get_state()
+    b = s.run(50).cpu().numpy()
+    o = oracle.Solver.from_workload(w)
+    assert o.n_state == 33
+    o.set_sources(w.src_ijk, w.src_m, w.wavelet)
+    o.run(40)
+    ref = o.get_state()
+    o.close()
+    for f in range(33):
+        e = rel(st[f], ref[f])
+        assert e <= TOL, (f, e)
+    s2 = B.Solver.from_workload(w)
+    s2.set_tuning(**s.tuning_values())
+    s2.set_workload_sources(w)
+    s2.set_state(st, 40)
+    np.testing.assert_array_equal(s2.run(50).cpu().numpy(), b)
+    # back to lossless: 24 state fields
+    s2.set_viscosity(None, None)
+    assert s2.n_state == 24
+    s.close()
+    s2.close()
+    assert a.shape == (1, 4, w.rec.shape[0], 40)
