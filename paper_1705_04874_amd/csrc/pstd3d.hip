@@ -339,6 +339,8 @@ struct pstd3d_ctx {
     float2* tw = nullptr;      // x, y, z twiddles
     float2* sym = nullptr;     // per axis D-, D+
     float* kap = nullptr;
+    float* k2tab = nullptr;    // per-axis (c_ref dt / 2)^2 k^2 for the kappa series
+    bool kseries_ok = false;   // the series is accurate on this grid
     int* rec_ptr = nullptr;
     int4* rec_ent = nullptr;
     ZDesc* zdesc = nullptr;
@@ -430,6 +432,7 @@ struct pstd3d_ctx {
         (void)hipFree(tw);
         (void)hipFree(sym);
         (void)hipFree(kap);
+        (void)hipFree(k2tab);
         (void)hipFree(rec_ptr);
         (void)hipFree(rec_ent);
         (void)hipFree(zdesc);
@@ -571,6 +574,43 @@ int build_model(pstd3d_ctx* c, const pstd3d_model* m)
     if (rc) return rc;
     c->O.kap = c->kap;
     c->O.kapn = c->kap + kmain;
+
+    // kappa as a power series in s = (c_ref dt / 2)^2 |k|^2 (sin(a)/a = sum_n
+    // (-s)^n / (2n+1)!), for the z operator to evaluate instead of reading the
+    // table: per-axis squares (x over 0..nx/2) and eight coefficients with the
+    // 1/(nx ny nz) folded in.  Offered where s stays <= 4 on the whole grid
+    // (the ninth term is then below 2e-10 of kappa).
+    const double b2 = 0.25 * c->c_ref * c->c_ref * dt * dt;
+    std::vector<float> hk2;
+    size_t k2off[3];
+    double smax = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        k2off[d] = hk2.size();
+        double mx = 0.0;
+        for (int mi = 0; mi < len[d]; ++mi) {
+            const double k = kval(mi, N[d], c->h[d]);
+            hk2.push_back(c->kspace ? (float)(b2 * k * k) : 0.0f);
+            mx = std::max(mx, b2 * k * k);
+        }
+        smax += mx;
+    }
+    rc = dev_upload(&c->k2tab, hk2);
+    if (rc) return rc;
+    for (int d = 0; d < 3; ++d) c->O.k2[d] = c->k2tab + k2off[d];
+    double fact = 1.0;
+    for (int t = 0; t < 8; ++t) {
+        if (t > 0) fact *= (2.0 * t) * (2.0 * t + 1.0);
+        c->O.kc[t] = c->kspace ? (float)(((t & 1) ? -1.0 : 1.0) / fact * inv_n) : (t == 0 ? (float)inv_n : 0.0f);
+    }
+    // The stress phase's operator (3 inputs, 3 outputs each: every input's
+    // blocks re-read the table) measured faster with the series, the velocity
+    // phase's (6 inputs, 1-2 outputs) with the table.  PSTD_KAPPA=table or
+    // series forces one way for both phases.
+    c->kseries_ok = !c->kspace || smax <= 4.0;
+    const char* km = std::getenv("PSTD_KAPPA");
+    const std::string kmode = km ? km : "";
+    c->O.kpoly[0] = (c->kseries_ok && kmode == "series") ? 1 : 0;
+    c->O.kpoly[1] = (c->kseries_ok && kmode != "table") ? 1 : 0;
     {
         std::vector<ZDesc> zd(1);
         zd[0].ph[0] = phase_v();

@@ -79,6 +79,13 @@ struct Ops {
     const float2* sym[3][2];   // per axis, [0] = D-, [1] = D+ : i k exp(-+ i k h/2)
     const float* kap;          // kappa(|k|) / (nx ny nz), main block [nz][ny][ldx]
     const float* kapn;         // the same on the Nyquist plane [nz][ny]
+    // kappa evaluated in the kernel instead of read from the table (kpoly[phase]
+    // = 1): s = (c_ref dt / 2)^2 |k|^2 from the per-axis squares k2[d] (x:
+    // 0..nx/2), kappa / (nx ny nz) = sum_n kc[n] s^n, the series of sin(a)/a in
+    // s = a^2
+    int kpoly[2];
+    const float* k2[3];
+    float kc[8];
 };
 
 // device-resident descriptor of the two derivative phases (read with uniform
@@ -207,8 +214,20 @@ __device__ __forceinline__ void pencil_set(float2* s, int p, int x, float v)
 // ---------------------------------------------------------------------------
 // V phase tail: inverse x FFT of the 9 stress derivatives, velocity split-PML
 // update (eq. 2 second line), receivers vx vy vz, x FFT of the summed v.
+// Occupancy hint for the velocity update: at power-of-two lengths up to 256
+// with 256 or 512 threads (and 512 with 512) the compiler fits it in 96 VGPRs
+// without spilling when asked for 5 waves per SIMD (4 otherwise), which
+// measured faster; at other lengths the same request spills to scratch or
+// cannot be met, so it is not made there.  (The stress
+// update, asked the same, measured slightly slower.)
 template <int NX, int NT>
-__global__ __launch_bounds__(NT) void k_vel(Geo g, Mat m, Pml pm, const float2* __restrict__ twx,
+constexpr int vel_waves()
+{
+    return (NX >= 32 && (NX & (NX - 1)) == 0 && NT >= 256 && (NX <= 256 || NT == 512)) ? 5 : 1;
+}
+
+template <int NX, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vel_waves<NX, NT>()))) void k_vel(Geo g, Mat m, Pml pm, const float2* __restrict__ twx,
                                             float* __restrict__ fields, float2* __restrict__ spec,
                                             Rec rc, float* __restrict__ traces,
                                             const int* __restrict__ stepp, int* __restrict__ stepn, int n0,
@@ -642,6 +661,14 @@ __global__ __launch_bounds__(NT) void k_z(Geo g, const float2* __restrict__ twz,
     __shared__ float2 tw[NZ];
     __shared__ float2 symz[2][NZ];
     __shared__ float2 symc[2][2][TX];
+    __shared__ float kz2[NZ];
+    __shared__ float kxy2[TX];
+    // the forward spectrum is reused by every output of the input field; kept
+    // in registers it stays live through the inverse transforms (about a
+    // quarter of the kernel's VGPRs), so where it takes at most 16 KB it is
+    // parked in thread-private LDS slots instead
+    constexpr bool STASH = QL * RL * NT * (int)sizeof(float2) <= 16384;
+    __shared__ float2 xs[STASH ? QL * RL * NT : 1];
     const int tmain = (g.nxm + TX - 1) / TX;
     const int shot = blockIdx.z / ph.nin, fi = blockIdx.z % ph.nin;
     long off, zs;
@@ -667,11 +694,18 @@ __global__ __launch_bounds__(NT) void k_z(Geo g, const float2* __restrict__ twz,
         ncol = min(TX, g.ny - ky0);
         kap = ops.kapn + ky0;
     }
+    const bool kpoly = ops.kpoly[phase] != 0;
     for (int i = threadIdx.x; i < NZ; i += NT) {
         tw[i] = twz[i];
         symz[0][i] = gld(ops.sym[2][0] + i);
         symz[1][i] = gld(ops.sym[2][1] + i);
+        if (kpoly) kz2[i] = gld(ops.k2[2] + i);
     }
+    if (kpoly)
+        for (int i = threadIdx.x; i < TX; i += NT) {
+            const int c = min(i, ncol - 1);
+            kxy2[i] = gld(ops.k2[0] + kx0 + kxc * c) + gld(ops.k2[1] + ky0 + kyc * c);
+        }
     // x and y symbols of this tile's columns (main tiles: kx0 + c and ky0;
     // Nyquist tile: nx/2 and ky0 + c), so that the multiply loop reads LDS only
     for (int i = threadIdx.x; i < 4 * TX; i += NT) {
@@ -687,15 +721,29 @@ __global__ __launch_bounds__(NT) void k_z(Geo g, const float2* __restrict__ twz,
         for (int r = 0; r < RL; ++r) {
             int c, z;
             const bool ok = reg_coords<NZ, RL, TX, NT, true>(q, r, c, z);
-            // unconditional load (no branch between the loads) at a valid
-            // element: slots past the last butterfly (ok false) carry z >= NZ
-            const float kv = gld(kap + (ok ? z : 0) * zs + min(c, ncol - 1));
+            float kv;
+            if (kpoly) {
+                const float sv = kxy2[min(c, TX - 1)] + kz2[ok ? z : 0];
+                kv = ops.kc[7];
+#pragma unroll
+                for (int t = 6; t >= 0; --t) kv = fmaf(kv, sv, ops.kc[t]);
+            } else {
+                // unconditional load (no branch between the loads) at a valid
+                // element: slots past the last butterfly (ok false) carry z >= NZ
+                kv = gld(kap + (ok ? z : 0) * zs + min(c, ncol - 1));
+            }
             kr[q][r] = (ok && c < ncol) ? kv : 0.f;
         }
     float2* __restrict__ sb = spec + (long)shot * g.sstride;
     const Tile in{sb + (long)(in0 + fi) * g.nspec + off, 1, zs, ncol};
     float2 X[QL][RL];
     fft_g2r<NZ, TX, NT, -1, 1, IS, true>(s, tw, in, X);
+    if constexpr (STASH) {
+#pragma unroll
+        for (int q = 0; q < QL; ++q)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) xs[(q * RL + r) * NT + threadIdx.x] = X[q][r];
+    }
     for (int o = 0; o < ph.nout[fi]; ++o) {
         const int axis = ph.axis[fi][o], plus = ph.plus[fi][o];
         // symbol table of this output: along z indexed by z, along x or y by column
@@ -709,7 +757,8 @@ __global__ __launch_bounds__(NT) void k_z(Geo g, const float2* __restrict__ twz,
                 int c, z;
                 reg_coords<NZ, RL, TX, NT, true>(q, r, c, z);
                 const float2 sv = tab[byz ? z : c];
-                Y[q][r] = c_scale(c_mul(sv, X[q][r]), kr[q][r]);
+                const float2 xv = STASH ? xs[(q * RL + r) * NT + threadIdx.x] : X[q][r];
+                Y[q][r] = c_scale(c_mul(sv, xv), kr[q][r]);
             }
         __syncthreads();   // s was read by the previous pass
         const Tile out{sb + (long)(9 + ph.oidx[fi][o]) * g.nspec + off, 1, zs, ncol};

@@ -10,6 +10,9 @@ times (one context, graph replay of step pairs).
    the wavelet by m samples delays every trace by m samples exactly (the
    state stays exactly zero until the source starts), and the derivative
    operators at lengths 384 and 256 match the oracle on a thin grid.
+   At full size the oracle can still take one step: from the GPU's state
+   after 600 steps (waves in the PML on every face) one GPU step and one FP64
+   oracle step agree on every cell of all 24 split fields.
  * 64 shots batched on the 128^3 model: selected shots equal the same shots
    run alone, bit for bit.
 """
@@ -56,7 +59,8 @@ def test_layered128_full_against_oracle_golden(B):
         assert e <= 1e-4
 
 
-@pytest.mark.parametrize("shape", [(256, 16, 384), (16, 384, 40)])
+# the full-size lengths, and the largest built length (512) on each axis
+@pytest.mark.parametrize("shape", [(256, 16, 384), (16, 384, 40), (16, 20, 512), (512, 16, 24), (20, 512, 16)])
 def test_derivatives_at_large_lengths(B, shape):
     import torch
     say("derivs", shape)
@@ -114,6 +118,41 @@ def test_layered384_time_shift_is_exact(layered384_runs):
     a, b = layered384_runs["base"], layered384_runs["lag"]
     assert np.abs(b[..., :lag]).max() == 0.0
     np.testing.assert_array_equal(b[..., lag:], a[..., :-lag])
+
+
+def test_layered384_one_step_from_a_late_state_matches_oracle(B):
+    """Full size, autotuned launch shapes: state after n GPU steps -> one more
+    GPU step, against one FP64 oracle step from the same (FP32) state.  The
+    tolerance covers the FP32 operators of one step (~1e-6 of each field)."""
+    n = 600
+    w = inputs.layered384_workload(nt=n + 1)
+    say("layered384 one step", w.model.shape, n)
+    s = B.Solver.from_workload(w)
+    s.set_workload_sources(w)
+    s.run(n)
+    st = s.get_state()
+    tr_gpu = s.run(1).cpu().numpy()[0]
+    got = s.get_state()
+    s.close()
+    o = oracle.Solver.from_workload(w)
+    o.set_sources(w.src_ijk, w.src_m, w.wavelet)
+    o.set_state(st.astype(np.float64))
+    del st
+    o.step = n
+    tr_ref = o.run(1)
+    ref = o.get_state()
+    o.close()
+    worst = 0.0
+    for f in range(24):
+        nr = np.linalg.norm(ref[f])
+        assert nr > 0, f
+        e = float(np.linalg.norm(got[f].astype(np.float64) - ref[f]) / nr)
+        worst = max(worst, e)
+        assert e <= 2e-5, (oracle.STATE_NAMES[f], e)
+    for c in range(4):
+        e = float(np.linalg.norm(tr_gpu[c] - tr_ref[c]) / np.linalg.norm(tr_ref[c]))
+        assert e <= 2e-5, (c, e)
+    say(f"  worst field rel-L2 {worst:.2e}")
 
 
 def test_batch_of_64_shots_matches_single_shots(B):

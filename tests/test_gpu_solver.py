@@ -390,3 +390,75 @@ def test_kelvin_voigt_state_matches_oracle_and_checkpoints(B):
     s.close()
     s2.close()
     assert a.shape == (1, 4, w.rec.shape[0], 40)
+
+
+def test_degenerate_inputs(B):
+    """Empty and degenerate inputs: a shot without sources records exact zeros
+    next to a live shot; a zero moment tensor records exact zeros; a wavelet
+    shorter than the run equals the same wavelet zero-padded; nt = 0 is a
+    no-op; a model without receivers runs; chi = eta = 0 reproduces the
+    lossless traces (up to the order of two roundings)."""
+    import torch
+    w = small_workload(nt=40, shots=1, seed=9)
+    src, m6 = w.src_ijk[:1], w.src_m[:1]
+    wav = w.wavelet[:1, :40]
+    s = B.Solver.from_workload(w)
+    s.set_sources([0, 0, 1], src, m6, wav)
+    two = s.run(40).cpu().numpy()
+    assert not two[0].any() and two[1].any()
+    s.set_sources([0, 1], src, np.zeros((1, 6)), wav)
+    assert not s.run(40).cpu().numpy().any()
+    s.set_sources([0, 1], src, m6, wav)
+    full = s.run(40).cpu().numpy()
+    np.testing.assert_array_equal(full[0], two[1])
+    short = wav[:, :12]
+    s.set_sources([0, 1], src, m6, short)
+    a = s.run(40).cpu().numpy()
+    padded = np.concatenate([short, np.zeros((1, 28))], axis=1)
+    s.set_sources([0, 1], src, m6, padded)
+    np.testing.assert_array_equal(a, s.run(40).cpu().numpy())
+    step = s.step
+    e = s.run(0)
+    assert e.numel() == 0 and s.step == step
+    n = B.Solver(w.model.vp, w.model.vs, w.model.rho, w.d, w.dt, pml=w.pml, rec=np.zeros((0, 3), np.int32))
+    n.set_sources([0, 1], src, m6, wav)
+    assert n.run(10).shape == (1, 4, 0, 10)
+    st = n.get_state()
+    assert np.isfinite(st).all() and st.any()
+    z = B.Solver.from_workload(w)
+    z.set_tuning(**s.tuning_values())
+    z.set_viscosity(np.zeros(w.model.shape), np.zeros(w.model.shape))
+    z.set_sources([0, 1], src, m6, wav)
+    zv = z.run(40).cpu().numpy()
+    assert float(np.abs(zv - full).max()) <= 1e-5 * float(np.abs(full).max())
+    for x in (s, n, z):
+        x.close()
+
+
+@pytest.mark.parametrize("dt", [0.8e-3, 2.2e-3])
+def test_kappa_series_against_oracle(B, monkeypatch, dt):
+    """The z operator can evaluate the k-space correction as the power series of
+    sin(a)/a in s = a^2 (a = c_ref |k| dt / 2) instead of reading the table.
+    Both ways against the FP64 oracle; dt = 2.2 ms puts s near 4, the largest
+    value the series is offered for (the corner wavenumbers), and is stable
+    because the corrected scheme with c_ref >= c_max has no CFL limit."""
+    w = small_workload(nt=60, shots=1, seed=12)
+    w.dt = dt
+    ref = oracle.run_shot(w, nt=w.nt)
+    out = {}
+    for mode in ("table", "series", "default"):
+        if mode == "default":
+            monkeypatch.delenv("PSTD_KAPPA", raising=False)   # series in the stress phase only
+        else:
+            monkeypatch.setenv("PSTD_KAPPA", mode)
+        s = B.Solver.from_workload(w)
+        s.set_workload_sources(w)
+        out[mode] = s.run(w.nt).cpu().numpy()[0]
+        s.close()
+    for c in range(4):
+        for mode in ("table", "series", "default"):
+            e = rel(out[mode][c], ref[c])
+            say(f"  dt {dt} {mode} comp {c} rel-L2 {e:.3e}")
+            assert e <= TOL
+        assert rel(out["series"][c], out["table"][c]) <= 2e-5
+        assert rel(out["default"][c], out["table"][c]) <= 2e-5
