@@ -647,6 +647,14 @@ Rec rec_of(const pstd3d_ctx* c) { return Rec{c->rec_ptr, c->rec_ent, c->n_rec}; 
 Inj inj_of(const pstd3d_ctx* c) { return Inj{c->inj_ptr, c->inj_ent, c->wav, c->nt_w}; }
 
 // one leapfrog step of every shot of a context
+// Grid of the two update kernels (see update_block): (shots, row blocks) for
+// a batch, (row blocks, 1) for one shot.
+dim3 update_grid(const pstd3d_ctx* c)
+{
+    const int nrb = (c->g.nrows + c->xf.rows - 1) / c->xf.rows;
+    return c->g.shot_fast ? dim3(c->n_shots, nrb) : dim3(nrb, c->n_shots);
+}
+
 // Step n reads the step counter word n & 1 and the velocity kernel writes n + 1
 // into the other word.
 void enqueue_step(pstd3d_ctx* c, hipStream_t st, float* traces, int n0, int ldt, int parity)
@@ -655,7 +663,7 @@ void enqueue_step(pstd3d_ctx* c, hipStream_t st, float* traces, int n0, int ldt,
     int* nxt = c->stepd + (parity ^ 1);
     const Geo& g = c->g;
     const int S = c->n_shots;
-    const dim3 gx((g.nrows + c->xf.rows - 1) / c->xf.rows, S);
+    const dim3 gx = update_grid(c);
     const int tyn = (g.nxm + c->yf.tile - 1) / c->yf.tile + g.has_nyq;
     const int tzn = (g.nxm + c->zf.tile - 1) / c->zf.tile + g.has_nyq;
     long e;
@@ -745,7 +753,7 @@ int autotune(pstd3d_ctx* c)
         *us = ms * 1000.f / 3.f;
         return e;
     };
-    const dim3 gx((g.nrows + c->xf.rows - 1) / c->xf.rows, S);
+    const dim3 gx = update_grid(c);
     for (int k = 0; k < PSTD_TUNE_COUNT; ++k) {
         int best = -1;
         for (int i = 0; i < c->nvar[k]; ++i) {
@@ -981,6 +989,12 @@ int pstd3d_set_sources(pstd3d_ctx* c, int n_shots, const int32_t* shot_ofs, cons
     for (size_t i = 0; i < w.size(); ++i) w[i] = (float)wavelet[i];
 
     c->release_shots();
+    {
+        int ymax = 65535;
+        (void)hipDeviceGetAttribute(&ymax, hipDeviceAttributeMaxGridDimY, c->device);
+        const int nrb = (c->g.nrows + c->xf.rows - 1) / c->xf.rows;
+        c->g.shot_fast = (n_shots > 1 && nrb <= ymax) ? 1 : 0;
+    }
     const size_t fbytes = (size_t)n_shots * c->g.fstride * sizeof(float);
     const size_t sbytes = (size_t)n_shots * c->g.sstride * sizeof(float2);
     HIP_TRY(hipMalloc(&c->fields, fbytes));

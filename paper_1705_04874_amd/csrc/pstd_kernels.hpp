@@ -27,6 +27,7 @@ struct Geo {
     long nspec;                        // complex values per spectrum
     long fstride;                      // floats per shot of split fields (24 n)
     long sstride;                      // complex values per shot of spectra (18 nspec)
+    int shot_fast;                     // update kernels' grid is (shots, row blocks)
 };
 
 // material coefficients pre-multiplied by dt (FP64 on the host, stored FP32)
@@ -211,27 +212,42 @@ __device__ __forceinline__ void pencil_set(float2* s, int p, int x, float v)
     f[p & 1] = v;
 }
 
-// ---------------------------------------------------------------------------
-// V phase tail: inverse x FFT of the 9 stress derivatives, velocity split-PML
-// update (eq. 2 second line), receivers vx vy vz, x FFT of the summed v.
+// Block -> (shot, first row) of the update kernels.  A batch of shots is
+// launched on a grid of (shots, row blocks), so that consecutive blocks take
+// consecutive shots of one row block and the shots read the model's material
+// and PML tables at about the same time and share them in cache; one shot
+// (or more row blocks than a grid's y extent holds) on (row blocks, shots).
+// The choice is a scalar flag: no division, so shot and row stay scalar.
+__device__ __forceinline__ void update_block(const Geo& g, int& shot, int& row0, int rows)
+{
+    if (g.shot_fast) {
+        shot = blockIdx.x;
+        row0 = blockIdx.y * rows;
+    } else {
+        shot = blockIdx.y;
+        row0 = blockIdx.x * rows;
+    }
+}
+
 // Occupancy hint for the velocity update: at power-of-two lengths up to 256
 // with 256 or 512 threads (and 512 with 512) the compiler fits it in 96 VGPRs
 // without spilling when asked for 5 waves per SIMD (4 otherwise), which
 // measured faster; at other lengths the same request spills to scratch or
-// cannot be met, so it is not made there.  (The stress
-// update, asked the same, measured slightly slower.)
+// cannot be met, so it is not made there.  (The stress update, asked the
+// same, measured slightly slower.)
 template <int NX, int NT>
 constexpr int vel_waves()
 {
     return (NX >= 32 && (NX & (NX - 1)) == 0 && NT >= 256 && (NX <= 256 || NT == 512)) ? 5 : 1;
 }
 
+// ---------------------------------------------------------------------------
+// V phase tail: inverse x FFT of the 9 stress derivatives, velocity split-PML
+// update (eq. 2 second line), receivers vx vy vz, x FFT of the summed v.
 template <int NX, int NT>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vel_waves<NX, NT>()))) void k_vel(Geo g, Mat m, Pml pm, const float2* __restrict__ twx,
-                                            float* __restrict__ fields, float2* __restrict__ spec,
-                                            Rec rc, float* __restrict__ traces,
-                                            const int* __restrict__ stepp, int* __restrict__ stepn, int n0,
-                                            int ldt)
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vel_waves<NX, NT>()))) void k_vel(
+    Geo g, Mat m, Pml pm, const float2* __restrict__ twx, float* __restrict__ fields, float2* __restrict__ spec,
+    Rec rc, float* __restrict__ traces, const int* __restrict__ stepp, int* __restrict__ stepn, int n0, int ldt)
 {
     constexpr int ROWS = rows_for(NX);
     constexpr int PS = padded_len(NX);
@@ -246,8 +262,8 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vel_waves<NX
     const int step = *stepp;
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *stepn = step + 1;
 
-    const int shot = blockIdx.y;
-    const int row0 = blockIdx.x * ROWS;
+    int shot, row0;
+    update_block(g, shot, row0, ROWS);
     float* __restrict__ F = fields + (long)shot * g.fstride;
     const float2* __restrict__ D9 = spec + (long)shot * g.sstride + 9 * g.nspec;
     float2* __restrict__ S3 = spec + (long)shot * g.sstride + 6 * g.nspec;
@@ -358,8 +374,8 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
     __shared__ float2 s[NPI * PS];
     __shared__ float2 tw[NX];
 
-    const int shot = blockIdx.y;
-    const int row0 = blockIdx.x * ROWS;
+    int shot, row0;
+    update_block(g, shot, row0, ROWS);
     float* __restrict__ F = fields + (long)shot * g.fstride + 9 * g.n;   // 15 stress parts
     // viscous: the nine velocity derivatives of the previous step, after the 24
     // split parts, in the order D-x vx, D-y vy, D-z vz, Dx+ vy, Dy+ vx, Dx+ vz,
