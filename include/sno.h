@@ -21,7 +21,7 @@
  * error of traces normalised per component by their training-set RMS.  An
  * error head predicts each sample's relative L2 error from the pooled last
  * hidden layer and the moment features; predictions whose estimate exceeds a tolerance are recomputed
- * by the pseudo-spectral solver (pstd3d), which stays the judge of accuracy.
+ * by the pseudo-spectral solver (pstd3d), which stays the reference for accuracy.
  *
  * Layout: features X [n][9] (x, y, z cell indices, moment tensor xx yy zz xy xz
  * yz in N*m), traces Y [n][4][n_rec][T] (components p, vx, vy, vz).  Errors:

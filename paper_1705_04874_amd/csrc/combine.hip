@@ -6,7 +6,10 @@
 // the events whose shifted support can touch the tile (a superset is harmless:
 // an event outside its support adds exactly 0.0).  Each thread then
 // accumulates SPT consecutive output samples of one (component, receiver) in
-// double precision, event by event, and rounds once to float.
+// double precision, event by event, and rounds once to float.  The input
+// position of its first sample costs one division per event, the others
+// follow by steps of dt_out / dt_in, and an event that misses the thread's
+// samples is skipped (most events of a tile miss most threads).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,7 +22,7 @@
 namespace {
 
 constexpr int CT = 256;          // threads per block
-constexpr int SPT = 4;           // output samples per thread
+constexpr int SPT = 8;           // output samples per thread
 constexpr int TILE = CT * SPT;   // output samples per block
 
 struct Ev {
@@ -29,7 +32,7 @@ struct Ev {
 };
 
 __global__ __launch_bounds__(CT) void k_combine(const float* __restrict__ tr, int n_rec, int nt_in, double dt_in,
-                                                double t00, double t01, double t02, double t03,
+                                                double ratio, double t00, double t01, double t02, double t03,
                                                 const int* __restrict__ tile_ptr, const int* __restrict__ tile_ev,
                                                 const Ev* __restrict__ ev, int nt_out, double dt_out,
                                                 float* __restrict__ out)
@@ -46,16 +49,21 @@ __global__ __launch_bounds__(CT) void k_combine(const float* __restrict__ tr, in
     const int e0 = tile_ptr[tile], e1 = tile_ptr[tile + 1];
     for (int j = e0; j < e1; ++j) {
         const Ev E = ev[tile_ev[j]];
+        // input position of this thread's first sample; the last one is
+        // (SPT - 1) ratio further; nothing to add outside [-1, nt_in)
+        const double u0 = ((double)m0 * dt_out - E.t - t0) / dt_in;
+        if (u0 + (SPT - 1) * ratio < -1.0 || u0 >= (double)nt_in) continue;
         const float* __restrict__ x = tr + (((long)E.src * 4 + c) * n_rec + r) * nt_in;
 #pragma unroll
         for (int s = 0; s < SPT; ++s) {
-            const int m = m0 + s;
-            const double u = ((double)m * dt_out - E.t - t0) / dt_in;
+            const double u = u0 + (double)s * ratio;
             const double fl = floor(u);
             const long i0 = (long)fl;
             const double f = u - fl;
-            const double x0 = (i0 >= 0 && i0 < nt_in) ? (double)x[i0] : 0.0;
-            const double x1 = (i0 + 1 >= 0 && i0 + 1 < nt_in) ? (double)x[i0 + 1] : 0.0;
+            const long ia = min(max(i0, 0L), (long)nt_in - 1), ib = min(max(i0 + 1, 0L), (long)nt_in - 1);
+            const float xa = x[ia], xb = x[ib];
+            const double x0 = (i0 >= 0 && i0 < nt_in) ? (double)xa : 0.0;
+            const double x1 = (i0 + 1 >= 0 && i0 + 1 < nt_in) ? (double)xb : 0.0;
             acc[s] += E.amp * ((1.0 - f) * x0 + f * x1);
         }
     }
@@ -125,8 +133,8 @@ extern "C" int seis_combine(const float* tr, int n_src, int n_rec, int nt_in, do
     if (!evs.empty())
         ok = ok && hipMemcpyAsync(dev, evs.data(), evs.size() * sizeof(Ev), hipMemcpyHostToDevice, st) == hipSuccess;
     if (ok) {
-        hipLaunchKernelGGL(k_combine, dim3(ntile, n_rec, 4), dim3(CT), 0, st, tr, n_rec, nt_in, dt_in, t0[0], t0[1],
-                           t0[2], t0[3], dptr, dlist, dev, nt_out, dt_out, out);
+        hipLaunchKernelGGL(k_combine, dim3(ntile, n_rec, 4), dim3(CT), 0, st, tr, n_rec, nt_in, dt_in,
+                           dt_out / dt_in, t0[0], t0[1], t0[2], t0[3], dptr, dlist, dev, nt_out, dt_out, out);
         ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
     }
     cleanup();
