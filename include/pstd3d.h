@@ -208,8 +208,24 @@ int pstd3d_set_tuning(pstd3d_ctx *c, const int value[PSTD_TUNE_COUNT]);
  * negative error code. */
 int pstd3d_get_tuning(const pstd3d_ctx *c, int knob, int *chosen, int *values, float *us, int max);
 
-/* Bytes of device memory held by the context. */
+/* Bytes of device memory held by the context (not counting a workspace). */
 long pstd3d_device_bytes(const pstd3d_ctx *c);
+
+/* Caller-provided device memory for the shots' state (the split fields and
+ * the spectra: the bulk of a context's memory, about 200 bytes per cell and
+ * shot), for callers that manage their own device memory pool.
+ * pstd3d_workspace_size: bytes n_shots shots need (with the current viscosity
+ * setting), or a negative error code.  pstd3d_set_workspace: from the next
+ * pstd3d_set_sources on, the shots' state lives in dev_ptr (device memory of
+ * the context's device, 256-byte aligned, `bytes` long); that call fails with
+ * PSTD_EINVAL if the shots need more.  NULL returns to memory the context
+ * allocates itself.  The call clears the shots (call pstd3d_set_sources
+ * again).  The memory stays the caller's: the context never frees it, and the
+ * caller keeps it allocated and leaves it alone while the context uses it (up
+ * to pstd3d_destroy, or a later pstd3d_set_workspace).  The source tables
+ * (a few bytes per source) are still allocated by the context. */
+long pstd3d_workspace_size(const pstd3d_ctx *c, int n_shots);
+int pstd3d_set_workspace(pstd3d_ctx *c, void *dev_ptr, long bytes);
 void pstd3d_destroy(pstd3d_ctx *c);
 const char *pstd3d_last_error(void);
 

@@ -58,6 +58,9 @@ _L.pstd3d_get_tuning.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POIN
 TUNE_KNOBS = ("y_tile", "z_tile", "vel_threads", "str_threads")
 _L.pstd3d_device_bytes.argtypes = [C.c_void_p]
 _L.pstd3d_device_bytes.restype = C.c_long
+_L.pstd3d_workspace_size.argtypes = [C.c_void_p, C.c_int]
+_L.pstd3d_workspace_size.restype = C.c_long
+_L.pstd3d_set_workspace.argtypes = [C.c_void_p, C.c_void_p, C.c_long]
 _L.pstd3d_destroy.argtypes = [C.c_void_p]
 _L.pstd3d_last_error.restype = C.c_char_p
 _L.seis_combine.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, _dp, C.c_int, _ip, _dp, _dp,
@@ -232,6 +235,26 @@ class Solver:
         _check(_L.pstd3d_derivs(self._h, int(phase), C.c_void_p(x.data_ptr()), C.c_void_p(out.data_ptr()),
                                 _stream_handle(stream)), "pstd3d_derivs")
         return out
+
+    def workspace_size(self, n_shots):
+        """Device bytes the state of n_shots shots needs in a caller workspace."""
+        n = _L.pstd3d_workspace_size(self._h, int(n_shots))
+        if n < 0:
+            _check(int(n), "pstd3d_workspace_size")
+        return int(n)
+
+    def set_workspace(self, buf):
+        """Keep the shots' state in `buf` (a contiguous CUDA tensor, kept referenced
+        here) from the next set_sources on; None returns to the library's own
+        memory.  Clears the shots."""
+        if buf is None:
+            _check(_L.pstd3d_set_workspace(self._h, None, 0), "pstd3d_set_workspace")
+        else:
+            assert buf.is_cuda and buf.is_contiguous()
+            nbytes = buf.numel() * buf.element_size()
+            _check(_L.pstd3d_set_workspace(self._h, C.c_void_p(buf.data_ptr()), nbytes), "pstd3d_set_workspace")
+        self._ws = buf
+        self.n_shots = 0
 
     @property
     def device_bytes(self):

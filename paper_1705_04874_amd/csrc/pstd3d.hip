@@ -283,6 +283,10 @@ int dev_upload(T** dst, const std::vector<T>& h)
     return PSTD_OK;
 }
 
+// shot state in a caller's workspace: the split fields first, the spectra at
+// the next 256-byte boundary
+size_t spec_offset(size_t fbytes) { return (fbytes + 255) / 256 * 256; }
+
 double pml_alpha(double pos, int n, int L, double A, double c, double h)
 {
     if (L <= 0) return 0.0;
@@ -352,6 +356,9 @@ struct pstd3d_ctx {
     int n_shots = 0;
     float* fields = nullptr;
     float2* spec = nullptr;
+    bool own_state = true;     // fields and spec allocated here (false: in the caller's workspace)
+    char* ws = nullptr;        // caller's workspace for the shot state (pstd3d_set_workspace)
+    long ws_bytes = 0;
     int* inj_ptr = nullptr;
     int4* inj_ent = nullptr;
     float* wav = nullptr;
@@ -412,8 +419,11 @@ struct pstd3d_ctx {
 
     void release_shots()
     {
-        (void)hipFree(fields);
-        (void)hipFree(spec);
+        if (own_state) {
+            (void)hipFree(fields);
+            (void)hipFree(spec);
+        }
+        own_state = true;
         (void)hipFree(inj_ptr);
         (void)hipFree(inj_ent);
         (void)hipFree(wav);
@@ -442,6 +452,13 @@ struct pstd3d_ctx {
 };
 
 namespace {
+
+// device bytes of n_shots shots' state in a workspace (fields, then spectra)
+size_t state_bytes(const pstd3d_ctx* c, int n_shots)
+{
+    const size_t fbytes = (size_t)n_shots * c->g.fstride * sizeof(float);
+    return spec_offset(fbytes) + (size_t)n_shots * c->g.sstride * sizeof(float2);
+}
 
 int build_model(pstd3d_ctx* c, const pstd3d_model* m)
 {
@@ -997,8 +1014,18 @@ int pstd3d_set_sources(pstd3d_ctx* c, int n_shots, const int32_t* shot_ofs, cons
     }
     const size_t fbytes = (size_t)n_shots * c->g.fstride * sizeof(float);
     const size_t sbytes = (size_t)n_shots * c->g.sstride * sizeof(float2);
-    HIP_TRY(hipMalloc(&c->fields, fbytes));
-    HIP_TRY(hipMalloc(&c->spec, sbytes));
+    if (c->ws) {
+        const size_t need = state_bytes(c, n_shots);
+        if ((long)need > c->ws_bytes)
+            return fail(PSTD_EINVAL, "workspace of " + std::to_string(c->ws_bytes) + " bytes is below the " +
+                                         std::to_string(need) + " the shots need (pstd3d_workspace_size)");
+        c->fields = (float*)c->ws;
+        c->spec = (float2*)(c->ws + spec_offset(fbytes));
+        c->own_state = false;
+    } else {
+        HIP_TRY(hipMalloc(&c->fields, fbytes));
+        HIP_TRY(hipMalloc(&c->spec, sbytes));
+    }
     c->n_shots = n_shots;
     HIP_TRY(hipMemset(c->fields, 0, fbytes));
     HIP_TRY(hipMemset(c->spec, 0, sbytes));
@@ -1378,7 +1405,27 @@ int pstd3d_get_tuning(const pstd3d_ctx* c, int knob, int* chosen, int* values, f
 long pstd3d_device_bytes(const pstd3d_ctx* c)
 {
     if (!c) return 0;
-    return c->bytes + (c->visc ? 20L * c->g.n : 0L) + (long)c->n_shots * (c->g.fstride * 4 + c->g.sstride * 8);
+    const long state = c->own_state ? (long)c->n_shots * (c->g.fstride * 4 + c->g.sstride * 8) : 0L;
+    return c->bytes + (c->visc ? 20L * c->g.n : 0L) + state;
+}
+
+long pstd3d_workspace_size(const pstd3d_ctx* c, int n_shots)
+{
+    if (!c || n_shots < 1) return fail(PSTD_EINVAL, "bad arguments");
+    return (long)state_bytes(c, n_shots);
+}
+
+int pstd3d_set_workspace(pstd3d_ctx* c, void* dev_ptr, long bytes)
+{
+    if (!c || (dev_ptr && bytes <= 0)) return fail(PSTD_EINVAL, "bad arguments");
+    if (dev_ptr && ((uintptr_t)dev_ptr % 256) != 0) return fail(PSTD_EINVAL, "workspace must be 256-byte aligned");
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipDeviceSynchronize());
+    c->release_shots();
+    c->step = 0;
+    c->ws = (char*)dev_ptr;
+    c->ws_bytes = dev_ptr ? bytes : 0;
+    return PSTD_OK;
 }
 
 void pstd3d_destroy(pstd3d_ctx* c)

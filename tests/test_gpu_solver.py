@@ -462,3 +462,38 @@ def test_kappa_series_against_oracle(B, monkeypatch, dt):
             assert e <= TOL
         assert rel(out["series"][c], out["table"][c]) <= 2e-5
         assert rel(out["default"][c], out["table"][c]) <= 2e-5
+
+
+def test_caller_workspace(B):
+    """Shot state in caller-provided device memory: the same traces bit for bit
+    (the workspace starts as garbage: set_sources clears it), the context's own
+    memory shrinks by the state, a short or misaligned workspace is rejected,
+    and NULL returns to the context's own memory."""
+    import torch
+    w = small_workload(nt=60, shots=2, seed=15)
+    a = B.Solver.from_workload(w)
+    a.set_workload_sources(w)
+    ref = a.run(60).cpu().numpy()
+    own = a.device_bytes
+    b = B.Solver.from_workload(w)
+    b.set_tuning(**a.tuning_values())
+    need = b.workspace_size(2)
+    assert need >= 2 * 24 * int(np.prod(w.model.shape)) * 4
+    b.set_workspace(torch.empty(need - 256, dtype=torch.uint8, device="cuda"))
+    with pytest.raises(B.PstdError) as e:
+        b.set_workload_sources(w)
+    assert e.value.code == B.PSTD_EINVAL
+    buf = torch.full((need + 512,), 0x7f, dtype=torch.uint8, device="cuda")
+    with pytest.raises(B.PstdError) as e:
+        b.set_workspace(buf[1:])
+    assert e.value.code == B.PSTD_EINVAL
+    b.set_workspace(buf)
+    b.set_workload_sources(w)
+    assert b.device_bytes < own
+    np.testing.assert_array_equal(b.run(60).cpu().numpy(), ref)
+    b.set_workspace(None)
+    b.set_workload_sources(w)
+    assert b.device_bytes == own
+    np.testing.assert_array_equal(b.run(60).cpu().numpy(), ref)
+    a.close()
+    b.close()
