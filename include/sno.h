@@ -52,6 +52,9 @@ typedef struct {
     double feat_scale[9];
     int n_four;         /* Fourier time features (0 .. SNO_MAX_FOUR) */
     double four_cycles[64]; /* their frequencies, cycles per window of T samples */
+    int pos_mod;        /* 1: also each position feature times each cos and sin
+                           feature (6 n_four more lift channels), so that a source
+                           shift can move the phase of the time features; 0: off */
 } sno_cfg;
 #define SNO_MAX_FOUR 64  /* size of four_cycles */
 
@@ -61,10 +64,14 @@ typedef struct {
     double lr;          /* peak learning rate, cosine decay to 0 */
     uint64_t seed;      /* shuffling (std::mt19937_64) */
     int n_calib;        /* last n_calib samples fit the error head, not the weights */
+    /* optional (may be NULL): called on the calling thread after every epoch
+     * with the epoch index and its mean training loss */
+    void (*on_epoch)(int epoch, float loss, void *user);
+    void *user;
 } sno_train_cfg;
 
-/* Create a model; params (host float, sno_n_params values, order P [C][4 +
- * 2 n_four], pb [C], {W_l [C][C], b_l [C], Rr_l, Ri_l [K][C][C]}_l, Q1 [H][C],
+/* Create a model; params (host float, sno_n_params values, order P [C][NA]
+ * with NA = 4 + 2 n_four (+ 6 n_four with pos_mod), pb [C], {W_l [C][C], b_l [C], Rr_l, Ri_l [K][C][C]}_l, Q1 [H][C],
  * q1b [H], Q2 [6 O][H], q2b [6 O]) are the initial weights. */
 int sno_create(const sno_cfg *cfg, const float *params, sno **out);
 long sno_n_params(const sno_cfg *cfg);

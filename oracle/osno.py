@@ -36,6 +36,7 @@ class Dims:
     n_pos: int = 3         # position features (broadcast along time)
     n_mt: int = 6          # moment-tensor features (the output is linear in them)
     four: tuple = ()       # Fourier time features: frequencies in cycles per window
+    pos_mod: bool = False  # also each position feature times each cos / sin feature
     C: int = 64            # width
     T: int = 1024          # time samples
     K: int = 16            # retained modes
@@ -45,8 +46,9 @@ class Dims:
 
 
 def n_lift(d: Dims):
-    """Input channels of the lift: position, t / T, cos and sin per frequency."""
-    return d.n_pos + 1 + 2 * len(d.four)
+    """Input channels of the lift: position, t / T, cos and sin per frequency,
+    and with position modulation n_pos x (cos, sin) products per frequency."""
+    return d.n_pos + 1 + 2 * len(d.four) + (2 * d.n_pos * len(d.four) if d.pos_mod else 0)
 
 
 def param_shapes(d: Dims):
@@ -111,6 +113,13 @@ def features(src, d: Dims):
     for f, c in enumerate(d.four):
         A[:, d.n_pos + 1 + 2 * f, :] = np.cos(2 * math.pi * c * t)
         A[:, d.n_pos + 2 + 2 * f, :] = np.sin(2 * math.pi * c * t)
+    if d.pos_mod:
+        # products with the position features, order (frequency, position, cos / sin)
+        base = d.n_pos + 1 + 2 * len(d.four)
+        for f, c in enumerate(d.four):
+            for k in range(d.n_pos):
+                A[:, base + 2 * (d.n_pos * f + k), :] = src[:, k, None] * np.cos(2 * math.pi * c * t)
+                A[:, base + 2 * (d.n_pos * f + k) + 1, :] = src[:, k, None] * np.sin(2 * math.pi * c * t)
     return A
 
 

@@ -308,12 +308,15 @@ def seis_combine(traces, t0, src_idx, amp, t_origin, nt_out, dt_in, dt_out, out=
 class SnoCfg(C.Structure):
     _fields_ = [("n_rec", C.c_int), ("T", C.c_int), ("C", C.c_int), ("K", C.c_int), ("L", C.c_int), ("H", C.c_int),
                 ("feat_off", C.c_double * 9), ("feat_scale", C.c_double * 9),
-                ("n_four", C.c_int), ("four_cycles", C.c_double * 64)]
+                ("n_four", C.c_int), ("four_cycles", C.c_double * 64), ("pos_mod", C.c_int)]
+
+
+_EPOCH_CB = C.CFUNCTYPE(None, C.c_int, C.c_float, C.c_void_p)
 
 
 class SnoTrainCfg(C.Structure):
     _fields_ = [("epochs", C.c_int), ("batch", C.c_int), ("lr", C.c_double), ("seed", C.c_uint64),
-                ("n_calib", C.c_int)]
+                ("n_calib", C.c_int), ("on_epoch", _EPOCH_CB), ("user", C.c_void_p)]
 
 
 _L.sno_n_params.argtypes = [C.POINTER(SnoCfg)]
@@ -350,15 +353,15 @@ def _dev(t):
 class Surrogate:
     """Spectral neural operator surrogate on the current GPU (see include/sno.h)."""
 
-    def __init__(self, n_rec, T, C_, K, L, H, feat_off, feat_scale, params, four_cycles=()):
+    def __init__(self, n_rec, T, C_, K, L, H, feat_off, feat_scale, params, four_cycles=(), pos_mod=False):
         four = [float(v) for v in four_cycles]
         if len(four) > 64:
             raise ValueError("at most 64 Fourier feature frequencies")
         self.cfg = SnoCfg(int(n_rec), int(T), int(C_), int(K), int(L), int(H),
                           (C.c_double * 9)(*[float(v) for v in feat_off]),
                           (C.c_double * 9)(*[float(v) for v in feat_scale]),
-                          len(four), (C.c_double * 64)(*(four + [0.0] * (64 - len(four)))))
-        self.n_lift = 4 + 2 * len(four)
+                          len(four), (C.c_double * 64)(*(four + [0.0] * (64 - len(four)))), int(bool(pos_mod)))
+        self.n_lift = 4 + 2 * len(four) + (6 * len(four) if pos_mod else 0)
         self.n_params = _L.sno_n_params(C.byref(self.cfg))
         if self.n_params < 0:
             raise ValueError("bad surrogate configuration")
@@ -373,8 +376,10 @@ class Surrogate:
         import torch
         return torch.empty((n, 4, self.cfg.n_rec, self.cfg.T), dtype=torch.float32, device="cuda")
 
-    def train(self, X, Y, epochs, batch, lr, seed=0, n_calib=0, stream=None):
-        tc = SnoTrainCfg(int(epochs), int(batch), float(lr), int(seed), int(n_calib))
+    def train(self, X, Y, epochs, batch, lr, seed=0, n_calib=0, stream=None, on_epoch=None):
+        """Train; on_epoch(epoch, mean_loss), if given, is called after every epoch."""
+        cb = _EPOCH_CB(lambda ep, loss, _u: on_epoch(int(ep), float(loss))) if on_epoch else _EPOCH_CB()
+        tc = SnoTrainCfg(int(epochs), int(batch), float(lr), int(seed), int(n_calib), cb, None)
         curve = np.zeros(max(1, int(epochs)), np.float32)
         _scheck(_L.sno_train(self._h, _dev(X), _dev(Y), X.shape[0], C.byref(tc), curve.ctypes.data_as(_fp),
                              _stream_handle(stream)), "sno_train")

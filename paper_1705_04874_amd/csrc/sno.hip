@@ -161,10 +161,21 @@ struct Feat {
     int n_four;
 };
 
-// lift input A[b][i][t], NA = 4 + 2 n_four channels: the 3 normalised position
-// features, t / T, then cos and sin of 2 pi c_f t / T per frequency
+// lift input A[b][i][t], NA channels: the 3 normalised position features,
+// t / T, cos and sin of 2 pi c_f t / T per frequency, and with position
+// modulation (NA = 4 + 8 n_four) the products p_k cos, p_k sin for each
+// frequency f and position feature k, in the order (f, k, cos / sin)
+__device__ __forceinline__ float four_feat(const Feat& f, int q, int sine, int t, int T)
+{
+    // phase c t / T reduced to [0, 1) turns before the sine and cosine
+    const float ph = f.cyc[q] * (float)t / (float)T;
+    const float r = 2.f * 3.14159265358979f * (ph - floorf(ph));
+    return sine ? sinf(r) : cosf(r);
+}
+
 __global__ void k_features(const float* __restrict__ X, Feat f, int B, int T, int NA, float* __restrict__ A)
 {
+    const int nbase = 4 + 2 * f.n_four;
     const long n = (long)B * NA * T;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
         const int t = e % T;
@@ -175,12 +186,11 @@ __global__ void k_features(const float* __restrict__ X, Feat f, int B, int T, in
             v = (X[b * 9 + i] - f.off[i]) * f.inv[i];
         } else if (i == 3) {
             v = (float)t / (float)T;
+        } else if (i < nbase) {
+            v = four_feat(f, (i - 4) >> 1, (i - 4) & 1, t, T);
         } else {
-            // phase c t / T reduced to [0, 1) turns before the sine and cosine
-            const int q = (i - 4) >> 1;
-            const float ph = f.cyc[q] * (float)t / (float)T;
-            const float r = 2.f * 3.14159265358979f * (ph - floorf(ph));
-            v = ((i - 4) & 1) ? sinf(r) : cosf(r);
+            const int j = i - nbase, q = j / 6, k = (j % 6) >> 1;
+            v = (X[b * 9 + k] - f.off[k]) * f.inv[k] * four_feat(f, q, j & 1, t, T);
         }
         A[e] = v;
     }
@@ -470,12 +480,16 @@ struct sno {
 
 namespace {
 
+// lift input channels: position, t / T, cos and sin per frequency, and with
+// position modulation the 6 products per frequency
+long n_lift(const sno_cfg& c) { return 4 + 2L * c.n_four + (c.pos_mod ? 6L * c.n_four : 0L); }
+
 long layout(sno_cfg c, sno* s)
 {
     const int O = 4 * c.n_rec;
     long o = 0;
     auto take = [&](long n) { long r = o; o += n; return r; };
-    long P = take((long)c.C * (4 + 2 * c.n_four)), pb = take(c.C);
+    long P = take((long)c.C * n_lift(c)), pb = take(c.C);
     long W[16], b[16], Rr[16], Ri[16];
     for (int l = 0; l < c.L; ++l) {
         W[l] = take((long)c.C * c.C);
@@ -510,7 +524,7 @@ bool cfg_ok(const sno_cfg* c)
         if (!(c->feat_scale[i] != 0.0) || !std::isfinite(c->feat_off[i]) || !std::isfinite(c->feat_scale[i])) return false;
     for (int i = 3; i < 9; ++i)
         if (c->feat_off[i] != 0.0) return false;
-    if (c->n_four < 0 || c->n_four > SNO_MAX_FOUR) return false;
+    if (c->n_four < 0 || c->n_four > SNO_MAX_FOUR || (c->pos_mod != 0 && c->pos_mod != 1)) return false;
     for (int f = 0; f < c->n_four; ++f)
         if (!(c->four_cycles[f] > 0.0 && c->four_cycles[f] <= c->T / 2)) return false;
     return true;
@@ -647,7 +661,7 @@ int sno_create(const sno_cfg* cfg, const float* params, sno** out)
     if (!s) return sfail(PSTD_ENOMEM, "host allocation");
     s->cfg = *cfg;
     s->O = 4 * cfg->n_rec;
-    s->NA = 4 + 2 * cfg->n_four;
+    s->NA = n_lift(*cfg);
     s->np = layout(*cfg, s);
     s->feat.n_four = cfg->n_four;
     for (int f = 0; f < cfg->n_four; ++f) s->feat.cyc[f] = (float)cfg->four_cycles[f];
@@ -808,6 +822,7 @@ int sno_train(sno* s, const float* X, const float* Y, int n, const sno_train_cfg
         for (float v : lbuf) lsum += v;
         if (loss_curve) loss_curve[ep] = (float)(lsum / std::max(1, steps_per_epoch));
         if (!std::isfinite(lsum)) return sfail(PSTD_EUNSTABLE, "training diverged");
+        if (tc->on_epoch) tc->on_epoch(ep, (float)(lsum / std::max(1, steps_per_epoch)), tc->user);
     }
     // error head: least squares of log(relative error) on the pooled last
     // hidden layer of the calibration samples, plus a one-sided 95 % margin

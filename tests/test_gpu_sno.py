@@ -33,14 +33,15 @@ def rel(a, b):
 
 def make(B, d, theta):
     return B.Surrogate(d.O // 4, d.T, d.C, d.K, d.L, d.H, np.zeros(9), np.ones(9), theta.astype(np.float32),
-                       four_cycles=d.four)
+                       four_cycles=d.four, pos_mod=d.pos_mod)
 
 
 SMALL = osno.Dims(four=(3.0, 7.0, 12.5), C=16, T=64, K=4, L=2, H=32, O=8)
+SMALL_PM = osno.Dims(four=(3.0, 7.0, 12.5), pos_mod=True, C=16, T=64, K=4, L=2, H=32, O=8)
 FULL = osno.Dims(four=inputs.sno_fourier_cycles(32, 4.0, 128.0), C=64, T=1024, K=16, L=4, H=256, O=256)
 
 
-@pytest.mark.parametrize("d", [SMALL, FULL], ids=["small", "full"])
+@pytest.mark.parametrize("d", [SMALL, SMALL_PM, FULL], ids=["small", "small_posmod", "full"])
 def test_forward_matches_oracle(B, d):
     import torch
     rng = np.random.default_rng(0)
@@ -71,9 +72,9 @@ def test_output_is_linear_in_the_moment_tensor(B):
     assert np.abs(y[3]).max() == 0.0
 
 
-def test_gradient_matches_oracle(B):
+@pytest.mark.parametrize("d", [SMALL, SMALL_PM], ids=["small", "small_posmod"])
+def test_gradient_matches_oracle(B, d):
     import torch
-    d = SMALL
     rng = np.random.default_rng(1)
     theta = init(d, 2) + 0.05 * rng.standard_normal(osno.n_params(d))
     theta = theta.astype(np.float32).astype(np.float64)

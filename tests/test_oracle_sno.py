@@ -47,7 +47,11 @@ def test_gelu_derivative():
     assert np.abs(fd - osno.gelu_grad(x)).max() < 1e-8
 
 
-def test_gradient_matches_finite_differences():
+D_PM = osno.Dims(n_pos=3, n_mt=6, four=(3.0, 7.5), pos_mod=True, C=4, T=32, K=5, L=2, H=6, O=5)
+
+
+@pytest.mark.parametrize("D", [D, D_PM], ids=["plain", "posmod"])
+def test_gradient_matches_finite_differences(D):
     rng = np.random.default_rng(1)
     theta = init(D, 3)
     theta += 0.05 * rng.standard_normal(theta.size)        # break the zero biases / positive R
@@ -95,3 +99,31 @@ def test_fourier_features_have_their_frequencies():
         assert np.argmax(np.abs(sp)) == int(c) and abs(sp[int(c)].real - d.T / 2) < 1e-9
         sp = np.fft.rfft(A[d.n_pos + 2 + 2 * f])
         assert np.argmax(np.abs(sp)) == int(c) and abs(sp[int(c)].imag + d.T / 2) < 1e-9
+
+
+def test_position_modulated_features_shift_the_phase():
+    """With position modulation a linear map of the lift input can move the
+    phase of a time feature with the source position: cos(w t - a p) is, to
+    first order in p, cos(w t) + a p sin(w t); the product channels carry
+    exactly p cos and p sin at each frequency (order frequency, position,
+    cos / sin), and are zero at p = 0."""
+    d = osno.Dims(four=(4.0, 11.0), pos_mod=True, T=64)
+    rng = np.random.default_rng(4)
+    src = np.concatenate([rng.uniform(-1, 1, (2, 3)), np.zeros((2, 6))], axis=1)
+    src[1, :3] = 0.0
+    A = osno.features(src, d)
+    base = d.n_pos + 1 + 2 * len(d.four)
+    assert A.shape[1] == base + 2 * d.n_pos * len(d.four)
+    t = np.arange(d.T) / d.T
+    for f, c in enumerate(d.four):
+        for k in range(d.n_pos):
+            p = src[0, k]
+            np.testing.assert_allclose(A[0, base + 2 * (3 * f + k)], p * np.cos(2 * np.pi * c * t), atol=1e-15)
+            np.testing.assert_allclose(A[0, base + 2 * (3 * f + k) + 1], p * np.sin(2 * np.pi * c * t), atol=1e-15)
+    assert not A[1, base:].any()
+    # first-order phase shift through the product channels
+    a, f = 0.05, 1
+    p = src[0, 0]
+    lin = A[0, d.n_pos + 1 + 2 * f] + a * A[0, base + 2 * (3 * f + 0) + 1]
+    exact = np.cos(2 * np.pi * d.four[f] * t - a * p)
+    assert np.abs(lin - exact).max() <= (a * p) ** 2
