@@ -91,7 +91,10 @@ int pstd3d_create(const pstd3d_model *m, const double d[3], double dt, const pst
  * In step n each stress component c,d of the source cell receives
  * -dt * w[n] * M_cd / (dx dy dz), split equally over its split parts; shear
  * components go 1/4 to each of the four shear nodes around the cell centre
- * (eq. 6-7; Sec. II-A point sources). */
+ * (eq. 6-7; Sec. II-A point sources).  The shots' state is allocated here
+ * (hipMalloc), or placed in the workspace given to pstd3d_set_workspace; the
+ * first call of a context also times the launch-shape candidates (see
+ * pstd3d_set_tuning). */
 int pstd3d_set_sources(pstd3d_ctx *c, int n_shots, const int32_t *shot_ofs, const int32_t *src_ijk,
                        const double *m6, const double *wavelet, int nt_w);
 
