@@ -1,19 +1,23 @@
 #!/usr/bin/env python3
 """Benchmark: Gcell-steps/s of the FP32 pseudo-spectral elastic solver on one GPU.
 
-Workload (default): the 128^3 layered marine model (water over 6 sediment
-layers with a seeded +-5 % correlated perturbation), dx = 10 m, dt = 0.8 ms,
-16-cell PML, one double-couple source with a 25 Hz Ricker wavelet, 64 x 64
-four-component seabed receivers, 2000 leapfrog steps.  One bench step is one
-complete shot: reset of the state and 2000 time steps through the HIP kernels
-(spectral derivatives, split-PML updates, source injection, receiver
-gathers), with the model tables already resident in HBM.
+Workload (default): the 384 x 384 x 256 layered marine model (water over 6
+sediment layers with a seeded +-5 % correlated perturbation), dx = 10 m,
+dt = 0.8 ms, 20-cell PML, one double-couple source with a 25 Hz Ricker
+wavelet, 128 x 128 four-component seabed receivers, a shot of 4000 leapfrog
+steps.  One bench step is a chunk of 200 leapfrog steps of that shot through
+the HIP kernels (spectral derivatives, split-PML updates, source injection,
+receiver gathers); the shot is reset when its 4000 steps are done, so the
+default 20 timed steps are one whole shot.  The model tables and the trace
+buffer are resident in HBM when the timed region starts.
 
 Prints one JSON line with the throughput, the roofline position of the
-dominant kernel (HIP-event timing over the timed region) and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+dominant kernel (HIP-event timing), the whole step against the algorithmic
+bytes, the parity of the same launch configuration against the stored FP64
+oracle state, and the FP64 CPU oracle timed on a bounded sample of the same
+shot.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--workload ...]
 """
 import argparse
 import json
@@ -68,22 +72,80 @@ def kernel_bytes_per_cell(nx, nxh):
     }
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+GOLDEN = {"layered128": "layered128_oracle_traces.npz", "layered384": "layered384_oracle_planes.npz"}
+
+
+def parity_check(args, w, s, binding, torch, np, chunk_traces):
+    """rel-L2 of this launch configuration against the stored FP64 oracle results:
+    traces of a whole 128^3 shot, or all 24 split fields of the 384 x 384 x 256 shot
+    on three planes through the source after the golden's step count."""
+    gold = os.path.join(ROOT, "tests", "golden", GOLDEN.get(args.workload, ""))
+    if args.workload not in GOLDEN or not os.path.exists(gold):
+        return None
+    g = np.load(gold, allow_pickle=False)
+    nt = int(g["nt"])
+    from tests.golden.make_layered128_golden import model_digest
+    wg = {"layered128": inputs_mod().layered128_workload,
+          "layered384": inputs_mod().layered384_workload}[args.workload](nt=nt)
+    if str(g["digest"]) != model_digest(wg):
+        return {"error": "workload generator changed since the golden was written"}
+    s.reset()
+    if args.workload == "layered128":
+        tr = s.run(nt).cpu().numpy()[0][:, g["receivers"]].astype(np.float64)
+        ref = g["traces"]
+        return {c: float(np.linalg.norm(tr[i] - ref[i]) / np.linalg.norm(ref[i]))
+                for i, c in enumerate(["p", "vx", "vy", "vz"])}
+    s.run(nt)
+    st = s.get_state()
+    from tests.golden.make_layered384_golden import planes
+    worst = {}
+    for name, zs, ys, xs in planes(w):
+        got = st[:, zs, ys, xs].astype(np.float64)
+        ref = g[name].astype(np.float64)
+        for f in range(ref.shape[0]):
+            nr = np.linalg.norm(ref[f])
+            if nr > 0:
+                worst[f] = max(worst.get(f, 0.0), float(np.linalg.norm(got[f] - ref[f]) / nr))
+    del st
+    return {"state_after_steps": nt, "planes": 3, "fields": 24,
+            "max_rel_l2": max(worst.values()), "median_rel_l2": float(np.median(list(worst.values())))}
+
+
+def inputs_mod():
+    from paper_1705_04874_amd import inputs
+    return inputs
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5, help="timed shots")
-    ap.add_argument("--warmup", type=int, default=1, help="untimed shots")
-    ap.add_argument("--nt", type=int, default=2000, help="time steps per shot")
-    ap.add_argument("--workload", default="layered128",
-                    choices=["layered128", "layered384", "paper125x75x300", "batched"],
+    ap.add_argument("--steps", type=int, default=20, help="timed bench steps (chunks of --chunk leapfrog steps)")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed bench steps")
+    ap.add_argument("--nt", type=int, default=None, help="leapfrog steps per shot (default: the workload's)")
+    ap.add_argument("--chunk", type=int, default=200, help="leapfrog steps per bench step")
+    ap.add_argument("--workload", default="layered384",
+                    choices=["layered384", "layered128", "paper125x75x300", "batched", "combine"],
                     help="batched: 64 shots on the 128^3 model plus 24 uneven models advanced together in one "
-                         "graph per step pair, then seis_combine of 300 events")
+                         "graph per step pair, then seis_combine of 300 events; combine: seis_combine alone "
+                         "on the batched configuration's record size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target oracle sample time")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run 1 GiB device copies first (reference kernels for HBM counters)")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event pass")
-    ap.add_argument("--profile-steps", type=int, default=1, help="shots in the per-kernel event pass")
+    ap.add_argument("--profile-steps", type=int, default=1, help="bench steps in the per-kernel event pass")
     ap.add_argument("--tuning", default="",
                     help="pin the launch shapes instead of autotuning: y_tile,z_tile,vel_threads,str_threads "
                          "(e.g. 16,16,256,256; 0 leaves a knob to the autotuner)")
@@ -103,16 +165,23 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batched":
         return bench_batched(args, binding, inputs, torch)
+    if args.workload == "combine":
+        return bench_combine(args, binding, inputs, torch)
     dev = torch.device("cuda:0")
-    w = {"layered128": inputs.layered128_workload, "layered384": inputs.layered384_workload,
-         "paper125x75x300": inputs.paper_shaped_workload}[args.workload](nt=args.nt)
+    make = {"layered128": inputs.layered128_workload, "layered384": inputs.layered384_workload,
+            "paper125x75x300": inputs.paper_shaped_workload}[args.workload]
+    w = make() if args.nt is None else make(nt=args.nt)
+    nt = w.nt
+    chunk = min(args.chunk, nt)
     nz, ny, nx = w.model.shape
     cells = nx * ny * nz
     s = binding.Solver.from_workload(w)
     if args.tuning:
         s.set_tuning(*[int(v) for v in args.tuning.split(",")])
     s.set_workload_sources(w)
-    traces = torch.empty((s.n_shots, 4, s.n_rec, args.nt), dtype=torch.float32, device=dev)
+    traces = torch.empty((s.n_shots, 4, s.n_rec, chunk), dtype=torch.float32, device=dev)
+    print(f"workload {w.name}: {nx}x{ny}x{nz}, shot of {nt} steps, bench step = {chunk} steps",
+          file=sys.stderr, flush=True)
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)   # 1 GiB
@@ -127,53 +196,51 @@ def main():
                           "copy_calibration_bytes_written": b.numel() * 4}), file=sys.stderr, flush=True)
         del a, b
 
-    for i in range(args.warmup):
-        s.reset()
-        s.run(args.nt, out=traces)
-        print(f"warmup shot {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
+    def bench_step():
+        # the shot restarts when its nt steps are done (the reset is part of the work)
+        if s.step + chunk > nt:
+            s.reset()
+        s.run(chunk, out=traces)
 
+    s.reset()
+    for i in range(args.warmup):
+        bench_step()
+        print(f"warmup step {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    s.reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        s.reset()
-        s.run(args.nt, out=traces)
-        print(f"timed shot {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+        bench_step()
+        print(f"timed step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
+    elapsed = time.perf_counter() - t0
 
-    # per-kernel durations: HIP events around every launch, over the same
-    # shots run again (eager launches; the timed region above replays graphs)
+    # per-kernel durations: HIP events recorded by the library on its stream
+    # around every launch, over bench steps run again eagerly (the timed region
+    # above replays graphs of step pairs)
     prof = {}
     prof_wall = None
     if not args.no_profile:
+        s.reset()
         s.profile(True)
         torch.cuda.synchronize()
         tp = time.perf_counter()
         for i in range(args.profile_steps):
-            s.reset()
-            s.run(args.nt, out=traces)
+            bench_step()
         torch.cuda.synchronize()
-        prof_wall = (time.perf_counter() - tp) / args.profile_steps
+        prof_wall = (time.perf_counter() - tp) / (args.profile_steps * chunk)
         prof = s.profile_read()
         s.profile(False)
         print("profiled pass done", file=sys.stderr, flush=True)
 
-    cell_steps = float(cells) * args.nt * args.steps * s.n_shots
+    cell_steps = float(cells) * chunk * args.steps * s.n_shots
     value = cell_steps / elapsed / 1e9
     ms_per_step = elapsed / args.steps * 1e3
 
-    # parity of the timed run against the stored FP64 oracle traces (if present)
     parity = None
-    gold = os.path.join(ROOT, "tests", "golden", "layered128_oracle_traces.npz")
-    if args.workload == "layered128" and os.path.exists(gold):
-        g = np.load(gold, allow_pickle=False)
-        if int(g["nt"]) == args.nt:
-            got = traces[0][:, torch.as_tensor(g["receivers"], device=dev)].cpu().numpy().astype(np.float64)
-            ref = g["traces"]
-            parity = {c: float(np.linalg.norm(got[i] - ref[i]) / np.linalg.norm(ref[i]))
-                      for i, c in enumerate(["p", "vx", "vy", "vz"])}
+    if not args.no_parity:
+        parity = parity_check(args, w, s, binding, torch, np, traces)
+        print("parity check done", file=sys.stderr, flush=True)
 
     roofline = None
     kernels = None
@@ -198,29 +265,34 @@ def main():
                     "alg_bytes_per_launch": kernels[dom]["alg_bytes"]}
         tot_bytes = sum(bpc.values()) * cells * s.n_shots
         step_us = sum(v["avg_us"] for v in kernels.values())
+        # the whole step: this design's algorithmic bytes (one HBM pass per
+        # kernel) and the one-pass bound of 548 B per cell-step, both at the
+        # throughput of the timed region
         roofline["step_alg_bytes_per_cell"] = round(sum(bpc.values()), 1)
         roofline["step_alg_GBs"] = round(tot_bytes / (step_us * 1e-6) / 1e9, 1)
-        roofline["timing"] = "HIP events around each launch, separate pass over the same shots"
-        roofline["profiled_ms_per_step"] = round(prof_wall * 1e3, 3)
+        roofline["step_frac"] = round(sum(bpc.values()) * value / HBM_PEAK_GBS, 4)
+        roofline["step_frac_548"] = round(548.0 * value / HBM_PEAK_GBS, 4)
+        roofline["timing"] = "HIP events around each launch on the solver's stream, separate eager pass"
+        roofline["profiled_ms_per_leapfrog_step"] = round(prof_wall * 1e3, 3)
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        ow = inputs.layered128_workload(nt=args.nt) if args.workload == "layered128" else w
-        so = oracle.Solver.from_workload(ow)
-        so.set_sources(ow.src_ijk, ow.src_m, ow.wavelet)
+        so = oracle.Solver.from_workload(w)
+        so.set_sources(w.src_ijk, w.src_m, w.wavelet)
         so.run(1)
         t = time.perf_counter()
         n_cpu = 0
-        while time.perf_counter() - t < args.cpu_seconds and n_cpu < args.nt:
+        while time.perf_counter() - t < args.cpu_seconds and n_cpu < nt:
             so.run(1)
             n_cpu += 1
         dt_cpu = time.perf_counter() - t
         so.close()
         cpu = {"value": round(cells * n_cpu / dt_cpu / 1e9, 6), "unit": "Gcell-steps/s", "cores": oracle.threads(),
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"{n_cpu} FP64 oracle steps (after 1 untimed) of the same {nx}x{ny}x{nz} shot, "
-                         f"{dt_cpu:.1f} s"}
+                         f"{dt_cpu:.1f} s; the rate of a whole {nt}-step shot is extrapolated from them"}
+        print("cpu baseline done", file=sys.stderr, flush=True)
 
     out = {
         "metric": METRIC,
@@ -235,9 +307,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "grid": [nx, ny, nz], "nt_per_shot": args.nt, "shots_per_step": s.n_shots,
-                   "receivers": s.n_rec, "pml": w.pml, "dx_m": w.d[0], "dt_s": w.dt,
-                   "step": "one full shot: state reset + nt leapfrog steps"},
+        "config": {"workload": w.name, "grid": [nx, ny, nz], "nt_per_shot": nt, "leapfrog_steps_per_step": chunk,
+                   "shots_per_step": s.n_shots, "receivers": s.n_rec, "pml": w.pml, "dx_m": w.d[0], "dt_s": w.dt,
+                   "step": f"{chunk} leapfrog steps of the shot (reset after {nt})"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity_rel_l2": parity,
@@ -250,6 +322,56 @@ def main():
     return 0
 
 
+def bench_combine(args, binding, inputs, torch):
+    """seis_combine alone on the batched configuration's record: 64 sources x 4
+    components x 4096 receivers x 2000 samples at 0.8 ms (seeded random traces),
+    300 events (amplitudes LogNormal(0, 1), origins U[0, 10 s)) into a 12 s record
+    at 1 ms.  One bench step is one call; the kernel time comes from HIP events
+    on the stream the call runs on."""
+    import numpy as np
+    n_src, n_rec, nt_in, dt_in, nt_out = 64, 4096, 2000, 0.8e-3, 12000
+    g = torch.Generator(device="cuda").manual_seed(5)
+    tr = torch.randn((n_src, 4, n_rec, nt_in), device="cuda", generator=g)
+    ev = inputs.event_catalogue(300, n_src, 10.0, 1.0, seed=2)
+    t0 = [dt_in, 0.5 * dt_in, 0.5 * dt_in, 0.5 * dt_in]
+    rec = torch.empty((4, n_rec, nt_out), dtype=torch.float32, device="cuda")
+
+    def call():
+        binding.seis_combine(tr, t0, ev.src_idx, ev.amp, ev.t_origin, nt_out, dt_in, 1e-3, out=rec)
+
+    for _ in range(max(1, args.warmup)):
+        call()
+    torch.cuda.synchronize()
+    evs = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        call()
+        e1.record()
+        evs.append((e0, e1))
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t_start) / args.steps
+    ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    used = sorted(set(int(v) for v in ev.src_idx))
+    alg = len(used) * 4 * n_rec * nt_in * 4 + 4 * n_rec * nt_out * 4
+    out = {
+        "metric": "seis_combine GB/s (algorithmic bytes)", "value": round(alg / (ms * 1e-3) / 1e9, 1),
+        "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "seis_combine_300_events_64x4x4096x2000_to_12s", "n_src": n_src, "n_rec": n_rec,
+                   "nt_in": nt_in, "nt_out": nt_out, "events": 300},
+        "roofline": {"bound": "hbm", "kernel": "k_combine", "achieved": round(alg / (ms * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None, "alg_bytes_per_launch": alg,
+                     "timing": "HIP events on the call's stream (includes the event-list upload)"},
+        "kernel_ms": round(ms, 3), "call_wall_ms": round(wall * 1e3, 3),
+        "sources_used": len(used),
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def bench_batched(args, binding, inputs, torch):
     """The batched configuration: 64 single-source shots on the 128^3 layered model
     (one context) and 24 uneven models (one context each), advanced together by
@@ -257,8 +379,9 @@ def bench_batched(args, binding, inputs, torch):
     bench step is a reset of every context plus nt steps of all of them.  Then
     seis_combine sums 300 events of the 64 shots' traces into 12 s records at
     1 ms, timed on its own."""
-    w64 = inputs.layered128_shots(64, nt=args.nt)
-    ws = [w64] + inputs.ragged_models(24, nt=args.nt)
+    nt = args.nt or 2000
+    w64 = inputs.layered128_shots(64, nt=nt)
+    ws = [w64] + inputs.ragged_models(24, nt=nt)
     ss = []
     for w in ws:
         s = binding.Solver.from_workload(w)
@@ -266,14 +389,14 @@ def bench_batched(args, binding, inputs, torch):
             s.set_tuning(*[int(v) for v in args.tuning.split(",")])
         s.set_workload_sources(w)
         ss.append(s)
-    outs = [torch.empty((s.n_shots, 4, s.n_rec, args.nt), dtype=torch.float32, device="cuda") for s in ss]
+    outs = [torch.empty((s.n_shots, 4, s.n_rec, nt), dtype=torch.float32, device="cuda") for s in ss]
     cells = sum(w.cells * w.n_shots for w in ws)
     shots = sum(w.n_shots for w in ws)
 
     def one_step():
         for s in ss:
             s.reset()
-        binding.run_many(ss, args.nt, outs=outs)
+        binding.run_many(ss, nt, outs=outs)
 
     for i in range(args.warmup):
         one_step()
@@ -285,7 +408,7 @@ def bench_batched(args, binding, inputs, torch):
         print(f"timed step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    value = cells * args.nt * args.steps / elapsed / 1e9
+    value = cells * nt * args.steps / elapsed / 1e9
 
     # seis_combine of 300 events over the 64 shots' traces
     ev = inputs.event_catalogue(300, 64, 10.0, 1.0, seed=2)
@@ -307,7 +430,7 @@ def bench_batched(args, binding, inputs, torch):
     bpc = kernel_bytes_per_cell(nxyz[0], nxyz[0] // 2 + 1)
     s.profile(True)
     s.reset()
-    s.run(min(args.nt, 40))
+    s.run(min(nt, 40))
     torch.cuda.synchronize()
     prof = s.profile_read()
     s.profile(False)
@@ -334,7 +457,7 @@ def bench_batched(args, binding, inputs, torch):
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "batched_64shots_128cubed_plus_24_ragged_models", "contexts": len(ss),
-                   "shots": shots, "cells_per_step": cells, "nt_per_shot": args.nt,
+                   "shots": shots, "cells_per_step": cells, "nt_per_shot": nt,
                    "step": "reset of every context + nt leapfrog steps of all of them (pstd3d_run_many)"},
         "seismograms_per_s": round(shots * args.steps / elapsed, 3),
         "seis_combine_ms": round(combine_ms, 3),

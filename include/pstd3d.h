@@ -211,6 +211,9 @@ int pstd3d_set_tuning(pstd3d_ctx *c, const int value[PSTD_TUNE_COUNT]);
  * negative error code. */
 int pstd3d_get_tuning(const pstd3d_ctx *c, int knob, int *chosen, int *values, float *us, int max);
 
+/* Receivers of the context (the n_rec of its model), or PSTD_EINVAL for NULL. */
+int pstd3d_n_rec(const pstd3d_ctx *c);
+
 /* Bytes of device memory held by the context (not counting a workspace). */
 long pstd3d_device_bytes(const pstd3d_ctx *c);
 
@@ -236,13 +239,22 @@ const char *pstd3d_last_error(void);
  * real-valued shifts):
  *   out[c][r][m] = sum_e amp[e] * x_e(m dt_out - t_origin[e] - t0[c]),
  * x_e(t) the linear interpolation of tr[src_idx[e]][c][r][.] at t / dt_in,
- * zero outside [0, nt_in - 1].  Accumulated in double, in event order.
+ * zero outside [0, nt_in - 1].  Each output sample is accumulated in double
+ * over its events grouped by source (sources ascending, event order within a
+ * source) and rounded once to float.
  * tr: device float [n_src][4][n_rec][nt_in]; out: device float
  * [4][n_rec][nt_out]; t0: host double[4] (time of sample 0 per component);
- * src_idx, amp, t_origin: host arrays [n_ev].  Runs on hip_stream. */
+ * src_idx, amp, t_origin: host arrays [n_ev].  The event lists (16 bytes per
+ * event and record segment of up to 12288 samples) go to a device buffer
+ * allocated and freed by the call; runs on hip_stream and returns after the
+ * stream has finished.  Errors: PSTD_EINVAL (sizes, source index out of
+ * range, non-finite value), PSTD_ENOMEM, PSTD_EDEVICE; the message is
+ * returned by seis_combine_last_error(). */
 int seis_combine(const float *tr, int n_src, int n_rec, int nt_in, double dt_in, const double t0[4],
                  int n_ev, const int32_t *src_idx, const double *amp, const double *t_origin,
                  int nt_out, double dt_out, float *out, void *hip_stream);
+/* Message of the last seis_combine error on the calling thread. */
+const char *seis_combine_last_error(void);
 
 #ifdef __cplusplus
 }

@@ -89,7 +89,8 @@ int sno_predict(sno *s, const float *X, int n, float *Y, float *est_err, void *h
 
 /* Predict, then recompute with the solver every sample whose estimated error
  * exceeds tol.  The solver context must have the surrogate's receivers, in
- * the same order; sample i is a single point source at src_ijk[3i..] with
+ * the same order (PSTD_EINVAL before any device work if its receiver count,
+ * pstd3d_n_rec, differs from cfg.n_rec); sample i is a single point source at src_ijk[3i..] with
  * moment tensor m6[6i..] (host) and wavelet (host, nt_w samples, shared);
  * the solver runs decim * T steps and every decim-th sample is kept.  used
  * (host, n, may be NULL) returns 1 where the solver answered.  Solver calls go

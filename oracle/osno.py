@@ -204,3 +204,26 @@ def adam(theta, g, m, v, step, lr, b1=0.9, b2=0.999, eps=1e-8):
     mh = m / (1 - b1 ** step)
     vh = v / (1 - b2 ** step)
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+# ---------------------------------------------------------------------------
+# Error head (a reading of this build: the paper leaves the proxy as future
+# work, Sec. VII): least squares of the log relative error on per-sample
+# features phi with a ridge, and a one-sided 95 % margin of the residuals.
+def error_head_fit(phi, err, ridge=1e-3):
+    """Fit h minimising |Phi h - log e|^2 + ridge n |h|^2 (e clamped below at
+    1e-6), by the normal equations; margin = 1.645 * the residual standard
+    deviation (n - 1 in the denominator).  Returns (h, margin)."""
+    phi = np.asarray(phi, np.float64)
+    n, D = phi.shape
+    y = np.log(np.maximum(1e-6, np.asarray(err, np.float64)))
+    A = phi.T @ phi + ridge * n * np.eye(D)
+    h = np.linalg.solve(A, phi.T @ y)
+    res = y - phi @ h
+    sd = math.sqrt(float(res @ res) / max(1, n - 1))
+    return h, 1.645 * sd
+
+
+def error_head_predict(phi, h, margin):
+    """Estimated relative error of each sample: exp(phi h + margin)."""
+    return np.exp(np.asarray(phi, np.float64) @ h + margin)

@@ -57,6 +57,7 @@ _L.pstd3d_set_tuning.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
 _L.pstd3d_get_tuning.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _fp, C.c_int]
 TUNE_KNOBS = ("y_tile", "z_tile", "vel_threads", "str_threads")
 _L.pstd3d_device_bytes.argtypes = [C.c_void_p]
+_L.pstd3d_n_rec.argtypes = [C.c_void_p]
 _L.pstd3d_device_bytes.restype = C.c_long
 _L.pstd3d_workspace_size.argtypes = [C.c_void_p, C.c_int]
 _L.pstd3d_workspace_size.restype = C.c_long
@@ -65,18 +66,19 @@ _L.pstd3d_destroy.argtypes = [C.c_void_p]
 _L.pstd3d_last_error.restype = C.c_char_p
 _L.seis_combine.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, _dp, C.c_int, _ip, _dp, _dp,
                             C.c_int, C.c_double, C.c_void_p, C.c_void_p]
+_L.seis_combine_last_error.restype = C.c_char_p
 
 
 class PstdError(RuntimeError):
-    def __init__(self, code, what):
-        msg = _L.pstd3d_last_error().decode(errors="replace")
+    def __init__(self, code, what, last_error=None):
+        msg = (last_error or _L.pstd3d_last_error)().decode(errors="replace")
         super().__init__(f"{what} failed with code {code}: {msg}")
         self.code = code
 
 
-def _check(rc, what):
+def _check(rc, what, last_error=None):
     if rc != PSTD_OK:
-        raise PstdError(rc, what)
+        raise PstdError(rc, what, last_error)
 
 
 def _stream_handle(stream=None):
@@ -299,7 +301,8 @@ def seis_combine(traces, t0, src_idx, amp, t_origin, nt_out, dt_in, dt_out, out=
     to = _f64(t_origin)
     _check(_L.seis_combine(C.c_void_p(traces.data_ptr()), n_src, n_rec, nt_in, float(dt_in), t0, si.size,
                            si.ctypes.data_as(_ip), am.ctypes.data_as(_dp), to.ctypes.data_as(_dp), int(nt_out),
-                           float(dt_out), C.c_void_p(out.data_ptr()), _stream_handle(stream)), "seis_combine")
+                           float(dt_out), C.c_void_p(out.data_ptr()), _stream_handle(stream)), "seis_combine",
+           _L.seis_combine_last_error)
     return out
 
 
@@ -395,6 +398,9 @@ class Surrogate:
 
     def predict_or_solve(self, solver, X, src_ijk, m6, wavelet, decim, tol, max_batch=64, stream=None):
         import torch
+        if _L.pstd3d_n_rec(solver._h) != self.cfg.n_rec:
+            raise ValueError(f"the solver has {_L.pstd3d_n_rec(solver._h)} receivers, the surrogate "
+                             f"{self.cfg.n_rec}")
         n = X.shape[0]
         Y = self._out(n)
         est = torch.empty(n, dtype=torch.float32, device="cuda")

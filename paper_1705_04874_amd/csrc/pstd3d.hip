@@ -1402,6 +1402,8 @@ int pstd3d_get_tuning(const pstd3d_ctx* c, int knob, int* chosen, int* values, f
     return c->nvar[knob];
 }
 
+int pstd3d_n_rec(const pstd3d_ctx* c) { return c ? c->n_rec : PSTD_EINVAL; }
+
 long pstd3d_device_bytes(const pstd3d_ctx* c)
 {
     if (!c) return 0;

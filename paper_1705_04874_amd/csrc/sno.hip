@@ -947,6 +947,10 @@ int sno_predict_or_solve(sno* s, pstd3d_ctx* solver, const float* X, const int32
     if (!s || !solver || !X || !src_ijk || !m6 || !wavelet || !Y || !est_err || n < 0 || decim < 1 ||
         max_batch < 1 || nt_w < 1)
         return sfail(PSTD_EINVAL, "bad arguments");
+    // the solver writes n_shots x 4 x (its receivers) x nt floats into a
+    // buffer sized for the surrogate's receivers: they must be the same
+    if (pstd3d_n_rec(solver) != s->cfg.n_rec)
+        return sfail(PSTD_EINVAL, "the solver's receiver count differs from the surrogate's n_rec");
     hipStream_t st = (hipStream_t)hip_stream;
     int rc = sno_predict(s, X, n, Y, est_err, hip_stream);
     if (rc) return rc;

@@ -141,3 +141,16 @@ def explosion_pressure(t, r, m0, vp, vs, rho, f0):
     from paper_1705_04874_amd.inputs import ricker_derivative
     K = rho * vp * vp - 4.0 / 3.0 * rho * vs * vs
     return m0 * K * ricker_derivative(f0, t - r / vp) / (4 * math.pi * rho * vp ** 4 * r)
+
+
+def explosion_radial_velocity(t, r, m0, vp, rho, f0):
+    """Whole-space radial particle velocity from an explosive point source with
+    moment rate m0 * w(t) (w a Ricker wavelet): the time derivative of the
+    displacement u_r = m0 / (4 pi rho vp^2) [S(tau) / r^2 + S'(tau) / (vp r)],
+    tau = t - r / vp, S' = w (Aki & Richards, Sec. 4.2), i.e.
+    v_r = m0 / (4 pi rho vp^2) [w(tau) / r^2 + w'(tau) / (vp r)]: a near-field
+    term in 1/r^2 and a far-field term in 1/r."""
+    from paper_1705_04874_amd.inputs import ricker_derivative, ricker_value
+    tau = t - r / vp
+    return m0 / (4 * math.pi * rho * vp * vp) * (ricker_value(f0, tau) / (r * r) +
+                                                 ricker_derivative(f0, tau) / (vp * r))

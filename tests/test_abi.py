@@ -63,3 +63,32 @@ def test_validation_without_device(lib):
     with pytest.raises(B.PstdError) as e:
         B.Solver(vp, vs, rho, (10, 10, 10), 1e-3, pml=9)
     assert e.value.code == B.PSTD_EINVAL
+
+
+def test_combine_validation_without_device(lib):
+    """seis_combine checks its host arguments before any device call (the
+    pointers below are never dereferenced)."""
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.seis_combine.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp,
+                                 ctypes.c_int, ip, dp, dp, ctypes.c_int, ctypes.c_double, ctypes.c_void_p,
+                                 ctypes.c_void_p]
+    lib.seis_combine_last_error.restype = ctypes.c_char_p
+    t0 = (ctypes.c_double * 4)(0, 0, 0, 0)
+    fake = ctypes.c_void_p(0x1000)
+
+    def call(src, amp, to, n_src=2, nt_in=10, dt_in=1e-3):
+        s = np.ascontiguousarray(src, np.int32)
+        a = np.ascontiguousarray(amp, np.float64)
+        t = np.ascontiguousarray(to, np.float64)
+        return lib.seis_combine(fake, n_src, 3, nt_in, dt_in, t0, s.size, s.ctypes.data_as(ip),
+                                a.ctypes.data_as(dp), t.ctypes.data_as(dp), 20, 1e-3, fake, None)
+
+    assert call([2], [1.0], [0.0]) == -1
+    assert b"source index" in lib.seis_combine_last_error()
+    assert call([-1], [1.0], [0.0]) == -1
+    assert call([0], [np.inf], [0.0]) == -1
+    assert call([0], [1.0], [np.nan]) == -1
+    assert call([0], [1.0], [0.0], nt_in=0) == -1
+    assert call([0], [1.0], [0.0], dt_in=0.0) == -1
+    assert call([0], [1.0], [0.0], n_src=0) == -1

@@ -114,3 +114,47 @@ def test_superposition_equals_joint_solver_run(B):
     for c in range(4):
         e = np.linalg.norm(got[c] - joint[c]) / np.linalg.norm(joint[c])
         assert e < 1e-5, (c, e)
+
+
+def test_long_record_in_several_segments(B):
+    """A record longer than one block's accumulator segment, input traces longer
+    than one staging chunk, and events before, inside and after the record."""
+    import torch
+    rng = np.random.default_rng(11)
+    n_src, n_rec, nt_in, dt_in = 3, 5, 9000, 1e-3
+    tr = rng.standard_normal((n_src, 4, n_rec, nt_in)).astype(np.float32)
+    t0 = [1e-3, 0.5e-3, 0.5e-3, 0.5e-3]
+    n_ev = 25
+    src = rng.integers(0, n_src, n_ev).astype(np.int32)
+    amp = rng.lognormal(0, 1, n_ev)
+    to = rng.uniform(-10.0, 30.0, n_ev)
+    nt_out, dt_out = 30001, 0.9e-3
+    say("combine segments", tr.shape, nt_out)
+    got = B.seis_combine(torch.from_numpy(tr).cuda(), t0, src, amp, to, nt_out, dt_in, dt_out).cpu().numpy()
+    ref = oracle.combine(tr, t0, src, amp, to, nt_out, dt_in, dt_out)
+    check(got, ref)
+
+
+def test_one_sample_traces_and_far_events(B):
+    """nt_in = 1 (a trace that is one spike), events far outside the record
+    (no sample touched), and repeated events of one source."""
+    import torch
+    tr = np.arange(1, 1 + 2 * 4 * 3, dtype=np.float32).reshape(2, 4, 3, 1)
+    src = np.array([1, 1, 0, 1, 0], np.int32)
+    amp = np.array([1.0, 2.0, 0.5, 1e3, 3.0])
+    to = np.array([0.0101, 0.0203, 0.0309, 1e12, -1e12])
+    got = B.seis_combine(torch.from_numpy(tr).cuda(), [0.0] * 4, src, amp, to, 40, 1e-3, 1e-3).cpu().numpy()
+    ref = oracle.combine(tr, [0.0] * 4, src, amp, to, 40, 1e-3, 1e-3)
+    check(got, ref)
+    assert np.count_nonzero(ref) > 0
+
+
+def test_invalid_arguments_are_rejected(B):
+    import torch
+    tr = torch.zeros((2, 4, 3, 10), device="cuda")
+    with pytest.raises(B.PstdError) as e:
+        B.seis_combine(tr, [0.0] * 4, [2], [1.0], [0.0], 20, 1e-3, 1e-3)
+    assert e.value.code == B.PSTD_EINVAL and "source index" in str(e.value)
+    with pytest.raises(B.PstdError) as e:
+        B.seis_combine(tr, [0.0] * 4, [0], [np.nan], [0.0], 20, 1e-3, 1e-3)
+    assert e.value.code == B.PSTD_EINVAL

@@ -60,7 +60,10 @@ def test_layered128_full_against_oracle_golden(B):
 
 
 # the full-size lengths, and the largest built length (512) on each axis
-@pytest.mark.parametrize("shape", [(256, 16, 384), (16, 384, 40), (16, 20, 512), (512, 16, 24), (20, 512, 16)])
+@pytest.mark.parametrize("shape", [(256, 16, 384), (16, 384, 40), (16, 20, 512), (512, 16, 24), (20, 512, 16),
+                                   # the lengths of the uneven-model batch (radix-5 and radix-3 plans)
+                                   (16, 20, 80), (20, 144, 16), (160, 20, 16), (96, 16, 120), (16, 96, 160),
+                                   (80, 120, 16), (144, 16, 20)])
 def test_derivatives_at_large_lengths(B, shape):
     import torch
     say("derivs", shape)
@@ -197,3 +200,80 @@ def test_ragged_batch_of_24_models_in_one_graph(B):
         s1.close()
     for s in ss:
         s.close()
+
+
+def test_run_many_of_uneven_models_against_oracle(B):
+    """Three models of uneven size whose lengths are those of the ragged batch
+    (80, 96, 120, 144, 160, 48, 64: radix-5, -3 and -2 plans on every axis),
+    advanced together by one run_many, against the FP64 oracle run of each
+    model alone: all 24 split fields after nt steps, rel-L2 <= 1e-4 each."""
+    nt = 110
+    sizes = [(80, 96, 64), (144, 120, 48), (160, 64, 80)]
+    ws, ss = [], []
+    rng = np.random.default_rng(21)
+    for i, (nx, ny, nz) in enumerate(sizes):
+        water = max(4, nz // 8)
+        m = inputs.layered(nx, ny, nz, water_cells=water, seed=40 + i)
+        src = np.array([[nx // 2 + 3, ny // 2 - 2, water + (nz - water) // 2]], np.int32)
+        mt = inputs.dc_plus_iso(rng, inputs.DV_UNIT_MOMENT)[None, :]
+        # receivers 4 cells above the source: the direct wave reaches them within nt
+        sx, sy, sz = (int(v) for v in src[0])
+        rec = inputs.receiver_block(sx - 4, sx + 4, sy - 4, sy + 4, sz - 4)
+        w = inputs.Workload(f"uneven_{nx}x{ny}x{nz}", m, (10.0, 10.0, 10.0), 0.8e-3, nt, 10, 2.0, 1, 0.0, rec, src,
+                            mt, np.array([0, 1], np.int32), inputs.ricker(25.0, 0.8e-3, nt)[None, :])
+        ws.append(w)
+        s = B.Solver.from_workload(w)
+        s.set_workload_sources(w)
+        ss.append(s)
+    say("run_many uneven", sizes, nt)
+    outs = [o.cpu().numpy() for o in B.run_many(ss, nt)]
+    for w, s, o in zip(ws, ss, outs):
+        got = s.get_state()
+        so = oracle.Solver.from_workload(w)
+        so.set_sources(w.src_ijk, w.src_m, w.wavelet)
+        tr = so.run(nt)
+        ref = so.get_state()
+        so.close()
+        worst = 0.0
+        for f in range(24):
+            e = float(np.linalg.norm(got[f].astype(np.float64) - ref[f]) / np.linalg.norm(ref[f]))
+            worst = max(worst, e)
+            assert e <= 1e-4, (w.name, oracle.STATE_NAMES[f], e)
+        for c in range(4):
+            e = float(np.linalg.norm(o[0, c] - tr[c]) / np.linalg.norm(tr[c]))
+            assert e <= 1e-4, (w.name, c, e)
+        say(f"  {w.name}: worst field rel-L2 {worst:.2e}")
+        s.close()
+
+
+def test_layered384_multistep_against_stored_oracle_planes(B):
+    """Full size, in the launch configuration the bench times (one context,
+    autotuned shapes, graph replay): the state after the golden's step count
+    against the FP64 oracle's, all 24 split fields on three planes through the
+    source (tests/golden/layered384_oracle_planes.npz), rel-L2 <= 1e-4 each."""
+    gold = os.path.join(ROOT, "tests", "golden", "layered384_oracle_planes.npz")
+    if not os.path.exists(gold):
+        pytest.fail("tests/golden/layered384_oracle_planes.npz missing (tests/golden/make_layered384_golden.py writes it)")
+    from tests.golden.make_layered128_golden import model_digest
+    from tests.golden.make_layered384_golden import planes
+    g = np.load(gold, allow_pickle=False)
+    nt = int(g["nt"])
+    w = inputs.layered384_workload(nt=nt)
+    assert str(g["digest"]) == model_digest(w), "workload generator changed since the golden was written"
+    say("layered384 multistep", w.model.shape, nt)
+    s = B.Solver.from_workload(w)
+    s.set_workload_sources(w)
+    s.run(nt)
+    st = s.get_state()
+    s.close()
+    for name, zs, ys, xs in planes(w):
+        got = st[:, zs, ys, xs].astype(np.float64)
+        ref = g[name].astype(np.float64)
+        worst = 0.0
+        for f in range(24):
+            nr = np.linalg.norm(ref[f])
+            assert nr > 0, (name, f)
+            e = float(np.linalg.norm(got[f] - ref[f]) / nr)
+            worst = max(worst, e)
+            assert e <= 1e-4, (name, oracle.STATE_NAMES[f], e)
+        say(f"  plane {name}: worst field rel-L2 {worst:.2e}")

@@ -146,6 +146,39 @@ def test_predict_or_solve_fallback(B):
     np.testing.assert_array_equal(Y1.cpu().numpy(), Yp.cpu().numpy())
 
 
+def test_predict_or_solve_rejects_a_solver_with_other_receivers(B):
+    """The fallback writes the solver's traces into buffers sized for the
+    surrogate's receivers: a solver with a different receiver count is refused
+    with PSTD_EINVAL before any device work (through the C entry point itself,
+    not only the binding's own check)."""
+    import ctypes
+    import torch
+    shape = (32, 24, 40)
+    vp = np.full(shape, 2800.0)
+    vs = np.full(shape, 1600.0)
+    rho = np.full(shape, 2200.0)
+    solver = B.Solver(vp, vs, rho, (10.0, 10.0, 10.0), 0.8e-3, pml=6, rec=inputs.receiver_line_x(12, 29, 12, 5))
+    d = osno.Dims(four=(5.0, 9.0), C=16, T=64, K=4, L=2, H=32, O=4 * 16)
+    s = make(B, d, init(d, 4))
+    X = torch.zeros((2, 9), dtype=torch.float32, device="cuda")
+    ijk = np.zeros((2, 3), np.int32)
+    m6 = np.zeros((2, 6))
+    w = np.zeros(128)
+    with pytest.raises(ValueError):
+        s.predict_or_solve(solver, X, ijk, m6, w, 2, tol=0.0)
+    Y = torch.full((2, 4, 16, 64), 7.0, device="cuda")
+    est = torch.zeros(2, device="cuda")
+    used = (ctypes.c_int * 2)()
+    L = B._L
+    rc = L.sno_predict_or_solve(s._h, solver._h, B._dev(X), ijk.ctypes.data_as(B._ip), m6.ctypes.data_as(B._dp),
+                                w.ctypes.data_as(B._dp), w.size, 2, 2, 0.0, 2, B._dev(Y), B._dev(est), used,
+                                B._stream_handle())
+    assert rc == B.PSTD_EINVAL
+    assert b"receiver" in L.sno_last_error()
+    torch.cuda.synchronize()
+    assert (Y == 7.0).all()   # nothing was written
+
+
 def test_trained_network_gains_over_the_solver_alone(B):
     """What the trained network adds to the solver: on a cluster of nearby
     sources it predicts held-out traces far better than the same network

@@ -277,6 +277,41 @@ def test_explosion_matches_whole_space_green_function(homogeneous_runs):
         assert rel(p[i][win], ana[win]) < 0.02, (o, rel(p[i][win], ana[win]))
 
 
+def test_explosion_radial_velocity_matches_whole_space_green_function(homogeneous_runs):
+    """v_r of the explosion at the receivers on the three axes, every velocity
+    component at its own staggered node: v_d of receiver q sits at q + e_d / 2,
+    so with d = node - source the component is v_r(|d|) d_d / |d| (12.5 or
+    11.5 cells along the axis for the axial component, half a cell off the axis
+    for the two others).  Samples at (n + 1/2) dt.  Near field (1/r^2) and far
+    field (1/r) both matter at these distances."""
+    R = homogeneous_runs
+    out = R["out"]["exp"]
+    t = (np.arange(R["nt"]) + 0.5) * R["dt"]
+    h = R["h"][0]
+    m0, vp, rho, f0 = 1000.0, R["vp"], R["rho"], R["f0"]
+    checked = 0
+    for i, o in enumerate(R["offs"]):
+        axes = [a for a in range(3) if o[a] != 0]
+        if len(axes) != 1:
+            continue
+        a = axes[0]
+        for b in range(3):
+            dvec = np.array(o, float) + 0.5 * np.eye(3)[b]
+            r = np.linalg.norm(dvec) * h
+            ana = physics.explosion_radial_velocity(t, r, m0, vp, rho, f0) * dvec[b] * h / r
+            win = t < r / vp + 3.0 / f0
+            got = out[1 + b][i]
+            tol = 0.02 if b == a else 0.05
+            assert rel(got[win], ana[win]) < tol, (o, b, rel(got[win], ana[win]))
+        # the near-field term is not negligible at the axial node
+        r = (abs(o[a]) + 0.5 * np.sign(o[a])) * h
+        full = physics.explosion_radial_velocity(t, r, m0, vp, rho, f0)
+        far = m0 / (4 * math.pi * rho * vp * vp) * inputs.ricker_derivative(f0, t - r / vp) / (vp * r)
+        assert np.abs(full - far).max() > 0.1 * np.abs(full).max()
+        checked += 1
+    assert checked == 6
+
+
 def test_radiation_patterns(homogeneous_runs):
     """Far-field P polarity follows gamma.M.gamma: DC tau_xy ~ sin(2 phi) in the
     xy-plane (opposite signs on the two diagonals), nodal on the axes; CLVD

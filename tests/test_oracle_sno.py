@@ -5,7 +5,13 @@
  * the hand-written gradient equals central finite differences of the loss
    for every parameter block (FP64);
  * gelu's derivative equals finite differences;
- * Adam's first step moves every weight by lr * sign(g) (bias correction);
+ * Adam's first step moves every weight by lr * sign(g) (bias correction), and
+   three steps equal the recurrence expanded by hand with beta1 = 0.9,
+   beta2 = 0.999 (the weights of g1, g2, g3 in m3 and v3, and the bias
+   corrections 1 - beta^t written out as numbers);
+ * the error head's ridge least squares equals numpy's lstsq of the augmented
+   system [Phi; sqrt(ridge n) I] h = [log e; 0], and its margin covers about
+   95 % of Gaussian residuals of known spread;
  * the output is linear in the moment-tensor features (the elastic system is
    linear in its source, eq. 2) and does not depend on them otherwise;
  * the Fourier time features are the modes numpy's FFT finds in them.
@@ -127,3 +133,60 @@ def test_position_modulated_features_shift_the_phase():
     lin = A[0, d.n_pos + 1 + 2 * f] + a * A[0, base + 2 * (3 * f + 0) + 1]
     exact = np.cos(2 * np.pi * d.four[f] * t - a * p)
     assert np.abs(lin - exact).max() <= (a * p) ** 2
+
+
+def test_adam_three_steps_equal_the_hand_expanded_recurrence():
+    rng = np.random.default_rng(4)
+    n = 7
+    theta0 = rng.standard_normal(n)
+    g = rng.standard_normal((3, n))
+    lr = 1e-2
+    th, m, v = theta0.copy(), np.zeros(n), np.zeros(n)
+    for t in range(3):
+        th, m, v = osno.adam(th, g[t], m, v, t + 1, lr)
+    # m3 = 0.1 (0.81 g1 + 0.9 g2 + g3); v3 = 0.001 (0.998001 g1^2 + 0.999 g2^2 + g3^2)
+    m3 = 0.081 * g[0] + 0.09 * g[1] + 0.1 * g[2]
+    v3 = 0.000998001 * g[0] ** 2 + 0.000999 * g[1] ** 2 + 0.001 * g[2] ** 2
+    assert np.abs(m - m3).max() < 1e-15 and np.abs(v - v3).max() < 1e-15
+    # bias corrections 1 - 0.9^t = 0.1, 0.19, 0.271 and 1 - 0.999^t = 0.001, 0.001999, 0.002997001
+    m1, v1 = 0.1 * g[0], 0.001 * g[0] ** 2
+    m2, v2 = 0.09 * g[0] + 0.1 * g[1], 0.000999 * g[0] ** 2 + 0.001 * g[1] ** 2
+    want = theta0.copy()
+    for mm, vv, c1, c2 in [(m1, v1, 0.1, 0.001), (m2, v2, 0.19, 0.001999), (m3, v3, 0.271, 0.002997001)]:
+        want = want - lr * (mm / c1) / (np.sqrt(vv / c2) + 1e-8)
+    assert np.abs(th - want).max() < 1e-13
+    # a wrong beta2 (0.99) is far off after three steps
+    th2, m2_, v2_ = theta0.copy(), np.zeros(n), np.zeros(n)
+    for t in range(3):
+        th2, m2_, v2_ = osno.adam(th2, g[t], m2_, v2_, t + 1, lr, b2=0.99)
+    assert np.abs(th2 - want).max() > 1e-5
+
+
+def test_error_head_fit_equals_lstsq_of_the_augmented_system():
+    rng = np.random.default_rng(6)
+    n, D = 200, 9
+    phi = rng.standard_normal((n, D))
+    err = np.exp(phi @ rng.standard_normal(D) * 0.3 - 3.0 + 0.2 * rng.standard_normal(n))
+    err[:3] = [0.0, 1e-9, 1e-7]                       # clamped at 1e-6
+    ridge = 1e-3
+    h, margin = osno.error_head_fit(phi, err, ridge)
+    y = np.log(np.maximum(1e-6, err))
+    aug = np.concatenate([phi, math.sqrt(ridge * n) * np.eye(D)])
+    ref = np.linalg.lstsq(aug, np.concatenate([y, np.zeros(D)]), rcond=None)[0]
+    assert np.abs(h - ref).max() < 1e-10 * np.abs(ref).max()
+    res = y - phi @ ref
+    assert margin == pytest.approx(1.645 * np.sqrt(res @ res / (n - 1)), rel=1e-12)
+
+
+def test_error_head_margin_covers_95_percent_of_gaussian_residuals():
+    rng = np.random.default_rng(8)
+    n, D, sigma = 4000, 5, 0.4
+    phi = np.concatenate([np.ones((n, 1)), rng.standard_normal((n, D - 1))], axis=1)
+    h_true = np.array([-4.0, 0.5, -0.3, 0.2, 0.1])
+    err = np.exp(phi @ h_true + sigma * rng.standard_normal(n))
+    h, margin = osno.error_head_fit(phi, err, ridge=1e-6)
+    assert np.abs(h - h_true).max() < 0.05
+    assert margin == pytest.approx(1.645 * sigma, rel=0.05)
+    est = osno.error_head_predict(phi, h, margin)
+    cover = float(np.mean(err <= est))
+    assert 0.93 < cover < 0.97
