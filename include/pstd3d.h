@@ -256,6 +256,23 @@ int seis_combine(const float *tr, int n_src, int n_rec, int nt_in, double dt_in,
 /* Message of the last seis_combine error on the calling thread. */
 const char *seis_combine_last_error(void);
 
+/* seis_combine for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same arguments, kernels and results, but the event lists go to a
+ * static device array of seis_combine_noalloc_max_bytes() bytes (4 MiB) that
+ * the library holds on each device it runs on until the process ends; the
+ * call makes no device allocation.  It needs 16 bytes per (event, record
+ * segment of up to 12288 samples) plus 16 per (source, segment) and a few
+ * hundred bytes: about 200 000 event-segments.  Larger event lists return
+ * PSTD_EINVAL before any device work (use seis_combine).  Every call on one
+ * device shares its array, so calls that overlap on one device (on other
+ * streams or threads) race; each call returns after its stream has finished.
+ * The other outputs and errors are those of seis_combine. */
+int seis_combine_noalloc(const float *tr, int n_src, int n_rec, int nt_in, double dt_in, const double t0[4],
+                         int n_ev, const int32_t *src_idx, const double *amp, const double *t_origin,
+                         int nt_out, double dt_out, float *out, void *hip_stream);
+long seis_combine_noalloc_max_bytes(void);
+
 #ifdef __cplusplus
 }
 #endif

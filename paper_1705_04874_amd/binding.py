@@ -67,6 +67,8 @@ _L.pstd3d_last_error.restype = C.c_char_p
 _L.seis_combine.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double, _dp, C.c_int, _ip, _dp, _dp,
                             C.c_int, C.c_double, C.c_void_p, C.c_void_p]
 _L.seis_combine_last_error.restype = C.c_char_p
+_L.seis_combine_noalloc.argtypes = _L.seis_combine.argtypes
+_L.seis_combine_noalloc_max_bytes.restype = C.c_long
 
 
 class PstdError(RuntimeError):
@@ -285,11 +287,16 @@ def run_many(solvers, nt, outs=None, stream=None):
     return outs
 
 
-def seis_combine(traces, t0, src_idx, amp, t_origin, nt_out, dt_in, dt_out, out=None, stream=None):
+def seis_combine(traces, t0, src_idx, amp, t_origin, nt_out, dt_in, dt_out, out=None, stream=None,
+                 noalloc=False):
     """Superposition of single-event traces on the GPU.
 
-    traces: float32 device tensor [n_src][4][n_rec][nt_in]; returns [4][n_rec][nt_out]."""
+    traces: float32 device tensor [n_src][4][n_rec][nt_in]; returns [4][n_rec][nt_out].
+    noalloc: call seis_combine_noalloc (event lists in the library's static device
+    memory; `out` must then be given, so that nothing is allocated)."""
     import torch
+    if noalloc and out is None:
+        raise ValueError("noalloc needs a preallocated out tensor")
     assert traces.is_cuda and traces.dtype == torch.float32 and traces.is_contiguous()
     n_src, four, n_rec, nt_in = traces.shape
     assert four == 4
@@ -299,7 +306,8 @@ def seis_combine(traces, t0, src_idx, amp, t_origin, nt_out, dt_in, dt_out, out=
     si = _i32(src_idx)
     am = _f64(amp)
     to = _f64(t_origin)
-    _check(_L.seis_combine(C.c_void_p(traces.data_ptr()), n_src, n_rec, nt_in, float(dt_in), t0, si.size,
+    fn = _L.seis_combine_noalloc if noalloc else _L.seis_combine
+    _check(fn(C.c_void_p(traces.data_ptr()), n_src, n_rec, nt_in, float(dt_in), t0, si.size,
                            si.ctypes.data_as(_ip), am.ctypes.data_as(_dp), to.ctypes.data_as(_dp), int(nt_out),
                            float(dt_out), C.c_void_p(out.data_ptr()), _stream_handle(stream)), "seis_combine",
            _L.seis_combine_last_error)

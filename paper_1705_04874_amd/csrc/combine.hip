@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -218,6 +219,35 @@ int launch(const Plan& p, char* dplan, const float* tr, int n_rec, int nt_in, do
     return PSTD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Work-list memory of seis_combine_noalloc: one array per device, in the
+// library's static device memory.  Host code never uses the array's name as an
+// address; it asks the runtime for each device's address once.
+constexpr size_t NOALLOC_BYTES = 4u << 20;
+__device__ __align__(256) char scratch[NOALLOC_BYTES];
+constexpr int MAX_DEVICES = 64;
+char* g_scratch_ptr[MAX_DEVICES] = {};
+std::mutex g_scratch_mu;
+
+// the address of this device's array, looked up once per device with the
+// device current
+int scratch_ptr(char** ptr)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES)
+        return cfail(PSTD_EDEVICE, "seis_combine_noalloc: no usable current device");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return cfail(PSTD_EDEVICE, std::string("seis_combine_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<char*>(p);
+    }
+    *ptr = g_scratch_ptr[dev];
+    return PSTD_OK;
+}
+
 }  // namespace
 
 extern "C" int seis_combine(const float* tr, int n_src, int n_rec, int nt_in, double dt_in, const double t0[4], int n_ev,
@@ -233,6 +263,26 @@ extern "C" int seis_combine(const float* tr, int n_src, int n_rec, int nt_in, do
     rc = launch(p, dplan, tr, n_rec, nt_in, dt_in, t0, nt_out, dt_out, out, (hipStream_t)hip_stream);
     (void)hipFree(dplan);
     return rc;
+}
+
+extern "C" long seis_combine_noalloc_max_bytes(void) { return (long)NOALLOC_BYTES; }
+
+extern "C" int seis_combine_noalloc(const float* tr, int n_src, int n_rec, int nt_in, double dt_in, const double t0[4],
+                                    int n_ev, const int32_t* src_idx, const double* amp, const double* t_origin,
+                                    int nt_out, double dt_out, float* out, void* hip_stream)
+{
+    int rc = check_args(tr, n_src, n_rec, nt_in, dt_in, t0, n_ev, src_idx, amp, t_origin, nt_out, dt_out, out);
+    if (rc || n_rec == 0 || nt_out == 0) return rc;
+    Plan p;
+    make_plan(p, n_ev, src_idx, amp, t_origin, t0, nt_in, dt_in, nt_out, dt_out);
+    if (p.bytes > NOALLOC_BYTES)
+        return cfail(PSTD_EINVAL, "seis_combine_noalloc: the event lists need " + std::to_string(p.bytes) +
+                                      " bytes, more than the " + std::to_string(NOALLOC_BYTES) +
+                                      " bytes of its static device memory (use seis_combine)");
+    char* dplan = nullptr;
+    rc = scratch_ptr(&dplan);
+    if (rc) return rc;
+    return launch(p, dplan, tr, n_rec, nt_in, dt_in, t0, nt_out, dt_out, out, (hipStream_t)hip_stream);
 }
 
 extern "C" const char* seis_combine_last_error(void) { return g_cerr.c_str(); }
