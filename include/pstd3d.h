@@ -183,27 +183,38 @@ int pstd3d_profile(pstd3d_ctx *c, int enable);
  * last pstd3d_profile(c, 1). */
 int pstd3d_profile_read(const pstd3d_ctx *c, int kind, double *total_ms, long *launches);
 
-/* Autotuner.  Four launch-shape knobs of a time step:
+/* Autotuner.  Six launch-shape knobs of a time step:
  *   PSTD_TUNE_Y, PSTD_TUNE_Z  the y and z transforms work on tiles of this
  *        many adjacent pencils (8, 16, 32 or 64, where the tile fits the LDS
  *        and register budget of its length; y tiles of 8 only where 16 does
  *        not fit);
  *   PSTD_TUNE_VEL, PSTD_TUNE_STR  threads per block of the velocity and the
  *        stress update kernels (x transforms fused with the split-PML
- *        updates): 128, 256 or 512, at most the cells of a block.
+ *        updates): 128, 256 or 512, at most the cells of a block;
+ *   PSTD_TUNE_ZT  threads per block of the z kernels: 256, or 512 where the
+ *        tile gives each of 512 threads a butterfly of a radix-8 (or 16) first
+ *        pass (half the registers per thread, so twice the waves in flight);
+ *   PSTD_TUNE_ZF  input spectra per z block: 1, or 6 (every input of the
+ *        phase in one block, which then reads its tile's kappa and symbols
+ *        once for all of them).
  * The first pstd3d_set_sources of a context times every built value of every
  * knob on the context's own state (HIP events, one warm-up and three
- * launches each) and keeps the fastest; the state is cleared afterwards.
+ * launches each; the z knobs one after another, each with the ones before
+ * at their choice) and keeps the fastest; the state is cleared afterwards.
  * pstd3d_set_tuning forces values (host int[PSTD_TUNE_COUNT]; a value must be
- * built, PSTD_EUNSUPPORTED otherwise); forced values take effect at once, and
- * a 0 entry is tuned again at the next pstd3d_set_sources.  The traces agree
+ * built, PSTD_EUNSUPPORTED otherwise, also for a z tile and z thread count
+ * that are not built together); forced values take effect at once, and a 0
+ * entry is tuned again at the next pstd3d_set_sources.  The traces agree
  * across values to FP32 rounding (the same butterflies and updates, possibly
- * contracted into fused multiply-adds differently). */
+ * contracted into fused multiply-adds differently, and radix-8 instead of
+ * radix-16 passes in the 512-thread z kernels). */
 #define PSTD_TUNE_Y 0
 #define PSTD_TUNE_Z 1
 #define PSTD_TUNE_VEL 2
 #define PSTD_TUNE_STR 3
-#define PSTD_TUNE_COUNT 4
+#define PSTD_TUNE_ZT 4
+#define PSTD_TUNE_ZF 5
+#define PSTD_TUNE_COUNT 6
 int pstd3d_set_tuning(pstd3d_ctx *c, const int value[PSTD_TUNE_COUNT]);
 /* The chosen value of `knob` (may be NULL), and its built values (host,
  * up to max entries) with the microseconds per launch measured by the last
@@ -244,7 +255,7 @@ const char *pstd3d_last_error(void);
  * source) and rounded once to float.
  * tr: device float [n_src][4][n_rec][nt_in]; out: device float
  * [4][n_rec][nt_out]; t0: host double[4] (time of sample 0 per component);
- * src_idx, amp, t_origin: host arrays [n_ev].  The event lists (16 bytes per
+ * src_idx, amp, t_origin: host arrays [n_ev].  The event lists (72 bytes per
  * event and record segment of up to 12288 samples) go to a device buffer
  * allocated and freed by the call; runs on hip_stream and returns after the
  * stream has finished.  Errors: PSTD_EINVAL (sizes, source index out of
@@ -261,9 +272,9 @@ const char *seis_combine_last_error(void);
  * the same arguments, kernels and results, but the event lists go to a
  * static device array of seis_combine_noalloc_max_bytes() bytes (4 MiB) that
  * the library holds on each device it runs on until the process ends; the
- * call makes no device allocation.  It needs 16 bytes per (event, record
+ * call makes no device allocation.  It needs 72 bytes per (event, record
  * segment of up to 12288 samples) plus 16 per (source, segment) and a few
- * hundred bytes: about 200 000 event-segments.  Larger event lists return
+ * hundred bytes: about 58 000 event-segments.  Larger event lists return
  * PSTD_EINVAL before any device work (use seis_combine).  Every call on one
  * device shares its array, so calls that overlap on one device (on other
  * streams or threads) race; each call returns after its stream has finished.

@@ -55,7 +55,7 @@ _L.pstd3d_set_viscosity.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
 _L.pstd3d_state_fields.argtypes = [C.c_void_p]
 _L.pstd3d_set_tuning.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
 _L.pstd3d_get_tuning.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), _fp, C.c_int]
-TUNE_KNOBS = ("y_tile", "z_tile", "vel_threads", "str_threads")
+TUNE_KNOBS = ("y_tile", "z_tile", "vel_threads", "str_threads", "z_threads", "z_fields")
 _L.pstd3d_device_bytes.argtypes = [C.c_void_p]
 _L.pstd3d_n_rec.argtypes = [C.c_void_p]
 _L.pstd3d_device_bytes.restype = C.c_long
@@ -149,9 +149,10 @@ class Solver:
         """0: point sources; 1: Blackman window in k-space (for later set_sources)."""
         _check(_L.pstd3d_set_source_smoothing(self._h, int(window)), "pstd3d_set_source_smoothing")
 
-    def set_tuning(self, y_tile=0, z_tile=0, vel_threads=0, str_threads=0):
+    def set_tuning(self, y_tile=0, z_tile=0, vel_threads=0, str_threads=0, z_threads=0, z_fields=0):
         """Force launch-shape knobs (0: autotuned at the next set_sources)."""
-        v = (C.c_int * 4)(int(y_tile), int(z_tile), int(vel_threads), int(str_threads))
+        v = (C.c_int * len(TUNE_KNOBS))(int(y_tile), int(z_tile), int(vel_threads), int(str_threads),
+                                        int(z_threads), int(z_fields))
         _check(_L.pstd3d_set_tuning(self._h, v), "pstd3d_set_tuning")
 
     def tuning_values(self):
@@ -319,7 +320,10 @@ def seis_combine(traces, t0, src_idx, amp, t_origin, nt_out, dt_in, dt_out, out=
 class SnoCfg(C.Structure):
     _fields_ = [("n_rec", C.c_int), ("T", C.c_int), ("C", C.c_int), ("K", C.c_int), ("L", C.c_int), ("H", C.c_int),
                 ("feat_off", C.c_double * 9), ("feat_scale", C.c_double * 9),
-                ("n_four", C.c_int), ("four_cycles", C.c_double * 64), ("pos_mod", C.c_int)]
+                ("n_four", C.c_int), ("four_cycles", C.c_double * 64), ("pos_mod", C.c_int),
+                ("frames", C.c_int), ("rec_ijk", C.POINTER(C.c_int32)), ("nz_slow", C.c_int),
+                ("slow_p", C.POINTER(C.c_double)), ("slow_s", C.POINTER(C.c_double)), ("h", C.c_double * 3),
+                ("dt", C.c_double), ("t_ref", C.c_double * 2)]
 
 
 _EPOCH_CB = C.CFUNCTYPE(None, C.c_int, C.c_float, C.c_void_p)
@@ -341,6 +345,8 @@ _L.sno_predict_or_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, _ip, _dp
 _L.sno_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
 _L.sno_gradient.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, _fp, C.c_void_p]
 _L.sno_get_params.argtypes = [C.c_void_p, _fp]
+_L.sno_adam_step.argtypes = [C.c_void_p, C.c_void_p, C.c_long, C.c_double, C.c_void_p]
+_L.sno_get_moments.argtypes = [C.c_void_p, _fp, _fp]
 _L.sno_get_scale.argtypes = [C.c_void_p, _fp]
 _L.sno_decimate.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]
 _L.sno_last_error.restype = C.c_char_p
@@ -364,7 +370,12 @@ def _dev(t):
 class Surrogate:
     """Spectral neural operator surrogate on the current GPU (see include/sno.h)."""
 
-    def __init__(self, n_rec, T, C_, K, L, H, feat_off, feat_scale, params, four_cycles=(), pos_mod=False):
+    def __init__(self, n_rec, T, C_, K, L, H, feat_off, feat_scale, params, four_cycles=(), pos_mod=False,
+                 frames=None):
+        """frames: None for the plain time axis, or a dict with the travel-time
+        alignment of include/sno.h: rec_ijk [n_rec][3], slow_p and slow_s
+        (slowness per depth cell, s/m), h (3 cell sizes, m), dt (s) and t_ref
+        (the P and S reference times, s)."""
         four = [float(v) for v in four_cycles]
         if len(four) > 64:
             raise ValueError("at most 64 Fourier feature frequencies")
@@ -372,6 +383,21 @@ class Surrogate:
                           (C.c_double * 9)(*[float(v) for v in feat_off]),
                           (C.c_double * 9)(*[float(v) for v in feat_scale]),
                           len(four), (C.c_double * 64)(*(four + [0.0] * (64 - len(four)))), int(bool(pos_mod)))
+        self.cfg.frames = 1
+        if frames is not None:
+            # kept alive until sno_create has copied them
+            self._rec = _i32(frames["rec_ijk"]).reshape(-1, 3)
+            self._sp = _f64(frames["slow_p"])
+            self._ss = _f64(frames["slow_s"])
+            assert self._rec.shape[0] == n_rec and self._sp.size == self._ss.size
+            self.cfg.frames = 2
+            self.cfg.rec_ijk = self._rec.ctypes.data_as(_ip)
+            self.cfg.nz_slow = self._sp.size
+            self.cfg.slow_p = self._sp.ctypes.data_as(_dp)
+            self.cfg.slow_s = self._ss.ctypes.data_as(_dp)
+            self.cfg.h = (C.c_double * 3)(*[float(v) for v in frames["h"]])
+            self.cfg.dt = float(frames["dt"])
+            self.cfg.t_ref = (C.c_double * 2)(*[float(v) for v in frames["t_ref"]])
         self.n_lift = 4 + 2 * len(four) + (6 * len(four) if pos_mod else 0)
         self.n_params = _L.sno_n_params(C.byref(self.cfg))
         if self.n_params < 0:
@@ -420,6 +446,16 @@ class Surrogate:
                                         wv.ctypes.data_as(_dp), wv.size, int(decim), n, float(tol), int(max_batch),
                                         _dev(Y), _dev(est), used, _stream_handle(stream)), "sno_predict_or_solve")
         return Y, est, np.array(used[:n], dtype=bool)
+
+    def adam_step(self, grad, step, lr, stream=None):
+        """One Adam step of the weights with a device gradient (test entry)."""
+        _scheck(_L.sno_adam_step(self._h, _dev(grad), int(step), float(lr), _stream_handle(stream)), "sno_adam_step")
+
+    def moments(self):
+        m = np.empty(self.n_params, np.float32)
+        v = np.empty(self.n_params, np.float32)
+        _scheck(_L.sno_get_moments(self._h, m.ctypes.data_as(_fp), v.ctypes.data_as(_fp)), "sno_get_moments")
+        return m, v
 
     def forward(self, X, stream=None):
         Y = self._out(X.shape[0])

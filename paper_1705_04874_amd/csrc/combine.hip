@@ -4,20 +4,24 @@
 // the linear interpolation of trace src_idx[e] (zero outside its samples).
 //
 // One block owns one output row (component c, receiver r) over a segment of
-// the record and keeps that segment's accumulators in LDS in double precision.
-// The events that can touch the segment are grouped by source on the host
-// (sources ascending, event order within a source), so the block stages each
-// source's input row in LDS once and applies all of that source's events from
-// there: every input trace is read from HBM once per segment, and the record
-// is written once.  Within an event, output sample m belongs to thread
-// m mod NT, so no two threads touch one accumulator and no barrier separates
-// the events of a source.
+// the record; each thread owns SPT consecutive output samples and keeps their
+// sums in registers in double precision.  The events that can touch the
+// segment are grouped by source on the host (sources ascending, event order
+// within a source), so the block stages each source's input row in LDS once
+// and applies all of that source's events from there: every input trace is
+// read from HBM once per segment and the record is written once.  A thread
+// skips an event whose sample range (precomputed on the host per event and
+// component) misses its samples, so the per-event cost falls on the few
+// waves an event touches.
 //
-// The input position of a sample is u = m (dt_out / dt_in) - (t_origin + t0)/dt_in,
-// one fused multiply-add in double; the interpolation weight f = u - floor(u)
-// and the two samples around it follow.  The lerp is continuous in u, so the
-// rounding of u (a few ulps against the direct quotient) moves the result by
-// the same few ulps.
+// The input position of a sample is u = m (dt_out / dt_in) - (t_origin + t0)/dt_in:
+// for a thread's first sample one fused multiply-add in double from the
+// per-event offset computed on the host, then in 32.32 fixed point, each next
+// sample adding the ratio in integers (its rounding, 2^-33 of a sample, grows
+// by that much per sample).  The integer part picks the two input samples, the
+// fraction f is the interpolation weight, the lerp x0 + f (x1 - x0) is formed
+// in float (the inputs are float) and added to the double sum.  The lerp is
+// continuous in u, so the rounding of u moves the result by as little.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,18 +35,22 @@
 namespace {
 
 constexpr int CT = 1024;           // threads per block
-constexpr int SEG_MAX = 12288;     // output samples per segment (96 KiB of double accumulators)
+constexpr int SPT = 12;            // output samples per thread
+constexpr int SEG_MAX = CT * SPT;  // output samples per segment
 constexpr int STG = 4096;          // input samples staged per chunk (plus one before and one after)
 
 // per-segment work list: groups of events sharing a source
 struct Grp {
     int src;
-    int e0, e1;    // events [e0, e1) of the segment's event array
+    int e0, e1;    // events [e0, e1) of the plan's event array
     int pad;
 };
+// one event of a segment: amplitude, and per component the input offset
+// (t_origin + t0[c]) / dt_in and the output samples [mlo, mhi) it can touch
 struct Ev {
     double amp;
-    double t;      // origin time
+    double be[4];
+    int mlo[4], mhi[4];
 };
 
 // Host-side lists of one call: per segment the source groups, per group its
@@ -57,28 +65,41 @@ struct Plan {
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-// Build the work lists.  An event can touch output sample m only if
-// u(m) lies in (-1, nt_in); the sample range of that is widened by one sample
-// on each side (and over all four components' t0): the kernel decides each
-// sample exactly, a superset only costs a skipped iteration.
+// Build the work lists.  An event can touch output sample m of component c
+// only if u(m) lies in (-1, nt_in); that sample range is widened by one
+// sample on each side (the kernel decides each sample exactly, a superset
+// only costs a skipped iteration).
 void make_plan(Plan& p, int n_ev, const int32_t* src_idx, const double* amp, const double* t_origin,
                const double t0[4], int nt_in, double dt_in, int nt_out, double dt_out)
 {
     p.nseg = (nt_out + SEG_MAX - 1) / SEG_MAX;
     p.seg_len = (nt_out + p.nseg - 1) / p.nseg;
-    const double tmin0 = std::min(std::min(t0[0], t0[1]), std::min(t0[2], t0[3]));
-    const double tmax0 = std::max(std::max(t0[0], t0[1]), std::max(t0[2], t0[3]));
+    const double ratio = dt_out / dt_in;
+    std::vector<Ev> all(n_ev);
+    std::vector<int> first(n_ev), last(n_ev);
+    for (int e = 0; e < n_ev; ++e) {
+        Ev& E = all[e];
+        E.amp = amp[e];
+        double lo_all = 1e300, hi_all = -1e300;
+        for (int c = 0; c < 4; ++c) {
+            E.be[c] = (t_origin[e] + t0[c]) / dt_in;
+            // clamped in double first: the offset may be far outside the record
+            const double lo = std::max(0.0, std::floor((E.be[c] - 1.0) / ratio) - 1.0);
+            const double hi = std::min((double)nt_out, std::ceil(((double)nt_in + E.be[c]) / ratio) + 2.0);
+            E.mlo[c] = (int)std::min(lo, (double)nt_out);
+            E.mhi[c] = hi > lo ? (int)hi : E.mlo[c];
+            if (E.mhi[c] > E.mlo[c]) {
+                lo_all = std::min(lo_all, (double)E.mlo[c]);
+                hi_all = std::max(hi_all, (double)E.mhi[c]);
+            }
+        }
+        first[e] = hi_all > lo_all ? (int)lo_all : 1;
+        last[e] = hi_all > lo_all ? (int)hi_all - 1 : 0;
+    }
     // events of each segment in event order, then stably grouped by source
     std::vector<std::vector<int>> per(p.nseg);
-    for (int e = 0; e < n_ev; ++e) {
-        const double a = t_origin[e] + tmin0 - dt_in;
-        const double b = t_origin[e] + tmax0 + nt_in * dt_in;
-        const double fd = std::max(0.0, std::floor(a / dt_out) - 1.0);
-        const double ld = std::min((double)nt_out - 1.0, std::ceil(b / dt_out) + 1.0);
-        if (!(ld >= fd)) continue;
-        const long first = (long)fd, last = (long)ld;
-        for (long s = first / p.seg_len; s <= last / p.seg_len; ++s) per[s].push_back(e);
-    }
+    for (int e = 0; e < n_ev; ++e)
+        for (int s = first[e] / p.seg_len; first[e] <= last[e] && s <= last[e] / p.seg_len; ++s) per[s].push_back(e);
     p.seg_ptr.assign(p.nseg + 1, 0);
     p.grp.clear();
     p.ev.clear();
@@ -89,7 +110,7 @@ void make_plan(Plan& p, int n_ev, const int32_t* src_idx, const double* amp, con
             size_t j = i;
             while (j < L.size() && src_idx[L[j]] == src_idx[L[i]]) ++j;
             Grp g{src_idx[L[i]], (int)p.ev.size(), 0, 0};
-            for (size_t k = i; k < j; ++k) p.ev.push_back(Ev{amp[L[k]], t_origin[L[k]]});
+            for (size_t k = i; k < j; ++k) p.ev.push_back(all[L[k]]);
             g.e1 = (int)p.ev.size();
             p.grp.push_back(g);
             i = j;
@@ -102,69 +123,109 @@ void make_plan(Plan& p, int n_ev, const int32_t* src_idx, const double* amp, con
     p.bytes = p.off_ev + align256(std::max<size_t>(1, p.ev.size()) * sizeof(Ev));
 }
 
-__global__ __launch_bounds__(CT) void k_combine(const float* __restrict__ tr, int n_rec, int nt_in, double dt_in,
-                                                double ratio, double t00, double t01, double t02, double t03,
-                                                const char* __restrict__ plan, long off_grp, long off_ev,
-                                                int seg_len, int nt_out, float* __restrict__ out)
+// values of the staging buffer each thread loads
+constexpr int NPT = (STG + 2 + CT - 1) / CT;
+// samples whose positions, loads and sums go together (the loads of a half
+// are all issued before the first wait)
+constexpr int HALF = SPT / 2;
+
+__global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(8))) void k_combine(const float* __restrict__ tr, int n_rec, int nt_in, double ratio,
+                                                long long ratio_fx, const char* __restrict__ plan, long off_grp,
+                                                long off_ev, int seg_len, int nt_out, float* __restrict__ out)
 {
-#pragma clang fp contract(off)
-    __shared__ double acc[SEG_MAX];
     __shared__ float stg[STG + 2];
     const int seg = blockIdx.x;
     const int r = blockIdx.y;
     const int c = blockIdx.z;
     const int tid = threadIdx.x;
-    const double t0 = c == 0 ? t00 : c == 1 ? t01 : c == 2 ? t02 : t03;
     const int s0 = seg * seg_len;
     const int s1 = min(s0 + seg_len, nt_out);
+    const int m0 = s0 + tid * SPT;                 // this thread's samples [m0, m0 + SPT)
+    const bool active = m0 < s1;
     const int* __restrict__ seg_ptr = reinterpret_cast<const int*>(plan);
     const Grp* __restrict__ grp = reinterpret_cast<const Grp*>(plan + off_grp);
     const Ev* __restrict__ ev = reinterpret_cast<const Ev*>(plan + off_ev);
-    for (int i = tid; i < s1 - s0; i += CT) acc[i] = 0.0;
+    double acc[SPT];
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) acc[k] = 0.0;
     const int g0 = seg_ptr[seg], g1 = seg_ptr[seg + 1];
-    // chunks of the input axis: chunk q owns the samples whose left neighbour
-    // i0 = floor(u) lies in [a, b), a = q STG - 1, b = a + STG (the last chunk
-    // ends at nt_in), and stages x[a .. b] (zero outside the trace)
+    // Work items: (source group, chunk of the input axis).  Chunk q owns the
+    // samples whose left neighbour i0 = floor(u) lies in [a, b), a = q STG - 1,
+    // b = a + STG (the last chunk ends at nt_in), and stages x[a .. b] (zero
+    // outside the trace).  The next item's values are loaded into registers
+    // while the current one is computed.
     const int nchunk = (nt_in + 1 + STG - 1) / STG;
-    for (int g = g0; g < g1; ++g) {
+    const int nitems = (g1 - g0) * nchunk;
+    const double md = (double)m0;
+    float pre[NPT];
+    auto fetch = [&](int item) {
+        const int g = g0 + item / nchunk, q = item % nchunk;
+        const int a = q * STG - 1;
+        const int b = q == nchunk - 1 ? nt_in : a + STG;
+        const float* __restrict__ x = tr + (((long)grp[g].src * 4 + c) * n_rec + r) * nt_in;
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            const int i = tid + j * CT, k = a + i;
+            pre[j] = (i <= b - a && k >= 0 && k < nt_in) ? x[k] : 0.0f;
+        }
+    };
+    if (nitems > 0) fetch(0);
+    for (int item = 0; item < nitems; ++item) {
+        const int g = g0 + item / nchunk, q = item % nchunk;
+        const int a = q * STG - 1;
+        const int b = q == nchunk - 1 ? nt_in : a + STG;
+        __syncthreads();   // the previous item's readers are done
+#pragma unroll
+        for (int j = 0; j < NPT; ++j) {
+            const int i = tid + j * CT;
+            if (i < STG + 2) stg[i] = pre[j];
+        }
+        __syncthreads();
+        if (item + 1 < nitems) fetch(item + 1);
         const Grp G = grp[g];
-        const float* __restrict__ x = tr + (((long)G.src * 4 + c) * n_rec + r) * nt_in;
-        for (int q = 0; q < nchunk; ++q) {
-            const int a = q * STG - 1;
-            const int b = q == nchunk - 1 ? nt_in : a + STG;
-            __syncthreads();   // the previous chunk's readers are done
-            for (int i = tid; i <= b - a; i += CT) {
-                const int k = a + i;
-                stg[i] = (k >= 0 && k < nt_in) ? x[k] : 0.0f;
-            }
-            __syncthreads();
-            for (int e = G.e0; e < G.e1; ++e) {
-                const Ev E = ev[e];
-                const double be = (E.t + t0) / dt_in;
-                // samples with u in [a, b), widened by one on each side (clamped
-                // in double first: be may be far outside the record)
-                const double lo = fmax((double)s0, floor(((double)a + be) / ratio) - 1.0);
-                const double hi = fmin((double)s1, ceil(((double)b + be) / ratio) + 2.0);
-                if (!(hi > lo)) continue;
-                const long mlo = (long)lo, mhi = (long)hi;
-                // sample m belongs to thread m mod CT in every event
-                for (long m = mlo - (mlo % CT) + tid; m < mhi; m += CT) {
-                    if (m < mlo) continue;
-                    const double u = fma((double)m, ratio, -be);
-                    const double fl = floor(u);
-                    if (fl < (double)a || fl >= (double)b) continue;
-                    const int i0 = (int)fl;
-                    const double f = u - fl;
-                    const double x0 = (double)stg[i0 - a];
-                    const double x1 = (double)stg[i0 - a + 1];
-                    acc[m - s0] += E.amp * (x0 + f * (x1 - x0));
+        for (int e = G.e0; e < G.e1; ++e) {
+            const Ev& E = ev[e];
+            if (!active || E.mhi[c] <= m0 || E.mlo[c] >= m0 + SPT) continue;
+            const double amp = E.amp;
+            // position of this thread's first sample in 32.32 fixed point
+            // (from double; each later sample adds ratio exactly in integers,
+            // 2^-32 of a sample per step), integer part = left neighbour
+            const double u0 = fma(md, ratio, -E.be[c]);
+            const double fl0 = floor(u0);
+            long long u = ((long long)fl0 << 32) + (long long)((u0 - fl0) * 4294967296.0);
+#pragma unroll
+            for (int h = 0; h < SPT; h += HALF) {
+                // branch free: the positions of a half, then all its LDS reads,
+                // then the arithmetic (a sample outside this chunk's input
+                // range reads slot 0 and adds 0 times it)
+                int idx[HALF];
+                float fr[HALF];
+                double w[HALF];
+#pragma unroll
+                for (int k = 0; k < HALF; ++k) {
+                    const int i0 = (int)(u >> 32);
+                    const bool in = i0 >= a && i0 < b;
+                    idx[k] = in ? i0 - a : 0;
+                    fr[k] = (float)(unsigned)(u & 0xffffffffLL) * 2.3283064365386963e-10f;
+                    w[k] = in ? amp : 0.0;
+                    u += ratio_fx;
                 }
+                float x0[HALF], x1[HALF];
+#pragma unroll
+                for (int k = 0; k < HALF; ++k) {
+                    x0[k] = stg[idx[k]];
+                    x1[k] = stg[idx[k] + 1];
+                }
+#pragma unroll
+                for (int k = 0; k < HALF; ++k)
+                    acc[h + k] = fma(w[k], (double)fmaf(fr[k], x1[k] - x0[k], x0[k]), acc[h + k]);
             }
         }
     }
-    __syncthreads();
     float* __restrict__ o = out + ((long)c * n_rec + r) * nt_out;
-    for (int i = tid; i < s1 - s0; i += CT) o[s0 + i] = (float)acc[i];
+#pragma unroll
+    for (int k = 0; k < SPT; ++k)
+        if (m0 + k < s1) o[m0 + k] = (float)acc[k];
 }
 
 thread_local std::string g_cerr;
@@ -209,9 +270,10 @@ int launch(const Plan& p, char* dplan, const float* tr, int n_rec, int nt_in, do
         ok = hipMemcpyAsync(dplan + p.off_ev, p.ev.data(), p.ev.size() * sizeof(Ev), hipMemcpyHostToDevice, st) ==
              hipSuccess;
     if (ok) {
-        hipLaunchKernelGGL(k_combine, dim3(p.nseg, n_rec, 4), dim3(CT), 0, st, tr, n_rec, nt_in, dt_in,
-                           dt_out / dt_in, t0[0], t0[1], t0[2], t0[3], dplan, (long)p.off_grp, (long)p.off_ev,
-                           p.seg_len, nt_out, out);
+        const double ratio = dt_out / dt_in;
+        const long long ratio_fx = (long long)std::llround(ratio * 4294967296.0);
+        hipLaunchKernelGGL(k_combine, dim3(p.nseg, n_rec, 4), dim3(CT), 0, st, tr, n_rec, nt_in, ratio, ratio_fx,
+                           dplan, (long)p.off_grp, (long)p.off_ev, p.seg_len, nt_out, out);
         ok = hipGetLastError() == hipSuccess;
     }
     const hipError_t se = hipStreamSynchronize(st);

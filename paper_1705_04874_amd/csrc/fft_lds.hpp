@@ -173,16 +173,17 @@ __device__ __forceinline__ constexpr int lidx(int i)
 __host__ __device__ constexpr int padded_len(int n) { return n + (n >> 4) + 1; }
 
 // ---------------------------------------------------------------------------
-// radix plan: as many 16s as possible, then 8, 4, 2, 3, 5
-__host__ __device__ constexpr int plan_radix(int n, int p)
+// radix plan: as many of the largest radix up to MR (16 or 8) as possible, then
+// 8, 4, 2, 3, 5
+__host__ __device__ constexpr int plan_radix(int n, int p, int mr = 16)
 {
     int idx = 0;
-    while (n % 16 == 0 && n > 1) {
+    while (mr >= 16 && n % 16 == 0 && n > 1) {
         if (idx == p) return 16;
         n /= 16;
         ++idx;
     }
-    while (n % 8 == 0 && n > 1) {
+    while (mr >= 8 && n % 8 == 0 && n > 1) {
         if (idx == p) return 8;
         n /= 8;
         ++idx;
@@ -210,17 +211,17 @@ __host__ __device__ constexpr int plan_radix(int n, int p)
     return 0;
 }
 
-__host__ __device__ constexpr int plan_passes(int n)
+__host__ __device__ constexpr int plan_passes(int n, int mr = 16)
 {
     int p = 0;
-    while (plan_radix(n, p)) ++p;
+    while (plan_radix(n, p, mr)) ++p;
     return p;
 }
 
-__host__ __device__ constexpr int plan_ns(int n, int p)
+__host__ __device__ constexpr int plan_ns(int n, int p, int mr = 16)
 {
     int ns = 1;
-    for (int i = 0; i < p; ++i) ns *= plan_radix(n, i);
+    for (int i = 0; i < p; ++i) ns *= plan_radix(n, i, mr);
     return ns;
 }
 
@@ -228,11 +229,14 @@ __host__ __device__ constexpr bool plan_ok(int n) { return n >= 2 && plan_ns(n, 
 
 // the same radices in reverse order (used by inverse transforms that start
 // from the register-resident output of a forward transform)
-__host__ __device__ constexpr int plan_radix_rev(int n, int p) { return plan_radix(n, plan_passes(n) - 1 - p); }
-__host__ __device__ constexpr int plan_ns_rev(int n, int p)
+__host__ __device__ constexpr int plan_radix_rev(int n, int p, int mr = 16)
+{
+    return plan_radix(n, plan_passes(n, mr) - 1 - p, mr);
+}
+__host__ __device__ constexpr int plan_ns_rev(int n, int p, int mr = 16)
 {
     int ns = 1;
-    for (int i = 0; i < p; ++i) ns *= plan_radix_rev(n, i);
+    for (int i = 0; i < p; ++i) ns *= plan_radix_rev(n, i, mr);
     return ns;
 }
 
@@ -388,12 +392,12 @@ __device__ __forceinline__ bool reg_coords(int q, int r, int& pen, int& idx)
 // One pass of a plan (REV selects the reversed radix order) with the inputs
 // in registers (FROM_R) and/or the outputs left in registers (TO_R).
 template <int N, int P, bool REV, int NPEN, int NT, int DIR, int PS, int IS, bool COLMAJOR, bool FROM_G, bool FROM_R,
-          bool TO_G, bool TO_R, class Ld, class St, class RIn, class ROut>
+          bool TO_G, bool TO_R, class Ld, class St, class RIn, class ROut, int MR = 16>
 __device__ __forceinline__ void fft_pass_r(float2* s, const float2* tw, const Ld& ld, const St& st, RIn& rin,
                                            ROut& rout)
 {
-    constexpr int R = REV ? plan_radix_rev(N, P) : plan_radix(N, P);
-    constexpr int NS = REV ? plan_ns_rev(N, P) : plan_ns(N, P);
+    constexpr int R = REV ? plan_radix_rev(N, P, MR) : plan_radix(N, P, MR);
+    constexpr int NS = REV ? plan_ns_rev(N, P, MR) : plan_ns(N, P, MR);
     constexpr int M = N / R;
     constexpr int NB = NPEN * M;
     constexpr int Q = (NB + NT - 1) / NT;
@@ -445,50 +449,50 @@ __device__ __forceinline__ void fft_pass_r(float2* s, const float2* tw, const Ld
 }
 
 template <int N, int P, bool REV, int NPEN, int NT, int DIR, int PS, int IS, bool COLMAJOR, bool LDG, bool LDR,
-          bool STG, bool STR, class Ld, class St, class RIn, class ROut>
+          bool STG, bool STR, class Ld, class St, class RIn, class ROut, int MR = 16>
 struct FftPassesR {
     static __device__ __forceinline__ void run(float2* s, const float2* tw, const Ld& ld, const St& st, RIn& rin,
                                                ROut& rout)
     {
-        constexpr int NP = plan_passes(N);
+        constexpr int NP = plan_passes(N, MR);
         if constexpr (P < NP) {
             constexpr bool first = P == 0, last = P == NP - 1;
             fft_pass_r<N, P, REV, NPEN, NT, DIR, PS, IS, COLMAJOR, LDG && first, LDR && first, STG && last,
-                       STR && last, Ld, St, RIn, ROut>(s, tw, ld, st, rin, rout);
-            FftPassesR<N, P + 1, REV, NPEN, NT, DIR, PS, IS, COLMAJOR, LDG, LDR, STG, STR, Ld, St, RIn, ROut>::run(
-                s, tw, ld, st, rin, rout);
+                       STR && last, Ld, St, RIn, ROut, MR>(s, tw, ld, st, rin, rout);
+            FftPassesR<N, P + 1, REV, NPEN, NT, DIR, PS, IS, COLMAJOR, LDG, LDR, STG, STR, Ld, St, RIn, ROut,
+                       MR>::run(s, tw, ld, st, rin, rout);
         }
     }
 };
 
 // register array shapes of the first / last pass
-template <int N, int NPEN, int NT>
+template <int N, int NPEN, int NT, int MR = 16>
 struct RegShape {
-    static constexpr int RL = plan_radix(N, plan_passes(N) - 1);   // forward last = reversed first
+    static constexpr int RL = plan_radix(N, plan_passes(N, MR) - 1, MR);   // forward last = reversed first
     static constexpr int QL = (NPEN * (N / RL) + NT - 1) / NT;
 };
 
 // Forward-plan transform from ld(pencil, i) leaving the outputs in registers
 // (no trailing barrier: the caller synchronises before it writes s again).
-template <int N, int NPEN, int NT, int DIR, int PS, int IS, bool COLMAJOR, class Ld, class ROut>
+template <int N, int NPEN, int NT, int DIR, int PS, int IS, bool COLMAJOR, class Ld, class ROut, int MR = 16>
 __device__ __forceinline__ void fft_g2r(float2* s, const float2* tw, const Ld& ld, ROut& rout)
 {
     static_assert(plan_ok(N), "length must factor into 2, 3 and 5");
     float2 dummy[1][1];
     FftPassesR<N, 0, false, NPEN, NT, DIR, PS, IS, COLMAJOR, true, false, false, true, Ld, NoSt, float2[1][1],
-               ROut>::run(s, tw, ld, NoSt{}, dummy, rout);
+               ROut, MR>::run(s, tw, ld, NoSt{}, dummy, rout);
 }
 
 // Reversed-plan transform from registers to st(pencil, i, v) (no trailing
 // barrier; the caller synchronises before the first pass writes s when s was
 // read just before).
-template <int N, int NPEN, int NT, int DIR, int PS, int IS, bool COLMAJOR, class RIn, class St>
+template <int N, int NPEN, int NT, int DIR, int PS, int IS, bool COLMAJOR, class RIn, class St, int MR = 16>
 __device__ __forceinline__ void fft_r2g(float2* s, const float2* tw, RIn& rin, const St& st)
 {
     static_assert(plan_ok(N), "length must factor into 2, 3 and 5");
     float2 dummy[1][1];
     FftPassesR<N, 0, true, NPEN, NT, DIR, PS, IS, COLMAJOR, false, true, true, false, NoLd, St, RIn,
-               float2[1][1]>::run(s, tw, NoLd{}, st, rin, dummy);
+               float2[1][1], MR>::run(s, tw, NoLd{}, st, rin, dummy);
 }
 
 }  // namespace pstd

@@ -63,11 +63,15 @@ struct YFns {
     int tile;
 };
 struct ZFns {
-    void (*op)(dim3, hipStream_t, Geo, const float2*, float2*, int, const ZDesc*, int);
+    void (*op)(dim3, hipStream_t, Geo, const float2*, float2*, int, const ZDesc*, int, int);
     int tile;
+    int nt;     // threads per block
 };
-constexpr int MAX_VARIANTS = 4;
-constexpr int TILE_CANDIDATES[MAX_VARIANTS] = {8, 16, 32, 64};
+constexpr int MAX_VARIANTS = 8;
+constexpr int N_TILES = 4;
+constexpr int TILE_CANDIDATES[N_TILES] = {8, 16, 32, 64};
+// input fields per block of the z kernels: one, or every input of the phase
+constexpr int ZF_VALUES[2] = {1, 6};
 
 // threads per block of the update kernels of length N: 128, 256 and 512,
 // none above the cells of a block
@@ -138,9 +142,15 @@ struct LaunchYZ {
     {
         hipLaunchKernelGGL((k_y<N, NT, +1, TX>), gr, dim3(NT), 0, st, g, tw, s, f0, nf);
     }
-    static void z(dim3 gr, hipStream_t st, Geo g, const float2* tw, float2* s, int in0, const ZDesc* zd, int ph)
+    static void z(dim3 gr, hipStream_t st, Geo g, const float2* tw, float2* s, int in0, const ZDesc* zd, int ph,
+                  int fpb)
     {
-        hipLaunchKernelGGL((k_z<N, NT, TX>), gr, dim3(NT), 0, st, g, tw, s, in0, zd, ph);
+        hipLaunchKernelGGL((k_z<N, NT, TX>), gr, dim3(NT), 0, st, g, tw, s, in0, zd, ph, fpb);
+    }
+    static void z512(dim3 gr, hipStream_t st, Geo g, const float2* tw, float2* s, int in0, const ZDesc* zd, int ph,
+                     int fpb)
+    {
+        hipLaunchKernelGGL((k_z<N, 512, TX, z_maxr(N, TX, 512)>), gr, dim3(512), 0, st, g, tw, s, in0, zd, ph, fpb);
     }
 };
 
@@ -148,10 +158,11 @@ struct LaunchYZ {
 template <int N, int I = 0>
 void yz_variants(YFns* y, int& ny, ZFns* z, int& nz)
 {
-    if constexpr (I < MAX_VARIANTS) {
+    if constexpr (I < N_TILES) {
         constexpr int TX = TILE_CANDIDATES[I];
         if constexpr (y_tile_built(N, TX)) y[ny++] = YFns{LaunchYZ<N, TX>::yf, LaunchYZ<N, TX>::yi, TX};
-        if constexpr (z_tile_built(N, TX)) z[nz++] = ZFns{LaunchYZ<N, TX>::z, TX};
+        if constexpr (z_tile_built(N, TX)) z[nz++] = ZFns{LaunchYZ<N, TX>::z, TX, NT};
+        if constexpr (z512_ok(N, TX)) z[nz++] = ZFns{LaunchYZ<N, TX>::z512, TX, 512};
         yz_variants<N, I + 1>(y, ny, z, nz);
     }
 }
@@ -311,27 +322,54 @@ struct pstd3d_ctx {
     VelVar velv[3]{};
     StrVar strv[3]{};
     YFns yv[MAX_VARIANTS]{};   // y variants of length ny
-    ZFns zv[MAX_VARIANTS]{};   // z variants of length nz
-    int nvar[PSTD_TUNE_COUNT] = {0, 0, 0, 0};
-    int force[PSTD_TUNE_COUNT] = {0, 0, 0, 0};
-    int sel[PSTD_TUNE_COUNT] = {0, 0, 0, 0};
+    ZFns zv[MAX_VARIANTS]{};   // z variants of length nz: every built (tile, threads)
+    int nzv = 0;
+    int ztile[MAX_VARIANTS]{}; // the distinct z tiles (values of PSTD_TUNE_Z)
+    int znt[MAX_VARIANTS]{};   // the distinct z thread counts (values of PSTD_TUNE_ZT)
+    int nvar[PSTD_TUNE_COUNT] = {};
+    int force[PSTD_TUNE_COUNT] = {};
+    int sel[PSTD_TUNE_COUNT] = {};
     bool tuned = false;
     bool visc = false;         // Kelvin-Voigt viscosity set (33 state fields)
     int smooth = 0;            // source smoothing for the next set_sources (0 off, 1 Blackman)
     float tune_us[PSTD_TUNE_COUNT][MAX_VARIANTS] = {};   // measured us per launch of each variant
     YFns yf{};                 // the chosen variants
     ZFns zf{};
+    int zfpb = 1;              // input fields per z block
     VelVar vel{};
     StrVar str{};
 
     int knob_value(int k, int i) const
     {
-        return k == PSTD_TUNE_Y ? yv[i].tile : k == PSTD_TUNE_Z ? zv[i].tile : k == PSTD_TUNE_VEL ? velv[i].nt : strv[i].nt;
+        switch (k) {
+        case PSTD_TUNE_Y: return yv[i].tile;
+        case PSTD_TUNE_Z: return ztile[i];
+        case PSTD_TUNE_VEL: return velv[i].nt;
+        case PSTD_TUNE_STR: return strv[i].nt;
+        case PSTD_TUNE_ZT: return znt[i];
+        default: return ZF_VALUES[i];
+        }
+    }
+    // the built z variant of (tile, threads), or null
+    const ZFns* zvar(int tile, int nt) const
+    {
+        for (int i = 0; i < nzv; ++i)
+            if (zv[i].tile == tile && zv[i].nt == nt) return &zv[i];
+        return nullptr;
     }
     void apply()
     {
         yf = yv[sel[PSTD_TUNE_Y]];
-        zf = zv[sel[PSTD_TUNE_Z]];
+        const int tile = ztile[sel[PSTD_TUNE_Z]];
+        const ZFns* z = zvar(tile, znt[sel[PSTD_TUNE_ZT]]);
+        if (!z) {
+            // every tile is built with NT threads: the thread knob follows
+            z = zvar(tile, NT);
+            for (int i = 0; i < nvar[PSTD_TUNE_ZT]; ++i)
+                if (znt[i] == NT) sel[PSTD_TUNE_ZT] = i;
+        }
+        zf = *z;
+        zfpb = ZF_VALUES[sel[PSTD_TUNE_ZF]];
         vel = velv[sel[PSTD_TUNE_VEL]];
         str = strv[sel[PSTD_TUNE_STR]];
     }
@@ -683,13 +721,14 @@ void enqueue_step(pstd3d_ctx* c, hipStream_t st, float* traces, int n0, int ldt,
     const dim3 gx = update_grid(c);
     const int tyn = (g.nxm + c->yf.tile - 1) / c->yf.tile + g.has_nyq;
     const int tzn = (g.nxm + c->zf.tile - 1) / c->zf.tile + g.has_nyq;
+    const int fpb = c->zfpb;
     long e;
     // V phase
     e = c->ev_begin(PSTD_K_YFWD_S, st);
     c->yf.fwd(dim3(tyn, g.nz, S * 6), st, g, c->twy, c->spec, 0, 6);
     c->ev_end(e, st);
     e = c->ev_begin(PSTD_K_ZOP_V, st);
-    c->zf.op(dim3(tzn, g.ny, S * 6), st, g, c->twz, c->spec, 0, c->zdesc, 0);
+    c->zf.op(dim3(tzn, g.ny, S * ((6 + fpb - 1) / fpb)), st, g, c->twz, c->spec, 0, c->zdesc, 0, fpb);
     c->ev_end(e, st);
     e = c->ev_begin(PSTD_K_YINV_V, st);
     c->yf.inv(dim3(tyn, g.nz, S * 9), st, g, c->twy, c->spec, 9, 9);
@@ -702,7 +741,7 @@ void enqueue_step(pstd3d_ctx* c, hipStream_t st, float* traces, int n0, int ldt,
     c->yf.fwd(dim3(tyn, g.nz, S * 3), st, g, c->twy, c->spec, 6, 3);
     c->ev_end(e, st);
     e = c->ev_begin(PSTD_K_ZOP_S, st);
-    c->zf.op(dim3(tzn, g.ny, S * 3), st, g, c->twz, c->spec, 6, c->zdesc, 1);
+    c->zf.op(dim3(tzn, g.ny, S * ((3 + fpb - 1) / fpb)), st, g, c->twz, c->spec, 6, c->zdesc, 1, fpb);
     c->ev_end(e, st);
     e = c->ev_begin(PSTD_K_YINV_S, st);
     c->yf.inv(dim3(tyn, g.nz, S * 9), st, g, c->twy, c->spec, 9, 9);
@@ -725,7 +764,7 @@ bool len_ok(int n)
 // built, else the first
 int default_variant(const pstd3d_ctx* c, int k)
 {
-    const int want = (k == PSTD_TUNE_Y || k == PSTD_TUNE_Z) ? 16 : 256;
+    const int want = (k == PSTD_TUNE_Y || k == PSTD_TUNE_Z) ? 16 : k == PSTD_TUNE_ZF ? 1 : 256;
     for (int i = 0; i < c->nvar[k]; ++i)
         if (c->knob_value(k, i) == want) return i;
     return 0;
@@ -771,7 +810,10 @@ int autotune(pstd3d_ctx* c)
         return e;
     };
     const dim3 gx = update_grid(c);
-    for (int k = 0; k < PSTD_TUNE_COUNT; ++k) {
+    const int order[PSTD_TUNE_COUNT] = {PSTD_TUNE_Y, PSTD_TUNE_Z, PSTD_TUNE_ZT, PSTD_TUNE_ZF, PSTD_TUNE_VEL,
+                                        PSTD_TUNE_STR};
+    for (int kk = 0; kk < PSTD_TUNE_COUNT; ++kk) {
+        const int k = order[kk];
         int best = -1;
         for (int i = 0; i < c->nvar[k]; ++i) {
             c->tune_us[k][i] = 0.f;
@@ -781,10 +823,18 @@ int autotune(pstd3d_ctx* c)
                 const YFns v = c->yv[i];
                 const int tyn = (g.nxm + v.tile - 1) / v.tile + g.has_nyq;
                 e = timed([&] { v.inv(dim3(tyn, g.nz, S * 9), nullptr, g, c->twy, c->spec, 9, 9); }, &c->tune_us[k][i]);
-            } else if (k == PSTD_TUNE_Z) {
-                const ZFns v = c->zv[i];
+            } else if (k == PSTD_TUNE_Z || k == PSTD_TUNE_ZT || k == PSTD_TUNE_ZF) {
+                // the velocity phase's z operator; the other two z knobs at
+                // their current choice (the tile knob is tuned first)
+                const int tile = k == PSTD_TUNE_Z ? c->ztile[i] : c->ztile[c->sel[PSTD_TUNE_Z]];
+                const int nt = k == PSTD_TUNE_ZT ? c->znt[i] : c->znt[c->sel[PSTD_TUNE_ZT]];
+                const int fpb = k == PSTD_TUNE_ZF ? ZF_VALUES[i] : ZF_VALUES[c->sel[PSTD_TUNE_ZF]];
+                const ZFns* zp = c->zvar(tile, nt);
+                if (!zp && k == PSTD_TUNE_ZT) continue;          // no such variant at this tile
+                const ZFns v = zp ? *zp : *c->zvar(tile, NT);
                 const int tzn = (g.nxm + v.tile - 1) / v.tile + g.has_nyq;
-                e = timed([&] { v.op(dim3(tzn, g.ny, S * 6), nullptr, g, c->twz, c->spec, 0, c->zdesc, 0); },
+                e = timed([&] { v.op(dim3(tzn, g.ny, S * ((6 + fpb - 1) / fpb)), nullptr, g, c->twz, c->spec, 0,
+                                     c->zdesc, 0, fpb); },
                           &c->tune_us[k][i]);
             } else if (k == PSTD_TUNE_VEL) {
                 const VelVar v = c->velv[i];
@@ -889,7 +939,15 @@ int pstd3d_create(const pstd3d_model* m, const double d[3], double dt, const pst
     c->n_rec = m->n_rec;
     (void)hipGetDevice(&c->device);
     c->nvar[PSTD_TUNE_Y] = y_variants(ny, c->yv);
-    c->nvar[PSTD_TUNE_Z] = z_variants(nz, c->zv);
+    c->nzv = z_variants(nz, c->zv);
+    for (int i = 0; i < c->nzv; ++i) {
+        bool seen_t = false, seen_n = false;
+        for (int j = 0; j < c->nvar[PSTD_TUNE_Z]; ++j) seen_t = seen_t || c->ztile[j] == c->zv[i].tile;
+        for (int j = 0; j < c->nvar[PSTD_TUNE_ZT]; ++j) seen_n = seen_n || c->znt[j] == c->zv[i].nt;
+        if (!seen_t) c->ztile[c->nvar[PSTD_TUNE_Z]++] = c->zv[i].tile;
+        if (!seen_n) c->znt[c->nvar[PSTD_TUNE_ZT]++] = c->zv[i].nt;
+    }
+    c->nvar[PSTD_TUNE_ZF] = 2;
     x_fns(nx, &c->xf, c->velv, c->strv, &c->nvar[PSTD_TUNE_VEL]);
     c->nvar[PSTD_TUNE_STR] = c->nvar[PSTD_TUNE_VEL];
     for (int k = 0; k < PSTD_TUNE_COUNT; ++k) c->sel[k] = default_variant(c, k);
@@ -1286,7 +1344,8 @@ int pstd3d_derivs(pstd3d_ctx* c, int phase, const float* in_dev, float* out_dev,
     // shot 0 scratch: spectra in0.. and the derivative block
     c->xf.xfwd(gx, st, g, c->twx, in_dev, 0, c->spec + in0 * g.nspec, 0, sd);
     c->yf.fwd(dim3(tyn, g.nz, sd.nf), st, g, c->twy, c->spec, in0, sd.nf);
-    c->zf.op(dim3(tzn, g.ny, sd.nf), st, g, c->twz, c->spec, in0, c->zdesc, phase);
+    c->zf.op(dim3(tzn, g.ny, (sd.nf + c->zfpb - 1) / c->zfpb), st, g, c->twz, c->spec, in0, c->zdesc, phase,
+             c->zfpb);
     c->yf.inv(dim3(tyn, g.nz, 9), st, g, c->twy, c->spec, 9, 9);
     c->xf.xinv(gx, st, g, c->twx, c->spec + 9 * g.nspec, out_dev);
     // the stress spectra are part of the state between steps: rebuild them
@@ -1381,6 +1440,8 @@ int pstd3d_set_tuning(pstd3d_ctx* c, const int value[PSTD_TUNE_COUNT])
             if (c->knob_value(k, i) == value[k]) idx[k] = i;
         if (idx[k] < 0) return fail(PSTD_EUNSUPPORTED, "tuning value not built for this grid length");
     }
+    if (idx[PSTD_TUNE_Z] >= 0 && idx[PSTD_TUNE_ZT] >= 0 && !c->zvar(value[PSTD_TUNE_Z], value[PSTD_TUNE_ZT]))
+        return fail(PSTD_EUNSUPPORTED, "z threads per block not built for that z tile");
     for (int k = 0; k < PSTD_TUNE_COUNT; ++k) {
         c->force[k] = value[k];
         if (idx[k] >= 0) c->sel[k] = idx[k];

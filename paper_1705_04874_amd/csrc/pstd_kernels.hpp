@@ -658,26 +658,34 @@ __global__ __launch_bounds__(NT) void k_y(Geo g, const float2* __restrict__ twy,
 }
 
 // z FFT, multiply by the staggered derivative symbols and kappa, inverse z
-// FFT.  grid: (main tiles + Nyquist tile, ny, shots * nin).  Main tile bx
+// FFT.  grid: (main tiles + Nyquist tile, ny, shots * groups).  Main tile bx
 // covers columns [TX bx, +TX) of row ky = by; the Nyquist tile covers the
-// Nyquist pencils of rows [TX by, +TX).  Reads spectrum `in0 + input`, writes
-// the derivative spectra (9 + output index) of the shot.  The forward
-// spectrum stays in registers; each output is multiplied there and inverted
-// with the reversed radix plan.
-template <int NZ, int NT, int TX>
+// Nyquist pencils of rows [TX by, +TX).  A block takes the input spectra
+// [fpb g, fpb g + fpb) of its shot (g = blockIdx.z % groups), so that with
+// fpb >= the phase's inputs one block applies its tile's kappa and symbols
+// (loaded once) to every input field in turn.  For each input it reads
+// spectrum `in0 + input`, writes the derivative spectra (9 + output index):
+// the forward spectrum stays in registers, each output is multiplied there
+// and inverted with the reversed radix plan.  MR caps the radix of the plan
+// (16, or 8 for the 512-thread variants, whose threads then all take a
+// butterfly of the first pass).
+template <int NZ, int NT, int TX, int MR = 16>
 __global__ __launch_bounds__(NT) void k_z(Geo g, const float2* __restrict__ twz, float2* __restrict__ spec,
-                                          int in0, const ZDesc* __restrict__ zd, int phase)
+                                          int in0, const ZDesc* __restrict__ zd, int phase, int fpb)
 {
     const PhaseDesc& ph = zd->ph[phase];
     const Ops& ops = zd->ops;
     constexpr int IS = TX + 1;
-    using RS = RegShape<NZ, TX, NT>;
+    using RS = RegShape<NZ, TX, NT, MR>;
     constexpr int RL = RS::RL, QL = RS::QL;
+    // LDS: the tile, the twiddles, and the D+ symbols along z and of the tile's
+    // columns (D- is D+ with the real part negated: i k e^{-i k h/2} =
+    // (k sin, k cos) against (-k sin, k cos)); kept under 40 KB at length 256
+    // so that four blocks share a CU
     __shared__ float2 s[NZ * IS];
     __shared__ float2 tw[NZ];
-    __shared__ float2 symz[2][NZ];
-    __shared__ float2 symc[2][2][TX];
-    __shared__ float kz2[NZ];
+    __shared__ float2 symz[NZ];
+    __shared__ float2 symc[2][TX];
     __shared__ float kxy2[TX];
     // the forward spectrum is reused by every output of the input field; kept
     // in registers it stays live through the inverse transforms (about a
@@ -686,7 +694,9 @@ __global__ __launch_bounds__(NT) void k_z(Geo g, const float2* __restrict__ twz,
     constexpr bool STASH = QL * RL * NT * (int)sizeof(float2) <= 16384;
     __shared__ float2 xs[STASH ? QL * RL * NT : 1];
     const int tmain = (g.nxm + TX - 1) / TX;
-    const int shot = blockIdx.z / ph.nin, fi = blockIdx.z % ph.nin;
+    const int groups = (ph.nin + fpb - 1) / fpb;
+    const int shot = blockIdx.z / groups, fg = blockIdx.z % groups;
+    const int f0 = fg * fpb, f1 = min(ph.nin, f0 + fpb);
     long off, zs;
     const float* kap;
     int ncol, kx0, kxc, ky0, kyc;
@@ -713,23 +723,21 @@ __global__ __launch_bounds__(NT) void k_z(Geo g, const float2* __restrict__ twz,
     const bool kpoly = ops.kpoly[phase] != 0;
     for (int i = threadIdx.x; i < NZ; i += NT) {
         tw[i] = twz[i];
-        symz[0][i] = gld(ops.sym[2][0] + i);
-        symz[1][i] = gld(ops.sym[2][1] + i);
-        if (kpoly) kz2[i] = gld(ops.k2[2] + i);
+        symz[i] = gld(ops.sym[2][1] + i);
     }
     if (kpoly)
         for (int i = threadIdx.x; i < TX; i += NT) {
             const int c = min(i, ncol - 1);
             kxy2[i] = gld(ops.k2[0] + kx0 + kxc * c) + gld(ops.k2[1] + ky0 + kyc * c);
         }
-    // x and y symbols of this tile's columns (main tiles: kx0 + c and ky0;
+    // x and y D+ symbols of this tile's columns (main tiles: kx0 + c and ky0;
     // Nyquist tile: nx/2 and ky0 + c), so that the multiply loop reads LDS only
-    for (int i = threadIdx.x; i < 4 * TX; i += NT) {
-        const int ax = i / (2 * TX), pl = (i / TX) & 1, c = min(i % TX, ncol - 1);
-        symc[ax][pl][i % TX] = gld(ops.sym[ax][pl] + (ax == 0 ? kx0 + kxc * c : ky0 + kyc * c));
+    for (int i = threadIdx.x; i < 2 * TX; i += NT) {
+        const int ax = i / TX, c = min(i % TX, ncol - 1);
+        symc[ax][i % TX] = gld(ops.sym[ax][1] + (ax == 0 ? kx0 + kxc * c : ky0 + kyc * c));
     }
     __syncthreads();
-    // kappa of the elements this thread multiplies (issued before the forward FFT)
+    // kappa of the elements this thread multiplies, once for all the block's inputs
     float kr[QL][RL];
 #pragma unroll
     for (int q = 0; q < QL; ++q)
@@ -739,7 +747,7 @@ __global__ __launch_bounds__(NT) void k_z(Geo g, const float2* __restrict__ twz,
             const bool ok = reg_coords<NZ, RL, TX, NT, true>(q, r, c, z);
             float kv;
             if (kpoly) {
-                const float sv = kxy2[min(c, TX - 1)] + kz2[ok ? z : 0];
+                const float sv = kxy2[min(c, TX - 1)] + gld(ops.k2[2] + (ok ? z : 0));
                 kv = ops.kc[7];
 #pragma unroll
                 for (int t = 6; t >= 0; --t) kv = fmaf(kv, sv, ops.kc[t]);
@@ -751,36 +759,47 @@ __global__ __launch_bounds__(NT) void k_z(Geo g, const float2* __restrict__ twz,
             kr[q][r] = (ok && c < ncol) ? kv : 0.f;
         }
     float2* __restrict__ sb = spec + (long)shot * g.sstride;
-    const Tile in{sb + (long)(in0 + fi) * g.nspec + off, 1, zs, ncol};
-    float2 X[QL][RL];
-    fft_g2r<NZ, TX, NT, -1, 1, IS, true>(s, tw, in, X);
-    if constexpr (STASH) {
+    for (int fi = f0; fi < f1; ++fi) {
+        if (fi > f0) __syncthreads();   // s was read by the previous input's last pass
+        const Tile in{sb + (long)(in0 + fi) * g.nspec + off, 1, zs, ncol};
+        float2 X[QL][RL];
+        fft_g2r<NZ, TX, NT, -1, 1, IS, true, Tile, float2[QL][RL], MR>(s, tw, in, X);
+        if constexpr (STASH) {
 #pragma unroll
-        for (int q = 0; q < QL; ++q)
+            for (int q = 0; q < QL; ++q)
 #pragma unroll
-            for (int r = 0; r < RL; ++r) xs[(q * RL + r) * NT + threadIdx.x] = X[q][r];
-    }
-    for (int o = 0; o < ph.nout[fi]; ++o) {
-        const int axis = ph.axis[fi][o], plus = ph.plus[fi][o];
-        // symbol table of this output: along z indexed by z, along x or y by column
-        const float2* tab = axis == 2 ? symz[plus] : symc[axis][plus];
-        const bool byz = axis == 2;
-        float2 Y[QL][RL];
+                for (int r = 0; r < RL; ++r) xs[(q * RL + r) * NT + threadIdx.x] = X[q][r];
+        }
+        for (int o = 0; o < ph.nout[fi]; ++o) {
+            const int axis = ph.axis[fi][o], plus = ph.plus[fi][o];
+            // symbol table of this output: along z indexed by z, along x or y by column
+            const float2* tab = axis == 2 ? symz : symc[axis];
+            const bool byz = axis == 2;
+            const float sgn = plus ? 1.f : -1.f;
+            float2 Y[QL][RL];
 #pragma unroll
-        for (int q = 0; q < QL; ++q)
+            for (int q = 0; q < QL; ++q)
 #pragma unroll
-            for (int r = 0; r < RL; ++r) {
-                int c, z;
-                reg_coords<NZ, RL, TX, NT, true>(q, r, c, z);
-                const float2 sv = tab[byz ? z : c];
-                const float2 xv = STASH ? xs[(q * RL + r) * NT + threadIdx.x] : X[q][r];
-                Y[q][r] = c_scale(c_mul(sv, xv), kr[q][r]);
-            }
-        __syncthreads();   // s was read by the previous pass
-        const Tile out{sb + (long)(9 + ph.oidx[fi][o]) * g.nspec + off, 1, zs, ncol};
-        fft_r2g<NZ, TX, NT, +1, 1, IS, true>(s, tw, Y, out);
+                for (int r = 0; r < RL; ++r) {
+                    int c, z;
+                    reg_coords<NZ, RL, TX, NT, true>(q, r, c, z);
+                    const float2 s1 = tab[byz ? z : c];
+                    const float2 sv = make_float2(sgn * s1.x, s1.y);
+                    const float2 xv = STASH ? xs[(q * RL + r) * NT + threadIdx.x] : X[q][r];
+                    Y[q][r] = c_scale(c_mul(sv, xv), kr[q][r]);
+                }
+            __syncthreads();   // s was read by the previous pass
+            const Tile out{sb + (long)(9 + ph.oidx[fi][o]) * g.nspec + off, 1, zs, ncol};
+            fft_r2g<NZ, TX, NT, +1, 1, IS, true, float2[QL][RL], Tile, MR>(s, tw, Y, out);
+        }
     }
 }
+
+// The 512-thread z variants: the largest radix (16 or 8) whose first pass
+// still gives every thread a butterfly
+constexpr int z_maxr(int n, int tx, int nt) { return tx * (n / 16) >= nt ? 16 : 8; }
+// at least four values per thread and a radix-8 (or 16) first pass
+constexpr bool z512_ok(int n, int tx) { return z_tile_ok(n, tx) && n * tx >= 4 * 512 && n % 8 == 0 && tx * (n / 8) >= 512; }
 
 // non-finite check on sampled trace values: flag = 1 if any is not finite
 __global__ void k_check_finite(const float* __restrict__ tr, long n, int* __restrict__ flag)

@@ -253,8 +253,18 @@ def test_every_tuning_value_gives_the_same_traces(B):
     combos = [dict(y_tile=y, z_tile=z, vel_threads=256, str_threads=256)
               for y in t["y_tile_candidates"] for z in t["z_tile_candidates"]]
     combos += [dict(y_tile=16, z_tile=16, vel_threads=v, str_threads=v) for v in t["vel_threads_candidates"]]
+    # the z kernels' thread counts with every tile they are built for, and both field groupings
+    for z in t["z_tile_candidates"]:
+        for zt in t["z_threads_candidates"]:
+            for zf in t["z_fields_candidates"]:
+                combos.append(dict(y_tile=16, z_tile=z, vel_threads=256, str_threads=256, z_threads=zt, z_fields=zf))
     for kw in combos:
-        s.set_tuning(**kw)
+        try:
+            s.set_tuning(**kw)
+        except B.PstdError as e:
+            # a z thread count that is not built for that tile
+            assert e.code == B.PSTD_EUNSUPPORTED and kw.get("z_threads", 256) != 256, kw
+            continue
         got_t = s.tuning()
         assert all(got_t[k] == v for k, v in kw.items())
         s.reset()
