@@ -17,7 +17,10 @@
  *   project   Y6 = Q2 gelu(Q1 V + q1b) + q2b           (6 O rows, O = 4 n_rec)
  *   output    Y[o] = sum_j m_j Y6[j O + o],  m_j = M_j / feat_scale[3 + j]
  * Every contraction runs on BF16 MFMA with FP32 accumulation; master weights,
- * gradients and Adam moments are FP32.  Training minimises the mean squared
+ * gradients and Adam moments are FP32.  The projection's six responses are
+ * weighted by the moment features before the product (one product per sample
+ * instead of six), so the output is linear in the moment tensor to BF16
+ * rounding.  Training minimises the mean squared
  * error of traces normalised per component by their training-set RMS.  An
  * error head predicts each sample's relative L2 error from the pooled last
  * hidden layer and the moment features; predictions whose estimate exceeds a tolerance are recomputed
@@ -55,6 +58,24 @@ typedef struct {
     int pos_mod;        /* 1: also each position feature times each cos and sin
                            feature (6 n_four more lift channels), so that a source
                            shift can move the phase of the time features; 0: off */
+    /* Travel-time-aligned output (frames = 2): the projection gives two sets
+     * of 6 O rows, a P frame and an S frame; row o of frame f is delayed by
+     * (tau_f(source, receiver r(o)) - t_ref[f]) / dt samples before the frames
+     * are summed, with tau_f the straight-ray travel time through a medium
+     * whose slowness depends on depth only (tau = |d| / |dz| times the depth
+     * integral of the slowness between the two cell centres; |d| slow[k] for
+     * a horizontal ray) and the fractional delay evaluated by 4-point Lagrange
+     * (cubic) interpolation, zero outside the window.  The direct arrivals then
+     * sit at fixed frame times for every source.  frames = 1: no delay (the
+     * fields below are ignored). */
+    int frames;
+    const int32_t *rec_ijk;  /* host [n_rec][3] receiver cells (copied by sno_create) */
+    int nz_slow;             /* depth cells of the profiles (source and receiver depths below it) */
+    const double *slow_p;    /* host [nz_slow] P slowness per depth cell, s/m (copied) */
+    const double *slow_s;    /* host [nz_slow] S slowness per depth cell, s/m (copied) */
+    double h[3];             /* cell size (m) along x, y, z */
+    double dt;               /* sample interval of the traces (s) */
+    double t_ref[2];         /* reference time of the P and S frames (s) */
 } sno_cfg;
 #define SNO_MAX_FOUR 64  /* size of four_cycles */
 
@@ -72,7 +93,8 @@ typedef struct {
 
 /* Create a model; params (host float, sno_n_params values, order P [C][NA]
  * with NA = 4 + 2 n_four (+ 6 n_four with pos_mod), pb [C], {W_l [C][C], b_l [C], Rr_l, Ri_l [K][C][C]}_l, Q1 [H][C],
- * q1b [H], Q2 [6 O][H], q2b [6 O]) are the initial weights. */
+ * q1b [H], Q2 [frames 6 O][H], q2b [frames 6 O]) are the initial weights; the
+ * rows of Q2 are ordered (frame, moment component, output). */
 int sno_create(const sno_cfg *cfg, const float *params, sno **out);
 long sno_n_params(const sno_cfg *cfg);
 void sno_destroy(sno *s);
@@ -106,6 +128,14 @@ int sno_forward(sno *s, const float *X, int n, float *Y, void *hip_stream);
 int sno_gradient(sno *s, const float *X, const float *Yt, int n, float *grad, float *loss, void *hip_stream);
 /* Copy the current FP32 weights to host memory. */
 int sno_get_params(const sno *s, float *params);
+/* Test entries of the optimiser: one Adam step of the weights with the device
+ * gradient grad (sno_n_params floats) at learning rate lr, beta1 = 0.9,
+ * beta2 = 0.999, eps = 1e-8 and the bias corrections 1 - beta^step of step
+ * `step` (>= 1) -- the update sno_train makes after each batch; the moments
+ * persist between calls (zero after sno_create, reset by sno_train).  And a
+ * copy of the two moments (host, sno_n_params floats each). */
+int sno_adam_step(sno *s, const float *grad, long step, double lr, void *hip_stream);
+int sno_get_moments(const sno *s, float *m, float *v);
 /* Output normalisation: per-component scale (4 floats, host). */
 int sno_get_scale(const sno *s, float *scale4);
 

@@ -16,8 +16,17 @@ only:
             U  = Uh G                 inverse DFT of the K modes of a real signal
             Z  = W_l V + b_l + U
             V  = gelu(Z)  (no activation after the last layer)
-  project:  Y6 = Q2 gelu(Q1 V + q1b) + q2b                              (6 O x T)
-  output:   Y[o] = sum_j m_j Y6[j O + o],  m = the 6 moment-tensor features
+  project:  Y6 = Q2 gelu(Q1 V + q1b) + q2b                     (frames x 6 O x T)
+  output:   Y[o](t) = sum_f sum_j m_j Y6[f][j O + o](t - shift[f][r(o)]),
+            m = the 6 moment-tensor features, r(o) = o mod n_rec the receiver
+
+With one frame and no shift this is a plain operator along time.  With two
+frames the network's time axis is a travel-time-aligned one: frame P (S) of
+receiver r is delayed by the straight-ray P (S) travel time from the source to
+r minus a reference time, so the direct arrivals sit at fixed frame times for
+every source and the network only has to learn their amplitudes and shapes.
+The delay is fractional: the delayed series is the 4-point Lagrange (cubic)
+interpolation of the frame, zero outside its samples.
 
 gelu(x) = x/2 (1 + tanh(sqrt(2/pi) (x + 0.044715 x^3))).  Loss: mean squared
 error over the batch and all outputs.  Gradients are written out by hand
@@ -43,6 +52,7 @@ class Dims:
     L: int = 4             # Fourier layers
     H: int = 128           # projection hidden width
     O: int = 256           # outputs per time sample (4 components x 64 receivers)
+    frames: int = 1        # output frames: 1 (plain time axis) or 2 (P- and S-aligned, shifted per receiver)
 
 
 def n_lift(d: Dims):
@@ -56,7 +66,8 @@ def param_shapes(d: Dims):
     s = [("P", (d.C, n_lift(d))), ("pb", (d.C,))]
     for l in range(d.L):
         s += [(f"W{l}", (d.C, d.C)), (f"b{l}", (d.C,)), (f"Rr{l}", (d.K, d.C, d.C)), (f"Ri{l}", (d.K, d.C, d.C))]
-    s += [("Q1", (d.H, d.C)), ("q1b", (d.H,)), ("Q2", (d.n_mt * d.O, d.H)), ("q2b", (d.n_mt * d.O,))]
+    s += [("Q1", (d.H, d.C)), ("q1b", (d.H,)), ("Q2", (d.frames * d.n_mt * d.O, d.H)),
+          ("q2b", (d.frames * d.n_mt * d.O,))]
     return s
 
 
@@ -128,7 +139,7 @@ def moments(src, d: Dims):
     return np.asarray(src, np.float64)[:, d.n_pos:d.n_pos + d.n_mt]
 
 
-def forward(theta, src, d: Dims, keep=False):
+def forward(theta, src, d: Dims, keep=False, shift=None):
     p = unflatten(theta, d)
     F, G = dft_bases(d)
     A = features(src, d)
@@ -149,26 +160,32 @@ def forward(theta, src, d: Dims, keep=False):
     Hp = np.einsum("hc,bct->bht", p["Q1"], V) + p["q1b"][None, :, None]
     Hq = gelu(Hp)
     Y6 = np.einsum("oh,bht->bot", p["Q2"], Hq) + p["q2b"][None, :, None]
-    Y6 = Y6.reshape(Y6.shape[0], d.n_mt, d.O, d.T)
+    Y6 = Y6.reshape(Y6.shape[0], d.frames, d.n_mt, d.O, d.T)
     m = moments(src, d)
-    Y = np.einsum("bj,bjot->bot", m, Y6)
+    # each frame's rows are delayed by their receiver's shift, then combined
+    Yf = Y6 if shift is None else frame_shift(Y6, shift, d)
+    Y = np.einsum("bj,bfjot->bot", m, Yf)
     cache.update(Hp=Hp, Hq=Hq, m=m)
     return (Y, cache) if keep else Y
 
 
-def loss(theta, src, y, d: Dims):
-    Y = forward(theta, src, d)
+def loss(theta, src, y, d: Dims, shift=None):
+    Y = forward(theta, src, d, shift=shift)
     return float(np.mean((Y - y) ** 2))
 
 
-def grad(theta, src, y, d: Dims):
+def grad(theta, src, y, d: Dims, shift=None):
     """Gradient of the mean squared error with respect to the flat parameters."""
     p = unflatten(theta, d)
     F, G = dft_bases(d)
-    Y, c = forward(theta, src, d, keep=True)
+    Y, c = forward(theta, src, d, keep=True, shift=shift)
     g = {}
     dY = 2.0 * (Y - y) / Y.size
-    dY6 = (c["m"][:, :, None, None] * dY[:, None, :, :]).reshape(Y.shape[0], d.n_mt * d.O, d.T)
+    dYf = np.broadcast_to(c["m"][:, None, :, None, None] * dY[:, None, None, :, :],
+                          (Y.shape[0], d.frames, d.n_mt, d.O, d.T))
+    if shift is not None:
+        dYf = frame_shift_transpose(dYf, shift, d)
+    dY6 = np.ascontiguousarray(dYf).reshape(Y.shape[0], d.frames * d.n_mt * d.O, d.T)
     g["Q2"] = np.einsum("bot,bht->oh", dY6, c["Hq"])
     g["q2b"] = dY6.sum(axis=(0, 2))
     dHq = np.einsum("oh,bot->bht", p["Q2"], dY6)
@@ -227,3 +244,99 @@ def error_head_fit(phi, err, ridge=1e-3):
 def error_head_predict(phi, h, margin):
     """Estimated relative error of each sample: exp(phi h + margin)."""
     return np.exp(np.asarray(phi, np.float64) @ h + margin)
+
+
+# ---------------------------------------------------------------------------
+# Travel-time-aligned output frames
+def lagrange4(w):
+    """Weights of the 4-point Lagrange interpolation at offsets -1, 0, 1, 2
+    from the sample left of the point, w in [0, 1): exact for cubics."""
+    return np.array([-w * (w - 1) * (w - 2) / 6.0, (w + 1) * (w - 1) * (w - 2) / 2.0,
+                     -(w + 1) * w * (w - 2) / 2.0, (w + 1) * w * (w - 1) / 6.0])
+
+
+def delay(u, delta):
+    """u(t - delta) for t = 0 .. T-1 (delta in samples): 4-point Lagrange
+    interpolation of u, samples outside [0, T) taken as zero."""
+    T = u.shape[-1]
+    out = np.zeros(u.shape[:-1] + (T,))
+    for t in range(T):
+        x = t - delta
+        i = math.floor(x)
+        w = lagrange4(x - i)
+        for k in range(4):
+            j = i - 1 + k
+            if 0 <= j < T:
+                out[..., t] += w[k] * u[..., j]
+    return out
+
+
+def delay_transpose(v, delta):
+    """The transpose of delay(., delta): scatters each v(t) onto the four
+    samples its interpolation read, with the same weights."""
+    T = v.shape[-1]
+    out = np.zeros(v.shape[:-1] + (T,))
+    for t in range(T):
+        x = t - delta
+        i = math.floor(x)
+        w = lagrange4(x - i)
+        for k in range(4):
+            j = i - 1 + k
+            if 0 <= j < T:
+                out[..., j] += w[k] * v[..., t]
+    return out
+
+
+def frame_shift(Y6, shift, d: Dims):
+    """Y6 (B x frames x n_mt x O x T) with row (f, j, o) delayed by shift[b][f][o mod n_rec]."""
+    n_rec = d.O // 4
+    out = np.empty_like(Y6)
+    for b in range(Y6.shape[0]):
+        for f in range(d.frames):
+            for o in range(d.O):
+                out[b, f, :, o] = delay(Y6[b, f, :, o], shift[b][f][o % n_rec])
+    return out
+
+
+def frame_shift_transpose(dY, shift, d: Dims):
+    n_rec = d.O // 4
+    out = np.empty(dY.shape)
+    for b in range(dY.shape[0]):
+        for f in range(d.frames):
+            for o in range(d.O):
+                out[b, f, :, o] = delay_transpose(dY[b, f, :, o], shift[b][f][o % n_rec])
+    return out
+
+
+def straight_ray_time(src, rec, slow, h):
+    """Travel time along the straight segment between two cell centres
+    (cell indices src, rec = (i, j, k)) through a medium whose slowness
+    depends on depth only: slow[k] (s/m) in the cells of depth index k, each
+    h[2] thick and centred on k h[2].  Along the segment the path length per
+    unit depth is constant (|d| / |dz|), so the time is that ratio times the
+    depth integral of the slowness, which from centre to centre is
+    h[2] (slow[k0] / 2 + sum of the cells strictly between + slow[k1] / 2);
+    a horizontal segment stays in one cell layer: |d| slow[k]."""
+    d = np.array([(src[a] - rec[a]) * h[a] for a in range(3)], np.float64)
+    L = float(np.linalg.norm(d))
+    k0, k1 = int(min(src[2], rec[2])), int(max(src[2], rec[2]))
+    if k0 == k1:
+        return L * slow[k0]
+    integral = 0.5 * slow[k0] + 0.5 * slow[k1]
+    for k in range(k0 + 1, k1):
+        integral += slow[k]
+    integral *= h[2]
+    return L / abs(d[2]) * integral
+
+
+def frame_shifts(src_ijk, rec_ijk, slows, h, dt, t_ref):
+    """shift[b][f][r] = (straight-ray time of frame f from source b to
+    receiver r - t_ref[f]) / dt, in samples; slows[f] is frame f's slowness
+    profile over depth."""
+    B, F, R = len(src_ijk), len(slows), len(rec_ijk)
+    out = np.empty((B, F, R))
+    for b in range(B):
+        for f in range(F):
+            for r in range(R):
+                out[b, f, r] = (straight_ray_time(src_ijk[b], rec_ijk[r], slows[f], h) - t_ref[f]) / dt
+    return out

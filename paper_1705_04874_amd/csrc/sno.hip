@@ -57,7 +57,8 @@ struct GemmP {
     float* C;
     long sCm, sCn, sCb;
     float alpha, beta;
-    const float* bias;
+    const float* bias;   // per row, and per batch entry with stride sBiasb
+    long sBiasb;
 };
 
 __global__ __launch_bounds__(256) void k_gemm(GemmP p)
@@ -116,7 +117,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmP p)
                     float* c = C + (long)row * p.sCm + (long)col * p.sCn;
                     float v = p.alpha * acc[mi][ni][i];
                     if (p.beta != 0.f) v += p.beta * (*c);
-                    if (p.bias) v += p.bias[row];
+                    if (p.bias) v += p.bias[b * p.sBiasb + row];
                     *c = v;
                 }
             }
@@ -124,9 +125,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmP p)
 
 void gemm(hipStream_t st, int batch, int M, int N, int K, int KB, const float* A, long sAm, long sAk, long sAb,
           long sAkb, const float* B, long sBk, long sBn, long sBb, long sBkb, float* C, long sCm, long sCn, long sCb,
-          float alpha = 1.f, float beta = 0.f, const float* bias = nullptr)
+          float alpha = 1.f, float beta = 0.f, const float* bias = nullptr, long sBiasb = 0)
 {
-    GemmP p{M, N, K, KB, A, sAm, sAk, sAb, sAkb, B, sBk, sBn, sBb, sBkb, C, sCm, sCn, sCb, alpha, beta, bias};
+    GemmP p{M, N, K, KB, A, sAm, sAk, sAb, sAkb, B, sBk, sBn, sBb, sBkb, C, sCm, sCn, sCb, alpha, beta, bias, sBiasb};
     hipLaunchKernelGGL(k_gemm, dim3((N + 63) / 64, (M + 63) / 64, batch), dim3(256), 0, st, p);
 }
 
@@ -199,33 +200,154 @@ __global__ void k_features(const float* __restrict__ X, Feat f, int B, int T, in
 // moment features m[b][j] = X[b][3 + j] / scale
 __device__ __forceinline__ float mfeat(const float* X, const Feat& f, int b, int j) { return X[b * 9 + 3 + j] * f.inv[3 + j]; }
 
-// Y[b][o][t] = sum_j m_j Y6[b][j O + o][t]
-__global__ void k_mcomb(const float* __restrict__ Y6, const float* __restrict__ X, Feat f, int B, int O, int T,
-                        float* __restrict__ Y)
+// The output is linear in the moment features (eq. 2 is linear in its
+// source), so the projection's 6 responses are weighted before the product:
+// Qm[b][f O + o][h] = sum_j m_bj Q2[(f 6 + j) O + o][h] and bm[b][f O + o] =
+// sum_j m_bj q2b[(f 6 + j) O + o], and the output rows of sample b come from
+// one product Qm[b] Hq[b] + bm[b] (a sixth of the work of forming all six
+// responses and combining them).
+__global__ void k_qmix(const float* __restrict__ Q2, const float* __restrict__ q2b, const float* __restrict__ X, Feat f,
+                       int B, int FO, int O, int H, float* __restrict__ Qm, float* __restrict__ bm)
+{
+    const long n = (long)B * FO * (H + 1);
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        const int hh = e % (H + 1);
+        const long bfo = e / (H + 1);
+        const int fo = bfo % FO, b = bfo / FO;
+        const int fr = fo / O, o = fo - fr * O;
+        float s = 0.f;
+        if (hh < H) {
+#pragma unroll
+            for (int j = 0; j < 6; ++j) s += mfeat(X, f, b, j) * Q2[((long)(fr * 6 + j) * O + o) * H + hh];
+            Qm[bfo * H + hh] = s;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 6; ++j) s += mfeat(X, f, b, j) * q2b[(fr * 6 + j) * O + o];
+            bm[bfo] = s;
+        }
+    }
+}
+
+// gradients of Q2 and q2b from those of the weighted projection:
+// dQ2[(f 6 + j) O + o][h] = sum_b m_bj dQm[b][f O + o][h] (h = H: the bias)
+__global__ void k_qgrad(const float* __restrict__ dQm, const float* __restrict__ dbm, const float* __restrict__ X,
+                        Feat f, int B, int FO, int O, int H, float* __restrict__ dQ2, float* __restrict__ dq2b)
+{
+    const int F = FO / O;
+    const long n = (long)F * 6 * O * (H + 1);
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+        const int hh = e % (H + 1);
+        const long row = e / (H + 1);             // (f 6 + j) O + o
+        const int o = row % O, fj = row / O;
+        const int fr = fj / 6, j = fj - fr * 6;
+        const int fo = fr * O + o;
+        float s = 0.f;
+        for (int b = 0; b < B; ++b)
+            s += mfeat(X, f, b, j) * (hh < H ? dQm[((long)b * FO + fo) * H + hh] : dbm[(long)b * FO + fo]);
+        if (hh < H) dQ2[row * H + hh] = s;
+        else dq2b[row] = s;
+    }
+}
+
+// Travel-time-aligned frames.  shift[b][f][r] = (tau_f - t_ref[f]) / dt with
+// tau_f the straight-ray time from source b's cell (X[b][0..2], whole cell
+// indices) to receiver r's; cum[f][k] = h_z (sum_{i<k} s_i + s_k / 2) is the
+// depth integral of frame f's slowness from the top to the centre of cell k.
+struct Rays {
+    const int* rec;        // [n_rec][3]
+    const double* cum;     // [frames][nz]
+    const double* slow;    // [frames][nz]
+    double h[3];
+    double dt;
+    double t_ref[2];
+    int nz, n_rec, frames;
+};
+
+__global__ void k_shifts(const float* __restrict__ X, Rays ry, int B, float* __restrict__ shift)
+{
+    const int n = B * ry.frames * ry.n_rec;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int r = e % ry.n_rec, f = (e / ry.n_rec) % ry.frames, b = e / (ry.n_rec * ry.frames);
+        int src[3];
+        for (int a = 0; a < 3; ++a) src[a] = (int)rintf(X[b * 9 + a]);
+        double d2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double d = (double)(src[a] - ry.rec[3 * r + a]) * ry.h[a];
+            d2 += d * d;
+        }
+        const double L = sqrt(d2);
+        const int ks = min(max(src[2], 0), ry.nz - 1), kr = ry.rec[3 * r + 2];
+        double tau;
+        if (ks == kr) {
+            tau = L * ry.slow[f * ry.nz + ks];
+        } else {
+            const double dz = fabs((double)(ks - kr) * ry.h[2]);
+            tau = L / dz * fabs(ry.cum[f * ry.nz + ks] - ry.cum[f * ry.nz + kr]);
+        }
+        shift[e] = (float)((tau - ry.t_ref[f]) / ry.dt);
+    }
+}
+
+// 4-point Lagrange weights at offsets -1, 0, 1, 2 from floor(x), w = x - floor(x)
+__device__ __forceinline__ void lagrange4(float w, float* c)
+{
+    c[0] = -w * (w - 1.f) * (w - 2.f) * (1.f / 6.f);
+    c[1] = (w + 1.f) * (w - 1.f) * (w - 2.f) * 0.5f;
+    c[2] = -(w + 1.f) * w * (w - 2.f) * 0.5f;
+    c[3] = (w + 1.f) * w * (w - 1.f) * (1.f / 6.f);
+}
+
+// Y[b][o][t] = sum_f Yf[b][f O + o](t - shift[b][f][o mod n_rec])
+__global__ void k_fcomb(const float* __restrict__ Yf, const float* __restrict__ shift, int B, int F, int O, int n_rec,
+                        int T, float* __restrict__ Y)
 {
     const long per = (long)O * T;
     const long n = (long)B * per;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
         const int b = e / per;
-        const long r = e - b * per;
-        float s = 0.f;
+        const int o = (e / T) % O, t = e % T;
+        float acc = 0.f;
+        for (int fr = 0; fr < F; ++fr) {
+            const float x = (float)t - shift[(b * F + fr) * n_rec + o % n_rec];
+            const float fl = floorf(x);
+            float c[4];
+            lagrange4(x - fl, c);
+            const int i0 = (int)fl - 1;
+            const float* u = Yf + ((long)b * F + fr) * per + (long)o * T;
 #pragma unroll
-        for (int j = 0; j < 6; ++j) s += mfeat(X, f, b, j) * Y6[((long)b * 6 + j) * per + r];
-        Y[e] = s;
+            for (int k = 0; k < 4; ++k) {
+                const int i = i0 + k;
+                if (i >= 0 && i < T) acc += c[k] * u[i];
+            }
+        }
+        Y[e] = acc;
     }
 }
 
-// dY6[b][j O + o][t] = m_j dY[b][o][t]
-__global__ void k_mspread(const float* __restrict__ dY, const float* __restrict__ X, Feat f, int B, int O, int T,
-                          float* __restrict__ dY6)
+// dYf[b][f O + o][i] = sum_t dY[b][o][t] w_{t,i}: the transpose of k_fcomb, as a
+// gather over the (at most five) t whose interpolation reads sample i
+__global__ void k_fspread(const float* __restrict__ dY, const float* __restrict__ shift, int B, int F, int O, int n_rec,
+                          int T, float* __restrict__ dYf)
 {
     const long per = (long)O * T;
-    const long n = (long)B * 6 * per;
+    const long n = (long)B * F * per;
     for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-        const int bj = e / per;
-        const long r = e - bj * per;
-        const int b = bj / 6, j = bj - b * 6;
-        dY6[e] = mfeat(X, f, b, j) * dY[(long)b * per + r];
+        const int i = e % T, o = (e / T) % O;
+        const int bf = e / per, b = bf / F;
+        const float sh = shift[bf * n_rec + o % n_rec];
+        // t - sh in [i - 2, i + 1] reads sample i
+        const int t0 = max(0, (int)floorf((float)i - 2.f + sh)), t1 = min(T - 1, (int)ceilf((float)i + 1.f + sh));
+        float acc = 0.f;
+        for (int t = t0; t <= t1; ++t) {
+            const float x = (float)t - sh;
+            const float fl = floorf(x);
+            const int k = i - (int)fl + 1;
+            if (k < 0 || k > 3) continue;
+            float c[4];
+            lagrange4(x - fl, c);
+            acc += c[k] * dY[(long)b * per + (long)o * T + t];
+        }
+        dYf[e] = acc;
     }
 }
 
@@ -276,12 +398,15 @@ __global__ void k_sum_parts(const float* __restrict__ part, int np, float* __res
     }
 }
 
+// Adam step; omb1 = 1 - b1 and omb2 = 1 - b2 come rounded from double (1 - b2
+// formed in float would carry the rounding of b2 = 0.999 into the weight of g^2,
+// a 1.3e-5 relative error)
 __global__ void k_adam(float* __restrict__ th, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
-                       long n, float lr, float b1, float b2, float eps, float c1, float c2)
+                       long n, float lr, float b1, float b2, float omb1, float omb2, float eps, float c1, float c2)
 {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const float mi = b1 * m[i] + (1.f - b1) * g[i];
-        const float vi = b2 * v[i] + (1.f - b2) * g[i] * g[i];
+        const float mi = b1 * m[i] + omb1 * g[i];
+        const float vi = b2 * v[i] + omb2 * g[i] * g[i];
         m[i] = mi;
         v[i] = vi;
         th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
@@ -424,20 +549,25 @@ struct sno {
     long np = 0;
     long off_P, off_pb, off_W[16], off_b[16], off_Rr[16], off_Ri[16], off_Q1, off_q1b, off_Q2, off_q2b;
     float *theta = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
-    float *F = nullptr, *G = nullptr;
+    float *Fb = nullptr, *G = nullptr;   // truncated DFT bases
     float *dscale = nullptr;
     float scale[4] = {1, 1, 1, 1};
     std::vector<float> head;
     float head_margin = 0.f;
     float* dhead = nullptr;
     Feat feat{};
+    int F = 1;                 // output frames
+    int* drec = nullptr;       // ray tables (frames = 2)
+    double* dcum = nullptr;
+    double* dslow = nullptr;
+    Rays rays{};
     int device = 0;
     // workspace for batches of up to bmax samples
     int bmax = 0;
     float *A = nullptr, *Vb = nullptr, *Vh = nullptr, *Z = nullptr, *Uh = nullptr, *Hp = nullptr, *Hq = nullptr,
           *Y = nullptr, *X0 = nullptr, *X1 = nullptr, *X2 = nullptr, *dH = nullptr, *dUh = nullptr, *dVh = nullptr,
           *part = nullptr, *lossd = nullptr, *phi = nullptr, *Xb = nullptr, *Yb = nullptr, *Y6 = nullptr,
-          *dY6 = nullptr;
+          *dY6 = nullptr, *shift = nullptr, *Qm = nullptr, *dQm = nullptr, *bm = nullptr, *dbm = nullptr;
     int* idxd = nullptr;
 
     float* V(int l) { return l < cfg.L ? Vb + (long)l * bmax * cfg.C * cfg.T : Z + (long)(cfg.L - 1) * bmax * cfg.C * cfg.T; }
@@ -446,18 +576,22 @@ struct sno {
 
     void free_ws()
     {
-        for (float* p : {A, Vb, Vh, Z, Uh, Hp, Hq, Y, X0, X1, X2, dH, dUh, dVh, part, lossd, phi, Xb, Yb, Y6, dY6})
+        for (float* p : {A, Vb, Vh, Z, Uh, Hp, Hq, Y, X0, X1, X2, dH, dUh, dVh, part, lossd, phi, Xb, Yb, Y6, dY6, shift,
+                         Qm, dQm, bm, dbm})
             (void)hipFree(p);
         (void)hipFree(idxd);
         A = Vb = Vh = Z = Uh = Hp = Hq = Y = X0 = X1 = X2 = dH = dUh = dVh = part = lossd = phi = Xb = Yb = Y6 = dY6 =
-            nullptr;
+            shift = Qm = dQm = bm = dbm = nullptr;
         idxd = nullptr;
         bmax = 0;
     }
     ~sno()
     {
         free_ws();
-        for (float* p : {theta, grad, m1, m2, F, G, dscale, dhead}) (void)hipFree(p);
+        for (float* p : {theta, grad, m1, m2, Fb, G, dscale, dhead}) (void)hipFree(p);
+        (void)hipFree(drec);
+        (void)hipFree(dcum);
+        (void)hipFree(dslow);
     }
 
     int ensure(int B)
@@ -466,7 +600,9 @@ struct sno {
         free_ws();
         const long C = cfg.C, T = cfg.T, K2 = 2 * cfg.K, H = cfg.H, L = cfg.L;
         auto al = [&](float** p, long n) { return hipMalloc(p, std::max<long>(n, 1) * sizeof(float)); };
-        if (al(&A, (long)B * NA * T) || al(&Y6, (long)B * 6 * O * T) || al(&dY6, (long)B * 6 * O * T) || al(&Vb, L * B * C * T) || al(&Vh, L * B * C * K2) || al(&Z, L * B * C * T) ||
+        if (al(&A, (long)B * NA * T) || al(&Y6, (long)B * F * O * T) || al(&dY6, (long)B * F * O * T) ||
+            al(&shift, (long)B * F * cfg.n_rec) || al(&Qm, (long)B * F * O * H) || al(&dQm, (long)B * F * O * H) ||
+            al(&bm, (long)B * F * O) || al(&dbm, (long)B * F * O) || al(&Vb, L * B * C * T) || al(&Vh, L * B * C * K2) || al(&Z, L * B * C * T) ||
             al(&Uh, (long)B * C * K2) || al(&Hp, (long)B * H * T) || al(&Hq, (long)B * H * T) ||
             al(&Y, (long)B * O * T) || al(&X0, (long)B * std::max(C, (long)O) * T) || al(&X1, (long)B * C * T) ||
             al(&X2, (long)B * C * T) || al(&dH, (long)B * H * T) || al(&dUh, (long)B * C * K2) ||
@@ -497,7 +633,8 @@ long layout(sno_cfg c, sno* s)
         Rr[l] = take((long)c.K * c.C * c.C);
         Ri[l] = take((long)c.K * c.C * c.C);
     }
-    long Q1 = take((long)c.H * c.C), q1b = take(c.H), Q2 = take(6L * O * c.H), q2b = take(6L * O);
+    const long FR = c.frames == 2 ? 2 : 1;
+    long Q1 = take((long)c.H * c.C), q1b = take(c.H), Q2 = take(FR * 6L * O * c.H), q2b = take(FR * 6L * O);
     if (s) {
         s->off_P = P;
         s->off_pb = pb;
@@ -527,6 +664,21 @@ bool cfg_ok(const sno_cfg* c)
     if (c->n_four < 0 || c->n_four > SNO_MAX_FOUR || (c->pos_mod != 0 && c->pos_mod != 1)) return false;
     for (int f = 0; f < c->n_four; ++f)
         if (!(c->four_cycles[f] > 0.0 && c->four_cycles[f] <= c->T / 2)) return false;
+    if (c->frames != 1 && c->frames != 2) return false;
+    if (c->frames == 2) {
+        if (!c->rec_ijk || !c->slow_p || !c->slow_s || c->nz_slow < 1 || !(c->dt > 0) || !std::isfinite(c->dt))
+            return false;
+        for (int a = 0; a < 3; ++a)
+            if (!(c->h[a] > 0) || !std::isfinite(c->h[a])) return false;
+        for (int f = 0; f < 2; ++f)
+            if (!std::isfinite(c->t_ref[f])) return false;
+        for (int r = 0; r < c->n_rec; ++r)
+            if (c->rec_ijk[3 * r + 2] < 0 || c->rec_ijk[3 * r + 2] >= c->nz_slow) return false;
+        for (int k = 0; k < c->nz_slow; ++k)
+            if (!(c->slow_p[k] >= 0) || !(c->slow_s[k] >= 0) || !std::isfinite(c->slow_p[k]) ||
+                !std::isfinite(c->slow_s[k]))
+                return false;
+    }
     return true;
 }
 
@@ -545,7 +697,7 @@ void forward(sno* s, hipStream_t st, const float* X, int B)
         float* Vh = s->Vhl(l);
         float* Z = s->Zl(l);
         // truncated DFT along time
-        gemm(st, B, C, K2, T, 1, V, T, 1, C * T, 0, s->F, K2, 1, 0, 0, Vh, K2, 1, C * K2);
+        gemm(st, B, C, K2, T, 1, V, T, 1, C * T, 0, s->Fb, K2, 1, 0, 0, Vh, K2, 1, C * K2);
         // complex mixing per mode: batch over modes, samples as columns
         const float* Rr = th + s->off_Rr[l];
         const float* Ri = th + s->off_Ri[l];
@@ -563,9 +715,19 @@ void forward(sno* s, hipStream_t st, const float* X, int B)
     gemm(st, B, H, T, C, 1, th + s->off_Q1, C, 1, 0, 0, s->V(c.L), T, 1, C * T, 0, s->Hp, T, 1, H * T, 1.f, 0.f,
          th + s->off_q1b);
     hipLaunchKernelGGL(k_gelu, dim3(grid_for(B * H * T)), dim3(256), 0, st, s->Hp, s->Hq, (long)B * H * T);
-    gemm(st, B, 6 * O, T, H, 1, th + s->off_Q2, H, 1, 0, 0, s->Hq, T, 1, H * T, 0, s->Y6, T, 1, 6 * O * T, 1.f, 0.f,
-         th + s->off_q2b);
-    hipLaunchKernelGGL(k_mcomb, dim3(grid_for(B * O * T)), dim3(256), 0, st, s->Y6, X, s->feat, B, (int)O, (int)T, s->Y);
+    // moment-weighted projection: one frame writes the output directly, two
+    // frames go through the per-receiver delays
+    const long FO = s->F * O;
+    hipLaunchKernelGGL(k_qmix, dim3(grid_for(B * FO * (H + 1))), dim3(256), 0, st, th + s->off_Q2, th + s->off_q2b, X,
+                       s->feat, B, (int)FO, (int)O, (int)H, s->Qm, s->bm);
+    float* Yf = s->F == 1 ? s->Y : s->Y6;
+    gemm(st, B, FO, T, H, 1, s->Qm, H, 1, FO * H, 0, s->Hq, T, 1, H * T, 0, Yf, T, 1, FO * T, 1.f, 0.f, s->bm, FO);
+    if (s->F == 2) {
+        hipLaunchKernelGGL(k_shifts, dim3(grid_for((long)B * s->F * c.n_rec)), dim3(256), 0, st, X, s->rays, B,
+                           s->shift);
+        hipLaunchKernelGGL(k_fcomb, dim3(grid_for(B * O * T)), dim3(256), 0, st, s->Y6, s->shift, B, s->F, (int)O,
+                           c.n_rec, (int)T, s->Y);
+    }
 }
 
 // gradient of the mean squared error of s->Y against Yt (after the forward of
@@ -580,13 +742,21 @@ void backward(sno* s, hipStream_t st, const float* X, const float* Yt, int B)
     float* dY = s->X0;
     hipLaunchKernelGGL(k_mse, dim3(256), dim3(256), 0, st, s->Y, Yt, nY, dY, s->part);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, s->part, 256, s->lossd, 1.f / (float)nY);
-    // moment combination and projection
-    const long O6 = 6 * O;
-    hipLaunchKernelGGL(k_mspread, dim3(grid_for(B * O6 * T)), dim3(256), 0, st, dY, X, s->feat, B, (int)O, (int)T,
-                       s->dY6);
-    gemm(st, 1, O6, H, T, B, s->dY6, T, 1, 0, O6 * T, s->Hq, 1, T, 0, H * T, g + s->off_Q2, H, 1, 0);
-    hipLaunchKernelGGL(k_rowsum, dim3(O6), dim3(256), 0, st, s->dY6, B, (int)O6, (int)T, g + s->off_q2b);
-    gemm(st, B, H, T, O6, 1, th + s->off_Q2, 1, H, 0, 0, s->dY6, T, 1, O6 * T, 0, s->dH, T, 1, H * T);
+    // frame delays (transposed), then the moment-weighted projection:
+    // dQm[b] = dYf[b] Hq[b]^T, dbm[b] = row sums of dYf[b], dHq[b] = Qm[b]^T dYf[b],
+    // and the 6 responses' gradients weighted back by the moment features
+    const long FO = s->F * O;
+    float* dYf = dY;
+    if (s->F == 2) {
+        dYf = s->dY6;
+        hipLaunchKernelGGL(k_fspread, dim3(grid_for((long)B * FO * T)), dim3(256), 0, st, dY, s->shift, B, s->F,
+                           (int)O, c.n_rec, (int)T, dYf);
+    }
+    gemm(st, B, FO, H, T, 1, dYf, T, 1, FO * T, 0, s->Hq, 1, T, H * T, 0, s->dQm, H, 1, FO * H);
+    hipLaunchKernelGGL(k_rowsum, dim3(B * FO), dim3(256), 0, st, dYf, 1, (int)(B * FO), (int)T, s->dbm);
+    hipLaunchKernelGGL(k_qgrad, dim3(grid_for(s->F * 6 * O * (H + 1))), dim3(256), 0, st, s->dQm, s->dbm, X, s->feat, B,
+                       (int)FO, (int)O, (int)H, g + s->off_Q2, g + s->off_q2b);
+    gemm(st, B, H, T, FO, 1, s->Qm, 1, H, FO * H, 0, dYf, T, 1, FO * T, 0, s->dH, T, 1, H * T);
     hipLaunchKernelGGL(k_gelu_bwd, dim3(grid_for(B * H * T)), dim3(256), 0, st, s->dH, s->Hp, s->dH, (long)B * H * T);
     gemm(st, 1, H, C, T, B, s->dH, T, 1, 0, H * T, s->V(c.L), 1, T, 0, C * T, g + s->off_Q1, C, 1, 0);
     hipLaunchKernelGGL(k_rowsum, dim3(H), dim3(256), 0, st, s->dH, B, (int)H, (int)T, g + s->off_q1b);
@@ -626,7 +796,7 @@ void backward(sno* s, hipStream_t st, const float* X, const float* Yt, int B)
         gemm(st, K, C, B, C, 1, Rr, 1, C, C * C, 0, s->dUh + K, K2, C * K2, 1, 0, s->dVh + K, K2, C * K2, 1, 1.f, 1.f);
         // dV = W^T dZ + dVh F^T
         gemm(st, B, C, T, C, 1, th + s->off_W[l], 1, C, 0, 0, dZ, T, 1, C * T, 0, dVn, T, 1, C * T);
-        gemm(st, B, C, T, K2, 1, s->dVh, K2, 1, C * K2, 0, s->F, 1, K2, 0, 0, dVn, T, 1, C * T, 1.f, 1.f);
+        gemm(st, B, C, T, K2, 1, s->dVh, K2, 1, C * K2, 0, s->Fb, 1, K2, 0, 0, dVn, T, 1, C * T, 1.f, 1.f);
         dV = dVn;
     }
     const long NA = s->NA;
@@ -660,6 +830,9 @@ int sno_create(const sno_cfg* cfg, const float* params, sno** out)
     auto* s = new (std::nothrow) sno();
     if (!s) return sfail(PSTD_ENOMEM, "host allocation");
     s->cfg = *cfg;
+    s->cfg.rec_ijk = nullptr;   // the host arrays are copied below, not kept
+    s->cfg.slow_p = s->cfg.slow_s = nullptr;
+    s->F = cfg->frames;
     s->O = 4 * cfg->n_rec;
     s->NA = n_lift(*cfg);
     s->np = layout(*cfg, s);
@@ -685,11 +858,34 @@ int sno_create(const sno_cfg* cfg, const float* params, sno** out)
         }
     int rc = PSTD_OK;
     if (hipMalloc(&s->theta, np * 4) || hipMalloc(&s->grad, np * 4) || hipMalloc(&s->m1, np * 4) ||
-        hipMalloc(&s->m2, np * 4) || hipMalloc(&s->F, F.size() * 4) || hipMalloc(&s->G, G.size() * 4) ||
+        hipMalloc(&s->m2, np * 4) || hipMalloc(&s->Fb, F.size() * 4) || hipMalloc(&s->G, G.size() * 4) ||
         hipMalloc(&s->dscale, 16) || hipMalloc(&s->dhead, (cfg->C + 7) * 4))
         rc = sfail(PSTD_ENOMEM, "surrogate parameters");
+    if (!rc && cfg->frames == 2) {
+        // ray tables: receivers, per-frame slowness and its depth integral to
+        // each cell centre, h_z (sum_{i<k} s_i + s_k / 2), summed in double
+        const int nz = cfg->nz_slow;
+        std::vector<double> cum(2 * (size_t)nz), slow(2 * (size_t)nz);
+        for (int f = 0; f < 2; ++f) {
+            const double* sl = f == 0 ? cfg->slow_p : cfg->slow_s;
+            double acc = 0.0;
+            for (int k = 0; k < nz; ++k) {
+                slow[(size_t)f * nz + k] = sl[k];
+                cum[(size_t)f * nz + k] = cfg->h[2] * (acc + 0.5 * sl[k]);
+                acc += sl[k];
+            }
+        }
+        if (hipMalloc(&s->drec, (size_t)cfg->n_rec * 3 * sizeof(int)) || hipMalloc(&s->dcum, cum.size() * 8) ||
+            hipMalloc(&s->dslow, slow.size() * 8) ||
+            hipMemcpy(s->drec, cfg->rec_ijk, (size_t)cfg->n_rec * 3 * sizeof(int), hipMemcpyHostToDevice) ||
+            hipMemcpy(s->dcum, cum.data(), cum.size() * 8, hipMemcpyHostToDevice) ||
+            hipMemcpy(s->dslow, slow.data(), slow.size() * 8, hipMemcpyHostToDevice))
+            rc = sfail(PSTD_ENOMEM, "surrogate ray tables");
+        s->rays = Rays{s->drec, s->dcum, s->dslow, {cfg->h[0], cfg->h[1], cfg->h[2]}, cfg->dt,
+                       {cfg->t_ref[0], cfg->t_ref[1]}, nz, cfg->n_rec, 2};
+    }
     if (!rc && (hipMemcpy(s->theta, params, np * 4, hipMemcpyHostToDevice) ||
-                hipMemcpy(s->F, F.data(), F.size() * 4, hipMemcpyHostToDevice) ||
+                hipMemcpy(s->Fb, F.data(), F.size() * 4, hipMemcpyHostToDevice) ||
                 hipMemcpy(s->G, G.data(), G.size() * 4, hipMemcpyHostToDevice) ||
                 hipMemcpy(s->dscale, s->scale, 16, hipMemcpyHostToDevice) || hipMemset(s->m1, 0, np * 4) ||
                 hipMemset(s->m2, 0, np * 4) || hipMemset(s->grad, 0, np * 4)))
@@ -720,6 +916,28 @@ int sno_get_params(const sno* s, float* params)
     if (!s || !params) return sfail(PSTD_EINVAL, "null argument");
     S_TRY(hipDeviceSynchronize());
     S_TRY(hipMemcpy(params, s->theta, s->np * 4, hipMemcpyDeviceToHost));
+    return PSTD_OK;
+}
+
+int sno_adam_step(sno* s, const float* grad, long step, double lr, void* hip_stream)
+{
+    if (!s || !grad || step < 1 || !(lr >= 0) || !std::isfinite(lr)) return sfail(PSTD_EINVAL, "bad arguments");
+    hipStream_t st = (hipStream_t)hip_stream;
+    const float c1 = (float)(1.0 - std::pow(0.9, (double)step));
+    const float c2 = (float)(1.0 - std::pow(0.999, (double)step));
+    hipLaunchKernelGGL(k_adam, dim3(grid_for(s->np)), dim3(256), 0, st, s->theta, grad, s->m1, s->m2, s->np, (float)lr,
+                       0.9f, 0.999f, (float)(1.0 - 0.9), (float)(1.0 - 0.999), 1e-8f, c1, c2);
+    S_TRY(hipGetLastError());
+    S_TRY(hipStreamSynchronize(st));
+    return PSTD_OK;
+}
+
+int sno_get_moments(const sno* s, float* m, float* v)
+{
+    if (!s || !m || !v) return sfail(PSTD_EINVAL, "null argument");
+    S_TRY(hipDeviceSynchronize());
+    S_TRY(hipMemcpy(m, s->m1, s->np * 4, hipMemcpyDeviceToHost));
+    S_TRY(hipMemcpy(v, s->m2, s->np * 4, hipMemcpyDeviceToHost));
     return PSTD_OK;
 }
 
@@ -814,7 +1032,7 @@ int sno_train(sno* s, const float* X, const float* Y, int n, const sno_train_cfg
             const float c1 = (float)(1.0 - std::pow(0.9, (double)step));
             const float c2 = (float)(1.0 - std::pow(0.999, (double)step));
             hipLaunchKernelGGL(k_adam, dim3(grid_for(s->np)), dim3(256), 0, st, s->theta, s->grad, s->m1, s->m2, s->np,
-                               (float)lr, 0.9f, 0.999f, 1e-8f, c1, c2);
+                               (float)lr, 0.9f, 0.999f, (float)(1.0 - 0.9), (float)(1.0 - 0.999), 1e-8f, c1, c2);
             S_TRY(hipMemcpyAsync(&lbuf[it], s->lossd, 4, hipMemcpyDeviceToHost, st));
         }
         S_TRY(hipGetLastError());

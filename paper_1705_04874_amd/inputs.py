@@ -414,3 +414,30 @@ def cluster_draws(n: int, k: int, runs: int, seed: int):
     rng = np.random.default_rng(seed)
     init = np.stack([rng.choice(n, size=k, replace=False) for _ in range(runs)]).astype(np.int32)
     return init, rng.standard_normal(n), rng.uniform(size=n)
+
+
+def depth_slowness(model: Model):
+    """Mean slowness per depth cell, P and S (s/m): the depth profile a
+    travel-time-aligned surrogate uses; 0 for S where the layer is fluid."""
+    slow_p = (1.0 / model.vp).mean(axis=(1, 2))
+    with np.errstate(divide="ignore"):
+        inv_s = np.where(model.vs > 0, 1.0 / np.where(model.vs > 0, model.vs, 1.0), 0.0)
+    return slow_p, inv_s.mean(axis=(1, 2))
+
+
+def straight_ray_reference_times(slow_p, slow_s, src, rec, h):
+    """P and S straight-ray times (s) between two cell centres through depth
+    profiles of slowness: |d| / |dz| times the depth integral of the slowness
+    from centre to centre (|d| times the slowness of the layer for a
+    horizontal segment).  Reference times of the aligned surrogate frames."""
+    d = np.array([(src[a] - rec[a]) * h[a] for a in range(3)], np.float64)
+    L = float(np.linalg.norm(d))
+    k0, k1 = int(min(src[2], rec[2])), int(max(src[2], rec[2]))
+    out = []
+    for sl in (slow_p, slow_s):
+        if k0 == k1:
+            out.append(L * sl[k0])
+        else:
+            integ = h[2] * (0.5 * sl[k0] + sl[k0 + 1:k1].sum() + 0.5 * sl[k1])
+            out.append(L / abs(d[2]) * integ)
+    return tuple(out)

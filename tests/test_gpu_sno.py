@@ -58,7 +58,9 @@ def test_forward_matches_oracle(B, d):
 
 def test_output_is_linear_in_the_moment_tensor(B):
     """Sources at one position: the traces of a combined mechanism equal the
-    combination of the traces (eq. 2 is linear in its source)."""
+    combination of the traces (eq. 2 is linear in its source).  The projection
+    weights its six responses by the moment features before the BF16 product,
+    so the combination holds to BF16 rounding; a zero tensor gives exactly zero."""
     import torch
     d = SMALL
     rng = np.random.default_rng(5)
@@ -68,7 +70,7 @@ def test_output_is_linear_in_the_moment_tensor(B):
     X = np.stack([np.concatenate([pos, m]) for m in (m1, m2, 1.5 * m1 - 0.25 * m2, np.zeros(6))])
     y = s.forward(torch.tensor(X, dtype=torch.float32, device="cuda")).cpu().numpy().astype(np.float64)
     comb = 1.5 * y[0] - 0.25 * y[1]
-    assert np.abs(y[2] - comb).max() <= 1e-5 * np.abs(comb).max()
+    assert np.abs(y[2] - comb).max() <= 1e-2 * np.abs(comb).max()
     assert np.abs(y[3]).max() == 0.0
 
 
@@ -245,3 +247,132 @@ def test_trained_network_gains_over_the_solver_alone(B):
     t_solver_all = t_rej * n_te / rej.size
     say("blend", t_blend, "solver alone (scaled)", t_solver_all, "accepted", int(acc.sum()))
     assert t_blend < t_solver_all
+
+
+# ---------------------------------------------------------------------------
+# travel-time-aligned frames, full-size gradients, Adam
+def frames_setup(d, rng, B):
+    """Receivers on a line at depth 20 of a 128-deep layered profile, sources
+    as whole cells below, and the oracle's shifts for them."""
+    n_rec = d.O // 4
+    rec = np.stack([32 + np.arange(n_rec) * (64 // n_rec), np.full(n_rec, 64), np.full(n_rec, 20)], 1).astype(np.int32)
+    vp = np.concatenate([np.full(20, 1500.0), np.linspace(2000.0, 4000.0, 108)])
+    slow_p = 1.0 / vp
+    slow_s = np.where(np.arange(128) < 20, 0.0, 1.8 / vp)
+    h, dt = (10.0, 10.0, 10.0), 1.6e-3
+    t_ref = (0.15, 0.26)
+    cells = np.stack([rng.integers(40, 90, B), rng.integers(40, 90, B), rng.integers(45, 95, B)], 1).astype(np.int32)
+    shift = osno.frame_shifts(cells, rec, [slow_p, slow_s], h, dt, t_ref)
+    fr = dict(rec_ijk=rec, slow_p=slow_p, slow_s=slow_s, h=h, dt=dt, t_ref=t_ref)
+    return cells, shift, fr
+
+
+def make_frames(B_, d, theta, fr, off, scl):
+    return B_.Surrogate(d.O // 4, d.T, d.C, d.K, d.L, d.H, off, scl, theta.astype(np.float32), four_cycles=d.four,
+                        pos_mod=d.pos_mod, frames=fr)
+
+
+SMALL_FR = osno.Dims(four=(3.0, 7.0, 12.5), C=16, T=128, K=4, L=2, H=32, O=8, frames=2)
+FULL_FR = osno.Dims(four=inputs.sno_fourier_cycles(32, 4.0, 128.0), pos_mod=True, C=64, T=1024, K=16, L=4, H=256,
+                    O=256, frames=2)
+
+
+def init_fr(d, seed):
+    return inputs.sno_init_params(d.C, d.K, d.L, d.H, d.frames * d.O, osno.n_lift(d), seed, d.n_mt)
+
+
+@pytest.mark.parametrize("d", [SMALL_FR, FULL_FR], ids=["small", "full"])
+def test_aligned_frames_forward_matches_oracle(B, d):
+    import torch
+    rng = np.random.default_rng(30)
+    nb = 2
+    cells, shift, fr = frames_setup(d, rng, nb)
+    theta = (init_fr(d, 31) + 0.02 * rng.standard_normal(osno.n_params(d))).astype(np.float32).astype(np.float64)
+    mts = rng.uniform(-1, 1, (nb, 6)) * 1000.0
+    off = [64.0, 64.0, 70.0] + [0.0] * 6
+    scl = [25.0] * 3 + [1000.0] * 6
+    X = np.concatenate([cells, mts], 1)
+    src = (X - np.array(off)) / np.array(scl)
+    ref = osno.forward(theta, src, d, shift=shift)
+    s = make_frames(B, d, theta, fr, off, scl)
+    got = s.forward(torch.tensor(X, dtype=torch.float32, device="cuda")).cpu().numpy().reshape(ref.shape)
+    e = rel(got, ref)
+    say("aligned forward", d.O, d.T, e, "shift range", shift.min(), shift.max())
+    assert shift.max() - shift.min() > 20          # the frames really move by many samples
+    assert e < 2e-2
+
+
+@pytest.mark.parametrize("d", [SMALL_FR, FULL_FR], ids=["small", "full"])
+def test_aligned_frames_gradient_matches_oracle(B, d):
+    """Gradients of every parameter block with the frame delays in the loop, at
+    a small size and at the configuration's full size (width 64, 16 modes, 4
+    layers, 1024 samples, 64 receivers x 4 components, H = 256)."""
+    import torch
+    rng = np.random.default_rng(32)
+    nb = 2
+    cells, shift, fr = frames_setup(d, rng, nb)
+    theta = (init_fr(d, 33) + 0.05 * rng.standard_normal(osno.n_params(d))).astype(np.float32).astype(np.float64)
+    mts = rng.uniform(-1, 1, (nb, 6)) * 1000.0
+    off = [64.0, 64.0, 70.0] + [0.0] * 6
+    scl = [25.0] * 3 + [1000.0] * 6
+    X = np.concatenate([cells, mts], 1)
+    src = (X - np.array(off)) / np.array(scl)
+    Yt = rng.standard_normal((nb, d.O, d.T))
+    ref = osno.grad(theta, src, Yt, d, shift=shift)
+    s = make_frames(B, d, theta, fr, off, scl)
+    g, loss = s.gradient(torch.tensor(X, dtype=torch.float32, device="cuda"),
+                         torch.tensor(Yt, dtype=torch.float32, device="cuda"))
+    g = g.cpu().numpy()
+    lref = osno.loss(theta, src, Yt, d, shift)
+    assert abs(loss - lref) < 2e-2 * lref
+    o = 0
+    for name, sh in osno.param_shapes(d):
+        n = int(np.prod(sh))
+        e = rel(g[o:o + n], ref[o:o + n])
+        say(f"  grad {name}: rel-L2 {e:.2e}")
+        assert e < 2e-2, name
+        o += n
+
+
+def test_full_size_gradient_of_the_plain_operator_matches_oracle(B):
+    """The plain (one frame) operator's gradient at the configuration's full
+    size: width 64, 16 modes, 4 layers, 1024 samples, 256 outputs, H = 256."""
+    import torch
+    d = FULL
+    rng = np.random.default_rng(34)
+    theta = (init(d, 35) + 0.05 * rng.standard_normal(osno.n_params(d))).astype(np.float32).astype(np.float64)
+    X = rng.uniform(-1, 1, (2, 9))
+    Yt = rng.standard_normal((2, d.O, d.T))
+    ref = osno.grad(theta, X, Yt, d)
+    s = make(B, d, theta)
+    g, _ = s.gradient(torch.tensor(X, dtype=torch.float32, device="cuda"),
+                      torch.tensor(Yt, dtype=torch.float32, device="cuda"))
+    g = g.cpu().numpy()
+    o = 0
+    for name, sh in osno.param_shapes(d):
+        n = int(np.prod(sh))
+        e = rel(g[o:o + n], ref[o:o + n])
+        assert e < 2e-2, (name, e)
+        o += n
+
+
+def test_adam_steps_match_oracle(B):
+    """Three GPU Adam steps with fixed gradients against osno.adam in FP64:
+    weights and both moments, element by element (FP32 arithmetic)."""
+    import torch
+    d = SMALL
+    rng = np.random.default_rng(36)
+    theta = init(d, 37).astype(np.float32)
+    s = make(B, d, theta.astype(np.float64))
+    th, m, v = theta.astype(np.float64), np.zeros(theta.size), np.zeros(theta.size)
+    lr = 3e-3
+    for step in range(1, 4):
+        g = (rng.standard_normal(theta.size) * np.exp(rng.uniform(-3, 1, theta.size))).astype(np.float32)
+        s.adam_step(torch.from_numpy(g).cuda(), step, lr)
+        th, m, v = osno.adam(th, g.astype(np.float64), m, v, step, lr)
+        gm, gv = s.moments()
+        gth = s.params()
+        assert np.abs(gm - m).max() <= 1e-6 * np.abs(m).max(), step
+        assert np.abs(gv - v).max() <= 1e-6 * np.abs(v).max(), step
+        # each weight moves by about lr per step: compare the moves, relative to lr
+        assert np.abs((gth - theta) - (th - theta)).max() <= 1e-4 * lr, step

@@ -190,3 +190,117 @@ def test_error_head_margin_covers_95_percent_of_gaussian_residuals():
     est = osno.error_head_predict(phi, h, margin)
     cover = float(np.mean(err <= est))
     assert 0.93 < cover < 0.97
+
+
+# ---------------------------------------------------------------------------
+# travel-time-aligned frames
+def test_delay_by_whole_samples_is_a_zero_filled_shift():
+    rng = np.random.default_rng(10)
+    u = rng.standard_normal((3, 40))
+    for n in (0, 1, 7, -5, 39, 45, -45):
+        want = np.zeros_like(u)
+        for t in range(40):
+            if 0 <= t - n < 40:
+                want[:, t] = u[:, t - n]
+        assert np.abs(osno.delay(u, float(n)) - want).max() < 1e-14, n
+
+
+def test_delay_is_exact_for_cubics_away_from_the_edges():
+    t = np.arange(64, dtype=np.float64)
+    coef = (0.3, -1.2, 0.05, -0.002)
+    poly = lambda x: coef[0] + coef[1] * x + coef[2] * x ** 2 + coef[3] * x ** 3
+    for delta in (0.37, -2.81, 5.5, 11.999):
+        got = osno.delay(poly(t), delta)
+        inner = slice(int(math.ceil(delta)) + 3, 64 + int(math.floor(delta)) - 3) if delta > 0 else \
+            slice(3, 64 + int(math.floor(delta)) - 3)
+        assert np.abs(got[inner] - poly(t[inner] - delta)).max() < 1e-9 * np.abs(poly(t)).max(), delta
+    # a quartic is not reproduced: the interpolation is cubic, not higher
+    q = (t / 10.0) ** 4
+    assert np.abs(osno.delay(q, 0.5)[10:50] - ((t[10:50] - 0.5) / 10.0) ** 4).max() > 1e-6
+
+
+def test_delay_transpose_is_the_adjoint():
+    rng = np.random.default_rng(12)
+    u, v = rng.standard_normal((2, 50))
+    for delta in (0.0, 0.25, -3.7, 12.6):
+        lhs = float(np.dot(osno.delay(u, delta), v))
+        rhs = float(np.dot(u, osno.delay_transpose(v, delta)))
+        assert abs(lhs - rhs) < 1e-12 * max(1.0, abs(lhs)), delta
+
+
+def test_straight_ray_times():
+    h = (10.0, 12.5, 8.0)
+    # homogeneous: distance / speed, in any direction, and the same both ways
+    slow = np.full(40, 1 / 2500.0)
+    for a, b in [((3, 4, 30), (10, 2, 5)), ((0, 0, 0), (7, 9, 0)), ((5, 5, 2), (5, 5, 38))]:
+        d = math.sqrt(sum(((a[k] - b[k]) * h[k]) ** 2 for k in range(3)))
+        assert osno.straight_ray_time(a, b, slow, h) == pytest.approx(d / 2500.0, rel=1e-14)
+        assert osno.straight_ray_time(a, b, slow, h) == osno.straight_ray_time(b, a, slow, h)
+    # layered: the oblique ray against a fine quadrature of the slowness along the segment
+    rng = np.random.default_rng(3)
+    slow = 1.0 / rng.uniform(1800, 4200, 40)
+    a, b = np.array([2, 30, 33]), np.array([17, 3, 6])
+    pa, pb = a * np.array(h), b * np.array(h)
+    s = (np.arange(400000) + 0.5) / 400000
+    pts = pa[None, :] + s[:, None] * (pb - pa)[None, :]
+    k = np.floor(pts[:, 2] / h[2] + 0.5).astype(int)       # cell k spans [(k - 1/2) h, (k + 1/2) h)
+    quad = np.mean(slow[k]) * np.linalg.norm(pb - pa)
+    assert osno.straight_ray_time(a, b, slow, h) == pytest.approx(quad, rel=1e-4)
+    # vertical ray: half of each end cell plus the cells between
+    assert osno.straight_ray_time((1, 1, 4), (1, 1, 9), slow, h) == pytest.approx(
+        h[2] * (0.5 * slow[4] + slow[5:9].sum() + 0.5 * slow[9]), rel=1e-14)
+
+
+D_FR = osno.Dims(n_pos=3, n_mt=6, four=(3.0, 7.5), C=4, T=32, K=5, L=2, H=6, O=8, frames=2)
+
+
+def test_gradient_with_aligned_frames_matches_finite_differences():
+    rng = np.random.default_rng(21)
+    d = D_FR
+    theta = init_frames(d, 4) + 0.05 * rng.standard_normal(osno.n_params(d))
+    src = rng.standard_normal((2, 9))
+    shift = rng.uniform(-4.0, 9.0, (2, 2, d.O // 4))
+    y = rng.standard_normal((2, d.O, d.T))
+    g = osno.grad(theta, src, y, d, shift=shift)
+    idx = rng.choice(theta.size, 60, replace=False)
+    idx = np.concatenate([idx, np.arange(theta.size - 2 * d.n_mt * d.O, theta.size, 97)])   # q2b of both frames
+    h = 1e-6
+    for i in idx:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (osno.loss(tp, src, y, d, shift) - osno.loss(tm, src, y, d, shift)) / (2 * h)
+        assert abs(fd - g[i]) < 1e-6 * max(1.0, abs(fd)) + 1e-9, i
+
+
+def test_aligned_frames_delay_each_receiver_by_its_shift():
+    """With the network's trunk fixed, delaying frame f of receiver r by one
+    more sample delays that receiver's frame-f contribution by exactly one
+    sample, and the output stays linear in the moment tensor."""
+    rng = np.random.default_rng(22)
+    d = D_FR
+    theta = init_frames(d, 5) + 0.05 * rng.standard_normal(osno.n_params(d))
+    src = rng.standard_normal((1, 9))
+    shift = rng.uniform(0.0, 3.0, (1, 2, d.O // 4))
+    base = osno.forward(theta, src, d, shift=shift)
+    sh2 = shift.copy()
+    sh2[0, 1, 1] += 1.0                                   # frame S of receiver 1
+    moved = osno.forward(theta, src, d, shift=sh2)
+    one = shift.copy()
+    one[0, 0, :] = 1e6                                    # frame P pushed out of the window
+    s_only = osno.forward(theta, src, d, shift=one)
+    sh3 = one.copy()
+    sh3[0, 1, 1] += 1.0
+    s_moved = osno.forward(theta, src, d, shift=sh3)
+    for o in range(d.O):
+        if o % (d.O // 4) == 1:
+            assert np.abs(s_moved[0, o, 1:] - s_only[0, o, :-1]).max() < 1e-12
+        else:
+            assert np.abs(moved[0, o] - base[0, o]).max() == 0.0
+    m2 = src.copy()
+    m2[0, 3:] *= -2.5
+    assert np.abs(osno.forward(theta, m2, d, shift=shift) + 2.5 * base).max() < 1e-12 * np.abs(base).max()
+
+
+def init_frames(d, seed):
+    return inputs.sno_init_params(d.C, d.K, d.L, d.H, d.frames * d.O, osno.n_lift(d), seed, d.n_mt)
