@@ -292,17 +292,25 @@ def test_explosion_radial_velocity_matches_whole_space_green_function(homogeneou
     checked = 0
     for i, o in enumerate(R["offs"]):
         axes = [a for a in range(3) if o[a] != 0]
-        if len(axes) != 1:
+        if len(axes) != 1 or abs(o[axes[0]]) != 12:     # the 16-cell receivers sit in the PML
             continue
         a = axes[0]
+        win = t < (abs(o[a]) + 0.5) * h / vp + 3.0 / f0
+        anas = []
         for b in range(3):
             dvec = np.array(o, float) + 0.5 * np.eye(3)[b]
             r = np.linalg.norm(dvec) * h
-            ana = physics.explosion_radial_velocity(t, r, m0, vp, rho, f0) * dvec[b] * h / r
-            win = t < r / vp + 3.0 / f0
+            anas.append(physics.explosion_radial_velocity(t, r, m0, vp, rho, f0) * dvec[b] * h / r)
+        axial = np.linalg.norm(anas[a][win])
+        for b in range(3):
             got = out[1 + b][i]
-            tol = 0.02 if b == a else 0.05
-            assert rel(got[win], ana[win]) < tol, (o, b, rel(got[win], ana[win]))
+            # the two off-axis components (half a cell off, about 4.2 % of the
+            # axial one) against 3 % of the axial amplitude: dropping the half
+            # cell (a zero there) would miss by 4.2 %
+            err = np.linalg.norm(got[win] - anas[b][win]) / (np.linalg.norm(anas[b][win]) if b == a else axial)
+            assert err < (0.02 if b == a else 0.03), (o, b, err)
+            if b != a:
+                assert np.linalg.norm(anas[b][win]) > 0.03 * axial
         # the near-field term is not negligible at the axial node
         r = (abs(o[a]) + 0.5 * np.sign(o[a])) * h
         full = physics.explosion_radial_velocity(t, r, m0, vp, rho, f0)
