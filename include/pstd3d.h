@@ -258,9 +258,9 @@ const char *pstd3d_last_error(void);
  * src_idx, amp, t_origin: host arrays [n_ev].  The event lists (72 bytes per
  * event and record segment of up to 12288 samples) go to a device buffer
  * allocated and freed by the call; runs on hip_stream and returns after the
- * stream has finished.  Errors: PSTD_EINVAL (sizes, source index out of
- * range, non-finite value), PSTD_ENOMEM, PSTD_EDEVICE; the message is
- * returned by seis_combine_last_error(). */
+ * stream has finished.  Errors: PSTD_EINVAL (sizes, dt_out / dt_in outside
+ * [2^-20, 2^20], source index out of range, non-finite value), PSTD_ENOMEM,
+ * PSTD_EDEVICE; the message is returned by seis_combine_last_error(). */
 int seis_combine(const float *tr, int n_src, int n_rec, int nt_in, double dt_in, const double t0[4],
                  int n_ev, const int32_t *src_idx, const double *amp, const double *t_origin,
                  int nt_out, double dt_out, float *out, void *hip_stream);

@@ -14,6 +14,14 @@
 // component) misses its samples, so the per-event cost falls on the few
 // waves an event touches.
 //
+// Two kernels share that scheme.  When a whole input trace fits a slot of the
+// staging buffer (nt_in + 4 values, two zeros on each side), k_combine_w
+// stages the rows of several sources between one pair of barriers and clamps
+// each sample's index into its slot (an index outside the trace lands on the
+// two zero pads at either end, so no sample needs a range test).  Longer traces go through
+// k_combine, which stages one source at a time in chunks of STG samples and
+// tests every sample against the chunk.
+//
 // The input position of a sample is u = m (dt_out / dt_in) - (t_origin + t0)/dt_in:
 // for a thread's first sample one fused multiply-add in double from the
 // per-event offset computed on the host, then in 32.32 fixed point, each next
@@ -46,11 +54,12 @@ struct Grp {
     int pad;
 };
 // one event of a segment: amplitude, and per component the input offset
-// (t_origin + t0[c]) / dt_in and the output samples [mlo, mhi) it can touch
+// (t_origin + t0[c]) / dt_in and the output samples [rng[c][0], rng[c][1])
+// it can touch
 struct Ev {
     double amp;
     double be[4];
-    int mlo[4], mhi[4];
+    int rng[4][2];
 };
 
 // Host-side lists of one call: per segment the source groups, per group its
@@ -86,11 +95,11 @@ void make_plan(Plan& p, int n_ev, const int32_t* src_idx, const double* amp, con
             // clamped in double first: the offset may be far outside the record
             const double lo = std::max(0.0, std::floor((E.be[c] - 1.0) / ratio) - 1.0);
             const double hi = std::min((double)nt_out, std::ceil(((double)nt_in + E.be[c]) / ratio) + 2.0);
-            E.mlo[c] = (int)std::min(lo, (double)nt_out);
-            E.mhi[c] = hi > lo ? (int)hi : E.mlo[c];
-            if (E.mhi[c] > E.mlo[c]) {
-                lo_all = std::min(lo_all, (double)E.mlo[c]);
-                hi_all = std::max(hi_all, (double)E.mhi[c]);
+            E.rng[c][0] = (int)std::min(lo, (double)nt_out);
+            E.rng[c][1] = hi > lo ? (int)hi : E.rng[c][0];
+            if (E.rng[c][1] > E.rng[c][0]) {
+                lo_all = std::min(lo_all, (double)E.rng[c][0]);
+                hi_all = std::max(hi_all, (double)E.rng[c][1]);
             }
         }
         first[e] = hi_all > lo_all ? (int)lo_all : 1;
@@ -185,7 +194,8 @@ __global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(8))) void k_
         const Grp G = grp[g];
         for (int e = G.e0; e < G.e1; ++e) {
             const Ev& E = ev[e];
-            if (!active || E.mhi[c] <= m0 || E.mlo[c] >= m0 + SPT) continue;
+            const int lo = E.rng[c][0], hi = E.rng[c][1];
+            if (!active || hi <= m0 || lo >= m0 + SPT) continue;
             const double amp = E.amp;
             // position of this thread's first sample in 32.32 fixed point
             // (from double; each later sample adds ratio exactly in integers,
@@ -228,6 +238,119 @@ __global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(8))) void k_
         if (m0 + k < s1) o[m0 + k] = (float)acc[k];
 }
 
+// Whole-trace staging: a slot holds a source row x[-2 .. nt_in + 1] (zeros
+// outside the trace), nt_in + 4 values, of which each thread loads VPS (so a
+// slot is at most VPS * CT values, VPS = 1, 2 or 4); an item is
+// NSLOT(VPS) = WPT / VPS slots, staged from WPT registers per thread (32 KB
+// of LDS).
+constexpr int WPT = 8;
+// samples whose loads are issued together
+constexpr int QTR = SPT / 3;
+
+__host__ __device__ constexpr int w_slot(int nt_in) { return nt_in + 4; }
+
+template <int VPS>
+__global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(8))) void k_combine_w(
+    const float* __restrict__ tr, int n_rec, int nt_in, double ratio, unsigned long long ratio_fx,
+    const char* __restrict__ plan, long off_grp, long off_ev, int seg_len, int nt_out, float* __restrict__ out)
+{
+    constexpr int NSLOT = WPT / VPS;
+    extern __shared__ float stw[];   // NSLOT slots of w_slot(nt_in) floats
+    const int seg = blockIdx.x;
+    const int r = blockIdx.y;
+    const int c = blockIdx.z;
+    const int tid = threadIdx.x;
+    const int L = w_slot(nt_in);
+    const int s0 = seg * seg_len;
+    const int s1 = min(s0 + seg_len, nt_out);
+    const int m0 = s0 + tid * SPT;
+    const bool active = m0 < s1;
+    const int* __restrict__ seg_ptr = reinterpret_cast<const int*>(plan);
+    const Grp* __restrict__ grp = reinterpret_cast<const Grp*>(plan + off_grp);
+    const Ev* __restrict__ ev = reinterpret_cast<const Ev*>(plan + off_ev);
+    double acc[SPT];
+#pragma unroll
+    for (int k = 0; k < SPT; ++k) acc[k] = 0.0;
+    const int g0 = seg_ptr[seg], g1 = seg_ptr[seg + 1];
+    // Item q stages the rows of groups [g0 + q NSLOT, g0 + (q + 1) NSLOT); the
+    // next item's values are loaded into registers while this one is computed.
+    const int nitems = (g1 - g0 + NSLOT - 1) / NSLOT;
+    const double md = (double)m0;
+    float pre[WPT];
+    auto fetch = [&](int item) {
+        const int gb = g0 + item * NSLOT;
+#pragma unroll
+        for (int sl = 0; sl < NSLOT; ++sl) {
+            const int g = gb + sl;
+            const float* __restrict__ x =
+                g < g1 ? tr + (((long)grp[g].src * 4 + c) * n_rec + r) * nt_in : tr;
+#pragma unroll
+            for (int v = 0; v < VPS; ++v) {
+                const int xi = tid + v * CT - 2;   // slot position tid + v CT holds x[xi]
+                pre[sl * VPS + v] = (g < g1 && xi >= 0 && xi < nt_in) ? x[xi] : 0.0f;
+            }
+        }
+    };
+    if (nitems > 0) fetch(0);
+    for (int item = 0; item < nitems; ++item) {
+        __syncthreads();   // the previous item's readers are done
+#pragma unroll
+        for (int sl = 0; sl < NSLOT; ++sl)
+#pragma unroll
+            for (int v = 0; v < VPS; ++v) {
+                const int k = tid + v * CT;
+                if (k < L) stw[sl * L + k] = pre[sl * VPS + v];
+            }
+        __syncthreads();
+        if (item + 1 < nitems) fetch(item + 1);
+        const int gb = g0 + item * NSLOT;
+        const int ng = min(NSLOT, g1 - gb);
+        for (int gi = 0; gi < ng; ++gi) {
+            const Grp G = grp[gb + gi];
+            const float* __restrict__ x = stw + gi * L;
+            for (int e = G.e0; e < G.e1; ++e) {
+                const Ev& E = ev[e];
+                const int lo = E.rng[c][0], hi = E.rng[c][1];
+                if (!active || hi <= m0 || lo >= m0 + SPT) continue;
+                const double amp = E.amp;
+                // slot index of this thread's first sample (x[i] sits at i + 2)
+                // in 32.32 fixed point
+                const double u0 = fma(md, ratio, 2.0 - E.be[c]);
+                const double fl0 = floor(u0);
+                unsigned long long u = ((unsigned long long)(unsigned)(int)fl0 << 32) |
+                                       (unsigned long long)(unsigned)((u0 - fl0) * 4294967296.0);
+#pragma unroll
+                for (int h = 0; h < SPT; h += QTR) {
+                    int idx[QTR];
+                    float fr[QTR];
+#pragma unroll
+                    for (int k = 0; k < QTR; ++k) {
+                        // clamped into [0, L - 2] as unsigned (a negative index
+                        // becomes L - 2): an index outside the trace reads two
+                        // of the zero pads
+                        idx[k] = (int)min((unsigned)(u >> 32), (unsigned)(L - 2));
+                        fr[k] = (float)(unsigned)u * 2.3283064365386963e-10f;
+                        u += ratio_fx;
+                    }
+                    float x0[QTR], x1[QTR];
+#pragma unroll
+                    for (int k = 0; k < QTR; ++k) {
+                        x0[k] = x[idx[k]];
+                        x1[k] = x[idx[k] + 1];
+                    }
+#pragma unroll
+                    for (int k = 0; k < QTR; ++k)
+                        acc[h + k] = fma(amp, (double)fmaf(fr[k], x1[k] - x0[k], x0[k]), acc[h + k]);
+                }
+            }
+        }
+    }
+    float* __restrict__ o = out + ((long)c * n_rec + r) * nt_out;
+#pragma unroll
+    for (int k = 0; k < SPT; ++k)
+        if (m0 + k < s1) o[m0 + k] = (float)acc[k];
+}
+
 thread_local std::string g_cerr;
 
 int cfail(int code, const std::string& msg)
@@ -243,6 +366,8 @@ int check_args(const float* tr, int n_src, int n_rec, int nt_in, double dt_in, c
     if (n_src < 1 || n_rec < 0 || nt_in < 1 || nt_out < 0 || n_ev < 0 || !(dt_in > 0) || !(dt_out > 0) || !t0 ||
         !std::isfinite(dt_in) || !std::isfinite(dt_out))
         return cfail(PSTD_EINVAL, "seis_combine: bad sizes or sampling intervals");
+    if (!(dt_out / dt_in <= 1048576.0) || !(dt_out / dt_in >= 1.0 / 1048576.0))
+        return cfail(PSTD_EINVAL, "seis_combine: dt_out / dt_in outside [2^-20, 2^20]");
     if (n_rec == 0 || nt_out == 0) return PSTD_OK;
     if (!tr || !out || (n_ev > 0 && (!src_idx || !amp || !t_origin)))
         return cfail(PSTD_EINVAL, "seis_combine: null pointer");
@@ -272,8 +397,23 @@ int launch(const Plan& p, char* dplan, const float* tr, int n_rec, int nt_in, do
     if (ok) {
         const double ratio = dt_out / dt_in;
         const long long ratio_fx = (long long)std::llround(ratio * 4294967296.0);
-        hipLaunchKernelGGL(k_combine, dim3(p.nseg, n_rec, 4), dim3(CT), 0, st, tr, n_rec, nt_in, ratio, ratio_fx,
-                           dplan, (long)p.off_grp, (long)p.off_ev, p.seg_len, nt_out, out);
+        const int L = w_slot(nt_in);
+        const dim3 grid(p.nseg, n_rec, 4);
+        const unsigned long long rfx = (unsigned long long)ratio_fx;
+        const long og = (long)p.off_grp, oe = (long)p.off_ev;
+        if (L <= CT) {
+            hipLaunchKernelGGL(k_combine_w<1>, grid, dim3(CT), (size_t)(WPT / 1) * L * sizeof(float), st, tr, n_rec,
+                               nt_in, ratio, rfx, dplan, og, oe, p.seg_len, nt_out, out);
+        } else if (L <= 2 * CT) {
+            hipLaunchKernelGGL(k_combine_w<2>, grid, dim3(CT), (size_t)(WPT / 2) * L * sizeof(float), st, tr, n_rec,
+                               nt_in, ratio, rfx, dplan, og, oe, p.seg_len, nt_out, out);
+        } else if (L <= 4 * CT) {
+            hipLaunchKernelGGL(k_combine_w<4>, grid, dim3(CT), (size_t)(WPT / 4) * L * sizeof(float), st, tr, n_rec,
+                               nt_in, ratio, rfx, dplan, og, oe, p.seg_len, nt_out, out);
+        } else {
+            hipLaunchKernelGGL(k_combine, dim3(p.nseg, n_rec, 4), dim3(CT), 0, st, tr, n_rec, nt_in, ratio, ratio_fx,
+                               dplan, (long)p.off_grp, (long)p.off_ev, p.seg_len, nt_out, out);
+        }
         ok = hipGetLastError() == hipSuccess;
     }
     const hipError_t se = hipStreamSynchronize(st);

@@ -135,6 +135,27 @@ def test_long_record_in_several_segments(B):
     check(got, ref)
 
 
+@pytest.mark.parametrize("nt_in", [1020, 1021, 2044, 2045, 4092, 4093])
+def test_staging_slot_boundaries(B, nt_in):
+    """Traces whose staging slot (nt_in + 4 values) fills one, two or four
+    values per thread exactly, and one past that (the next slot shape, or the
+    chunked staging beyond 4092 samples); events overlap both trace ends."""
+    import torch
+    rng = np.random.default_rng(nt_in)
+    n_src, n_rec = 11, 2
+    tr = rng.standard_normal((n_src, 4, n_rec, nt_in)).astype(np.float32)
+    t0 = [1e-3, 0.5e-3, 0.5e-3, 0.5e-3]
+    n_ev = 30
+    src = rng.integers(0, n_src, n_ev).astype(np.int32)
+    amp = rng.lognormal(0, 1, n_ev)
+    to = rng.uniform(-1.5 * nt_in * 1e-3, 1.5 * nt_in * 1e-3, n_ev)
+    nt_out, dt_out = 2 * nt_in + 7, 1.1e-3
+    say("combine slot boundary", nt_in)
+    got = B.seis_combine(torch.from_numpy(tr).cuda(), t0, src, amp, to, nt_out, 1e-3, dt_out).cpu().numpy()
+    ref = oracle.combine(tr, t0, src, amp, to, nt_out, 1e-3, dt_out)
+    check(got, ref)
+
+
 def test_one_sample_traces_and_far_events(B):
     """nt_in = 1 (a trace that is one spike), events far outside the record
     (no sample touched), and repeated events of one source."""
@@ -158,3 +179,6 @@ def test_invalid_arguments_are_rejected(B):
     with pytest.raises(B.PstdError) as e:
         B.seis_combine(tr, [0.0] * 4, [0], [np.nan], [0.0], 20, 1e-3, 1e-3)
     assert e.value.code == B.PSTD_EINVAL
+    with pytest.raises(B.PstdError) as e:
+        B.seis_combine(tr, [0.0] * 4, [0], [1.0], [0.0], 20, 1e-3, 1e-3 * 2.0 ** 21)
+    assert e.value.code == B.PSTD_EINVAL and "dt_out / dt_in" in str(e.value)
