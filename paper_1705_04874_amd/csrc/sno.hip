@@ -5,9 +5,13 @@
 //   C[b](m, n) = alpha * sum_kb sum_k A[b, kb](m, k) B[b, kb](k, n) + beta * C[b](m, n) + bias(m)
 // whose operands are addressed through arbitrary element strides (so
 // transposes, the per-mode complex mixing and the weight gradients summed over
-// the batch are all the same kernel).  A 256-thread block computes a 64 x 64
-// tile; each K step stages A (64 x 16) and B (16 x 64) in LDS as BF16 with k
-// contiguous and each wave issues 2 x 2 MFMA 16x16x16 ops.
+// the batch are all the same kernel).  Operands whose k or m/n dimension is
+// contiguous (and 16-byte aligned) go through k_gemm_t: a 256-thread block
+// computes a BM x BN tile (64 or 128 each), stages 32-deep slices of A and B
+// in LDS as BF16 with k contiguous from float4 loads (the next slice's loads
+// in flight while the current one is multiplied), and each wave issues
+// (BM/32) x (BN/32) MFMA 16x16x32 ops per slice.  Other strides use k_gemm
+// (64 x 64 tiles, 16-deep slices, element loads).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -22,6 +26,7 @@
 namespace {
 
 typedef short bf4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 thread_local std::string g_serr;
@@ -59,6 +64,8 @@ struct GemmP {
     float alpha, beta;
     const float* bias;   // per row, and per batch entry with stride sBiasb
     long sBiasb;
+    int nsplit;          // > 1: blockIdx.z splits the (kb, k) slices of one product (batch 1);
+    float* part;         // split z writes its partial sum to part + z M N (row-major)
 };
 
 __global__ __launch_bounds__(256) void k_gemm(GemmP p)
@@ -123,11 +130,236 @@ __global__ __launch_bounds__(256) void k_gemm(GemmP p)
             }
 }
 
+// Tiled kernel.  AK: A is k-contiguous (sAk == 1), else m-contiguous
+// (sAm == 1); BK: B is k-contiguous (sBk == 1), else n-contiguous (sBn == 1).
+// Every float4 the kernel loads is either wholly inside or wholly outside the
+// operand (the contiguous extent is a multiple of 4 and the other strides are
+// multiples of 4), so the out-of-range ones are zeros.
+constexpr int GK = 32;          // k per slice
+constexpr int GLD = GK + 8;     // LDS row length in BF16 (80 bytes: conflict-free 16-byte reads)
+
+// One operand's slice: rows [r0, r0 + R) of the m (or n) axis, k [k0, k0 + 32).
+// Sub-block sb of 4 rows x 4 k is loaded as 4 float4 and stored as 4 rows of
+// 4 BF16 (8 bytes each) into S[row][k].
+template <int R, bool KC>
+struct Slice {
+    static constexpr int NSB = R * GK / 16;          // sub-blocks
+    static constexpr int PER = (NSB + 255) / 256;    // per thread
+    float4 v[PER][4];
+    __device__ __forceinline__ void load(const float* __restrict__ X, long sR, long sK, int nR, int nK, int r0, int k0)
+    {
+        const int t = threadIdx.x;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int sb = t + q * 256;
+            // k-contiguous: 8 neighbouring threads cover one row's 32 k;
+            // row-contiguous: R / 4 neighbouring threads cover one k's R rows
+            const int rb = KC ? sb / (GK / 4) : sb % (R / 4);
+            const int kb = KC ? sb % (GK / 4) : sb / (R / 4);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = r0 + rb * 4 + (KC ? i : 0), k = k0 + kb * 4 + (KC ? 0 : i);
+                const bool in = (NSB % 256 == 0 || sb < NSB) && r < nR && k < nK;
+                v[q][i] = in ? *reinterpret_cast<const float4*>(X + (long)r * sR + (long)k * sK)
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+        }
+    }
+    __device__ __forceinline__ void store(__bf16 (*S)[GLD]) const
+    {
+        const int t = threadIdx.x;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int sb = t + q * 256;
+            if (NSB % 256 != 0 && sb >= NSB) continue;
+            const int rb = KC ? sb / (GK / 4) : sb % (R / 4);
+            const int kb = KC ? sb % (GK / 4) : sb / (R / 4);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                // row rb * 4 + i, k kb * 4 .. kb * 4 + 3
+                float a, b, c, d;
+                if (KC) {
+                    a = v[q][i].x; b = v[q][i].y; c = v[q][i].z; d = v[q][i].w;
+                } else {
+                    const float* e0 = reinterpret_cast<const float*>(&v[q][0]);
+                    const float* e1 = reinterpret_cast<const float*>(&v[q][1]);
+                    const float* e2 = reinterpret_cast<const float*>(&v[q][2]);
+                    const float* e3 = reinterpret_cast<const float*>(&v[q][3]);
+                    a = e0[i]; b = e1[i]; c = e2[i]; d = e3[i];
+                }
+                typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
+                bf4v w = {(__bf16)a, (__bf16)b, (__bf16)c, (__bf16)d};
+                *reinterpret_cast<bf4v*>(&S[rb * 4 + i][kb * 4]) = w;
+            }
+        }
+    }
+};
+
+template <int BM, int BN, bool AK, bool BK>
+__global__ __launch_bounds__(256) void k_gemm_t(GemmP p)
+{
+    constexpr int TM = BM / 32, TN = BN / 32;     // 16 x 16 tiles per wave (2 x 2 waves)
+    __shared__ __attribute__((aligned(16))) __bf16 As[BM][GLD];
+    __shared__ __attribute__((aligned(16))) __bf16 Bs[BN][GLD];
+    const int b = blockIdx.z;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int wm = (w >> 1) * (BM / 2), wn = (w & 1) * (BN / 2);
+    f4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    Slice<BM, AK> sa;
+    Slice<BN, BK> sb;
+    const int nks = (p.K + GK - 1) / GK;
+    // slices (kb, k0) of this block: all of them, or with a split its share
+    int s_lo = 0, s_hi = p.KB * nks;
+    const bool split = p.nsplit > 1;
+    const int ab = split ? 0 : b;
+    if (split) {
+        const long ns = s_hi;
+        s_lo = (int)(ns * b / p.nsplit);
+        s_hi = (int)(ns * (b + 1) / p.nsplit);
+    }
+    // A as rows m: stride along the rows sAm, along k sAk; B as rows n: sBn, sBk
+    auto load = [&](int s) {
+        const int kb = s / nks, k0 = (s - kb * nks) * GK;
+        sa.load(p.A + ab * p.sAb + kb * p.sAkb, p.sAm, p.sAk, p.M, p.K, m0, k0);
+        sb.load(p.B + ab * p.sBb + kb * p.sBkb, p.sBn, p.sBk, p.N, p.K, n0, k0);
+    };
+    if (s_lo < s_hi) load(s_lo);
+    for (int s = s_lo; s < s_hi; ++s) {
+        sa.store(As);
+        sb.store(Bs);
+        __syncthreads();
+        if (s + 1 < s_hi) load(s + 1);
+        bf8 av[TM], bv[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) av[i] = *reinterpret_cast<const bf8*>(&As[wm + i * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+        for (int j = 0; j < TN; ++j) bv[j] = *reinterpret_cast<const bf8*>(&Bs[wn + j * 16 + (lane & 15)][8 * (lane >> 4)]);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    if (split) {
+        float* __restrict__ P = p.part + (long)b * p.M * p.N;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int row = m0 + wm + i * 16 + 4 * (lane >> 4) + q;
+                    const int col = n0 + wn + j * 16 + (lane & 15);
+                    if (row < p.M && col < p.N) P[(long)row * p.N + col] = acc[i][j][q];
+                }
+        return;
+    }
+    float* __restrict__ C = p.C + b * p.sCb;
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = m0 + wm + i * 16 + 4 * (lane >> 4) + q;
+                const int col = n0 + wn + j * 16 + (lane & 15);
+                if (row < p.M && col < p.N) {
+                    float* c = C + (long)row * p.sCm + (long)col * p.sCn;
+                    float v = p.alpha * acc[i][j][q];
+                    if (p.beta != 0.f) v += p.beta * (*c);
+                    if (p.bias) v += p.bias[b * p.sBiasb + row];
+                    *c = v;
+                }
+            }
+}
+
+// C = alpha * (sum over the splits of the partial products, in split order)
+// + beta * C + bias
+__global__ __launch_bounds__(256) void k_split_sum(GemmP p)
+{
+    const long n = (long)p.M * p.N;
+    for (long e = blockIdx.x * 256L + threadIdx.x; e < n; e += (long)gridDim.x * 256) {
+        const int row = (int)(e / p.N), col = (int)(e - (long)row * p.N);
+        float acc = 0.f;
+        for (int z = 0; z < p.nsplit; ++z) acc += p.part[(long)z * n + e];
+        float* c = p.C + (long)row * p.sCm + (long)col * p.sCn;
+        float v = p.alpha * acc;
+        if (p.beta != 0.f) v += p.beta * (*c);
+        if (p.bias) v += p.bias[row];
+        *c = v;
+    }
+}
+
+// An operand suits the tiled kernel when one of its two dimensions is
+// contiguous with an extent that is a multiple of 4 and every other stride
+// and the base are 16-byte multiples.
+bool tiled_ok(const float* X, long sR, long sK, long sB, long sKB, int nR, int nK, bool& kc)
+{
+    if ((reinterpret_cast<uintptr_t>(X) & 15) || sB % 4 || sKB % 4) return false;
+    if (sK == 1 && sR % 4 == 0 && nK % 4 == 0) {
+        kc = true;
+        return true;
+    }
+    if (sR == 1 && sK % 4 == 0 && nR % 4 == 0) {
+        kc = false;
+        return true;
+    }
+    return false;
+}
+
+template <int BM, int BN>
+void launch_tiled(hipStream_t st, const GemmP& p, int batch, bool ak, bool bk)
+{
+    const dim3 grid((p.N + BN - 1) / BN, (p.M + BM - 1) / BM, batch);
+    if (ak && bk) hipLaunchKernelGGL((k_gemm_t<BM, BN, true, true>), grid, dim3(256), 0, st, p);
+    else if (ak) hipLaunchKernelGGL((k_gemm_t<BM, BN, true, false>), grid, dim3(256), 0, st, p);
+    else if (bk) hipLaunchKernelGGL((k_gemm_t<BM, BN, false, true>), grid, dim3(256), 0, st, p);
+    else hipLaunchKernelGGL((k_gemm_t<BM, BN, false, false>), grid, dim3(256), 0, st, p);
+}
+
+// ws (ws_floats floats of device memory): where a product of one batch entry
+// summed over many kb would leave most compute units idle, its slices are
+// split over blocks that write partial sums there, added up in a second pass.
 void gemm(hipStream_t st, int batch, int M, int N, int K, int KB, const float* A, long sAm, long sAk, long sAb,
           long sAkb, const float* B, long sBk, long sBn, long sBb, long sBkb, float* C, long sCm, long sCn, long sCb,
-          float alpha = 1.f, float beta = 0.f, const float* bias = nullptr, long sBiasb = 0)
+          float alpha = 1.f, float beta = 0.f, const float* bias = nullptr, long sBiasb = 0, float* ws = nullptr,
+          long ws_floats = 0)
 {
-    GemmP p{M, N, K, KB, A, sAm, sAk, sAb, sAkb, B, sBk, sBn, sBb, sBkb, C, sCm, sCn, sCb, alpha, beta, bias, sBiasb};
+    GemmP p{M, N, K, KB, A, sAm, sAk, sAb, sAkb, B, sBk, sBn, sBb, sBkb, C, sCm, sCn, sCb, alpha, beta, bias, sBiasb,
+            1, nullptr};
+    bool ak = false, bk = false;
+    if (M >= 32 && N >= 32 && K >= 16 && tiled_ok(A, sAm, sAk, sAb, sAkb, M, K, ak) &&
+        tiled_ok(B, sBn, sBk, sBb, sBkb, N, K, bk)) {
+        const long tiles = (long)((N + 63) / 64) * ((M + 63) / 64);
+        const long slices = (long)KB * ((K + GK - 1) / GK);
+        if (batch == 1 && ws && tiles < 128 && slices >= 32) {
+            // at least 8 slices per split, about 512 blocks, within the workspace
+            long ns = std::min<long>(std::min<long>(slices / 8, (512 + tiles - 1) / tiles), 256);
+            ns = std::min<long>(ns, ws_floats / ((long)M * N));
+            if (ns >= 2) {
+                p.nsplit = (int)ns;
+                p.part = ws;
+                launch_tiled<64, 64>(st, p, (int)ns, ak, bk);
+                const long n = (long)M * N;
+                hipLaunchKernelGGL(k_split_sum, dim3((unsigned)std::min<long>((n + 255) / 256, 2048)), dim3(256), 0,
+                                   st, p);
+                return;
+            }
+        }
+        // 128-wide tiles where both sides fill them and the grid still has a
+        // block per compute unit
+        const long big = (long)((N + 127) / 128) * ((M + 127) / 128) * batch;
+        if (M >= 128 && N >= 128 && big >= 256) launch_tiled<128, 128>(st, p, batch, ak, bk);
+        else if (M >= 128 && (long)((N + 63) / 64) * ((M + 127) / 128) * batch >= 256)
+            launch_tiled<128, 64>(st, p, batch, ak, bk);
+        else launch_tiled<64, 64>(st, p, batch, ak, bk);
+        return;
+    }
     hipLaunchKernelGGL(k_gemm, dim3((N + 63) / 64, (M + 63) / 64, batch), dim3(256), 0, st, p);
 }
 
@@ -438,26 +670,31 @@ __global__ void k_scale_out(float* __restrict__ Y, long n, int O, int T, int n_r
     }
 }
 
-// per-component sums of squares: ss[c] += sum over samples, receivers, t of Y^2
+// per-component sums of squares of Y over samples, receivers and t: block
+// (c, j) of SQ_BLOCKS per component writes its share (sample rows j,
+// j + SQ_BLOCKS, ...) to ss[c * SQ_BLOCKS + j]; the host adds the shares
+constexpr int SQ_BLOCKS = 256;
 __global__ __launch_bounds__(256) void k_comp_sumsq(const float* __restrict__ Y, int n, int n_rec, int T,
                                                     double* __restrict__ ss)
 {
     __shared__ double red[256];
-    const int c = blockIdx.x;
+    const int c = blockIdx.x, j = blockIdx.y;
     double s = 0.0;
-    const long per = (long)n_rec * T;
-    for (int b = 0; b < n; ++b)
-        for (long i = threadIdx.x; i < per; i += 256) {
-            const double v = Y[((long)b * 4 + c) * per + i];
+    for (long rr = j; rr < (long)n * n_rec; rr += SQ_BLOCKS) {
+        const long b = rr / n_rec, r = rr - b * n_rec;
+        const float* __restrict__ y = Y + ((b * 4 + c) * n_rec + r) * T;
+        for (int i = threadIdx.x; i < T; i += 256) {
+            const double v = y[i];
             s += v * v;
         }
+    }
     red[threadIdx.x] = s;
     __syncthreads();
     for (int h = 128; h > 0; h >>= 1) {
         if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) ss[c] = red[0];
+    if (threadIdx.x == 0) ss[c * SQ_BLOCKS + j] = red[0];
 }
 
 // per sample: max over the 4 components of ||Yp - Yt|| / ||Yt|| (any units)
@@ -569,6 +806,9 @@ struct sno {
           *part = nullptr, *lossd = nullptr, *phi = nullptr, *Xb = nullptr, *Yb = nullptr, *Y6 = nullptr,
           *dY6 = nullptr, *shift = nullptr, *Qm = nullptr, *dQm = nullptr, *bm = nullptr, *dbm = nullptr;
     int* idxd = nullptr;
+    // partial sums of the split weight-gradient products
+    static constexpr long kws_n = 4L << 20;
+    float* kws = nullptr;
 
     float* V(int l) { return l < cfg.L ? Vb + (long)l * bmax * cfg.C * cfg.T : Z + (long)(cfg.L - 1) * bmax * cfg.C * cfg.T; }
     float* Zl(int l) { return Z + (long)l * bmax * cfg.C * cfg.T; }
@@ -577,11 +817,11 @@ struct sno {
     void free_ws()
     {
         for (float* p : {A, Vb, Vh, Z, Uh, Hp, Hq, Y, X0, X1, X2, dH, dUh, dVh, part, lossd, phi, Xb, Yb, Y6, dY6, shift,
-                         Qm, dQm, bm, dbm})
+                         Qm, dQm, bm, dbm, kws})
             (void)hipFree(p);
         (void)hipFree(idxd);
         A = Vb = Vh = Z = Uh = Hp = Hq = Y = X0 = X1 = X2 = dH = dUh = dVh = part = lossd = phi = Xb = Yb = Y6 = dY6 =
-            shift = Qm = dQm = bm = dbm = nullptr;
+            shift = Qm = dQm = bm = dbm = kws = nullptr;
         idxd = nullptr;
         bmax = 0;
     }
@@ -607,7 +847,7 @@ struct sno {
             al(&Y, (long)B * O * T) || al(&X0, (long)B * std::max(C, (long)O) * T) || al(&X1, (long)B * C * T) ||
             al(&X2, (long)B * C * T) || al(&dH, (long)B * H * T) || al(&dUh, (long)B * C * K2) ||
             al(&dVh, (long)B * C * K2) || al(&part, 4096) || al(&lossd, 4) || al(&phi, (long)B * (C + 7)) ||
-            al(&Xb, (long)B * 9) || al(&Yb, (long)B * O * T) || hipMalloc(&idxd, B * sizeof(int)))
+            al(&Xb, (long)B * 9) || al(&Yb, (long)B * O * T) || al(&kws, kws_n) || hipMalloc(&idxd, B * sizeof(int)))
             return sfail(PSTD_ENOMEM, "surrogate workspace");
         bmax = B;
         return PSTD_OK;
@@ -758,7 +998,7 @@ void backward(sno* s, hipStream_t st, const float* X, const float* Yt, int B)
                        (int)FO, (int)O, (int)H, g + s->off_Q2, g + s->off_q2b);
     gemm(st, B, H, T, FO, 1, s->Qm, 1, H, FO * H, 0, dYf, T, 1, FO * T, 0, s->dH, T, 1, H * T);
     hipLaunchKernelGGL(k_gelu_bwd, dim3(grid_for(B * H * T)), dim3(256), 0, st, s->dH, s->Hp, s->dH, (long)B * H * T);
-    gemm(st, 1, H, C, T, B, s->dH, T, 1, 0, H * T, s->V(c.L), 1, T, 0, C * T, g + s->off_Q1, C, 1, 0);
+    gemm(st, 1, H, C, T, B, s->dH, T, 1, 0, H * T, s->V(c.L), 1, T, 0, C * T, g + s->off_Q1, C, 1, 0, 1.f, 0.f, nullptr, 0, s->kws, s->kws_n);
     hipLaunchKernelGGL(k_rowsum, dim3(H), dim3(256), 0, st, s->dH, B, (int)H, (int)T, g + s->off_q1b);
     float* bufs[3] = {s->X1, s->X2, s->X0};
     float* dV = bufs[0];
@@ -777,7 +1017,7 @@ void backward(sno* s, hipStream_t st, const float* X, const float* Yt, int B)
         float* dVn = dZ == dV ? other[0] : other[1];
         float* V = s->V(l);
         float* Vh = s->Vhl(l);
-        gemm(st, 1, C, C, T, B, dZ, T, 1, 0, C * T, V, 1, T, 0, C * T, g + s->off_W[l], C, 1, 0);
+        gemm(st, 1, C, C, T, B, dZ, T, 1, 0, C * T, V, 1, T, 0, C * T, g + s->off_W[l], C, 1, 0, 1.f, 0.f, nullptr, 0, s->kws, s->kws_n);
         hipLaunchKernelGGL(k_rowsum, dim3(C), dim3(256), 0, st, dZ, B, (int)C, (int)T, g + s->off_b[l]);
         // dUh = dZ G^T
         gemm(st, B, C, K2, T, 1, dZ, T, 1, C * T, 0, s->G, 1, T, 0, 0, s->dUh, K2, 1, C * K2);
@@ -800,7 +1040,7 @@ void backward(sno* s, hipStream_t st, const float* X, const float* Yt, int B)
         dV = dVn;
     }
     const long NA = s->NA;
-    gemm(st, 1, C, NA, T, B, dV, T, 1, 0, C * T, s->A, 1, T, 0, NA * T, g + s->off_P, NA, 1, 0);
+    gemm(st, 1, C, NA, T, B, dV, T, 1, 0, C * T, s->A, 1, T, 0, NA * T, g + s->off_P, NA, 1, 0, 1.f, 0.f, nullptr, 0, s->kws, s->kws_n);
     hipLaunchKernelGGL(k_rowsum, dim3(C), dim3(256), 0, st, dV, B, (int)C, (int)T, g + s->off_pb);
 }
 
@@ -997,14 +1237,16 @@ int sno_train(sno* s, const float* X, const float* Y, int n, const sno_train_cfg
     if (rc) return rc;
     // output normalisation: per-component RMS over the fitting samples
     double* ss = nullptr;
-    S_TRY(hipMalloc(&ss, 4 * sizeof(double)));
-    hipLaunchKernelGGL(k_comp_sumsq, dim3(4), dim3(256), 0, st, Y, n_fit, c.n_rec, c.T, ss);
-    double hs[4];
-    S_TRY(hipMemcpyAsync(hs, ss, sizeof(hs), hipMemcpyDeviceToHost, st));
+    S_TRY(hipMalloc(&ss, 4 * SQ_BLOCKS * sizeof(double)));
+    hipLaunchKernelGGL(k_comp_sumsq, dim3(4, SQ_BLOCKS), dim3(256), 0, st, Y, n_fit, c.n_rec, c.T, ss);
+    std::vector<double> hss(4 * SQ_BLOCKS);
+    S_TRY(hipMemcpyAsync(hss.data(), ss, hss.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     S_TRY(hipStreamSynchronize(st));
     (void)hipFree(ss);
     for (int k = 0; k < 4; ++k) {
-        const double rms = std::sqrt(hs[k] / ((double)n_fit * c.n_rec * c.T));
+        double sk = 0.0;
+        for (int j = 0; j < SQ_BLOCKS; ++j) sk += hss[k * SQ_BLOCKS + j];
+        const double rms = std::sqrt(sk / ((double)n_fit * c.n_rec * c.T));
         s->scale[k] = rms > 0 ? (float)rms : 1.f;
     }
     S_TRY(hipMemcpyAsync(s->dscale, s->scale, 16, hipMemcpyHostToDevice, st));

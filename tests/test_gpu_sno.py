@@ -181,23 +181,33 @@ def test_predict_or_solve_rejects_a_solver_with_other_receivers(B):
     assert (Y == 7.0).all()   # nothing was written
 
 
+# the fixed tolerance of the blend test (relative L2 per seismogram)
+TRAINED_TOL = 0.15
+
+
 def test_trained_network_gains_over_the_solver_alone(B):
-    """What the trained network adds to the solver: on a cluster of nearby
-    sources it predicts held-out traces far better than the same network
-    untrained, its error head accepts part of them at a tolerance, and the
-    blend (accepted predictions plus solver runs for the rest) is faster than
-    the solver alone while every rejected sample is the solver's own answer."""
+    """What the trained network adds to the solver, on a cluster of nearby
+    sources with travel-time aligned frames: it predicts held-out traces far
+    better than the same network untrained.  Its error head is a one-sided 95 %
+    bound of the log error fitted on a calibration split, so it is checked
+    statistically: it ranks the held-out errors (rank correlation >= 0.4), at
+    least 80 % of the held-out errors lie below their estimates, and at a fixed
+    tolerance it accepts part of the samples with at most a quarter of them
+    above the tolerance and none above twice it.  The blend (accepted
+    predictions plus solver runs for the rest) is faster than the solver
+    alone, and every rejected sample is the solver's own answer."""
     import time
 
     import torch
+    from scipy.stats import spearmanr
     from paper_1705_04874_amd import inputs
-    shape = (48, 48, 48)
     m = inputs.layered(48, 48, 48, water_cells=8, seed=11)
     dt, decim, T = 0.8e-3, 2, 256
     rec = inputs.receiver_line_x(12, 36, 24, 8)              # 24 receivers on the seabed
+    n_rec = rec.shape[0]
     solver = B.Solver(m.vp, m.vs, m.rho, (10.0, 10.0, 10.0), dt, pml=8, rec=rec)
     rng = np.random.default_rng(12)
-    n_tr, n_te = 96, 32
+    n_tr, n_te = 384, 32
     ctr = np.array([24.0, 24.0, 30.0])
     pos = np.floor(inputs.latin_hypercube(n_tr + n_te, ctr - 1.5, ctr + 1.5, rng)).astype(np.int32)
     mts = np.stack([inputs.dc_plus_iso(rng, inputs.DV_UNIT_MOMENT) for _ in range(n_tr + n_te)])
@@ -205,9 +215,14 @@ def test_trained_network_gains_over_the_solver_alone(B):
     solver.set_sources(np.arange(n_tr + n_te + 1, dtype=np.int32), pos, mts, np.repeat(wav[None], n_tr + n_te, 0))
     Y = B.decimate(solver.run(decim * T), decim)
     X = torch.tensor(np.concatenate([pos, mts], axis=1), dtype=torch.float32, device="cuda")
-    d = osno.Dims(four=inputs.sno_fourier_cycles(16, 2.0, 40.0), C=32, T=T, K=8, L=2, H=64, O=4 * rec.shape[0])
-    s = B.Surrogate(rec.shape[0], T, d.C, d.K, d.L, d.H, list(ctr) + [0.0] * 6, [1.5] * 3 + [1000.0] * 6,
-                    init(d, 13).astype(np.float32), four_cycles=d.four)
+    d = osno.Dims(four=inputs.sno_fourier_cycles(16, 2.0, 40.0), pos_mod=True, C=64, T=T, K=8, L=4, H=512,
+                  O=4 * n_rec, frames=2)
+    slow_p, slow_s = inputs.depth_slowness(m)
+    t_ref = inputs.straight_ray_reference_times(slow_p, slow_s, ctr.astype(int), rec[n_rec // 2], (10.0,) * 3)
+    fr = dict(rec_ijk=rec, slow_p=slow_p, slow_s=slow_s, h=(10.0,) * 3, dt=decim * dt, t_ref=t_ref)
+    theta = inputs.sno_init_params(d.C, d.K, d.L, d.H, 2 * 4 * n_rec, osno.n_lift(d), 13).astype(np.float32)
+    s = B.Surrogate(n_rec, T, d.C, d.K, d.L, d.H, list(ctr) + [0.0] * 6, [1.5] * 3 + [1000.0] * 6, theta,
+                    four_cycles=d.four, pos_mod=True, frames=fr)
     yt = Y[n_tr:].cpu().numpy().astype(np.float64)
 
     def err(Yp):
@@ -216,15 +231,24 @@ def test_trained_network_gains_over_the_solver_alone(B):
 
     s.train(X[:n_tr], Y[:n_tr], 1, 16, 1e-30, seed=1, n_calib=0)
     e0 = err(s.predict(X[n_tr:])[0])
-    curve = s.train(X[:n_tr], Y[:n_tr], 300, 16, 2e-3, seed=1, n_calib=24)
+    curve = s.train(X[:n_tr], Y[:n_tr], 300, 16, 1e-3, seed=1, n_calib=n_tr // 4)
     Yp, est = s.predict(X[n_tr:])
     e1 = err(Yp)
     est = est.cpu().numpy()
     say("untrained median", np.median(e0), "trained median", np.median(e1), "loss", curve[0], curve[-1])
     assert np.median(e1) < 0.5 * np.median(e0)
-    tol = float(np.quantile(est, 0.5))                       # a tolerance the head accepts half the samples at
+    rho = float(spearmanr(est, e1).correlation)
+    cover = float((e1 <= est).mean())
+    tol = TRAINED_TOL
     acc = est <= tol
+    false_acc = int((acc & (e1 > tol)).sum())
+    say("error head: spearman", rho, "coverage", cover, "tol", tol, "accepted", int(acc.sum()), "of", acc.size,
+        "above tol", false_acc, "worst accepted true error", float(e1[acc].max()) if acc.any() else None)
+    assert rho >= 0.4
+    assert cover >= 0.8
     assert acc.any() and (~acc).any()
+    assert false_acc <= 0.25 * acc.sum()
+    assert e1[acc].max() <= 2 * tol
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     Yb, est_b, used = s.predict_or_solve(solver, X[n_tr:], pos[n_tr:], mts[n_tr:], wav, decim, tol, max_batch=32)
@@ -245,7 +269,8 @@ def test_trained_network_gains_over_the_solver_alone(B):
     np.testing.assert_array_equal(yb[rej], direct.cpu().numpy())
     # the solver alone would answer all n_te samples: about n_te / rej.size times t_rej
     t_solver_all = t_rej * n_te / rej.size
-    say("blend", t_blend, "solver alone (scaled)", t_solver_all, "accepted", int(acc.sum()))
+    say(f"seismograms/s (accepted at {tol:.0%} estimated error): blend {n_te / t_blend:.1f}, "
+        f"solver alone {n_te / t_solver_all:.1f}")
     assert t_blend < t_solver_all
 
 
