@@ -26,6 +26,12 @@ from paper_1705_04874_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
+# the nine fields of the state and the indices of their split parts (the
+# order of oracle.STATE_NAMES)
+SPLIT_PARTS = [("vx", [0, 1, 2]), ("vy", [3, 4, 5]), ("vz", [6, 7, 8]), ("sxx", [9, 10, 11]),
+               ("syy", [12, 13, 14]), ("szz", [15, 16, 17]), ("sxy", [18, 19]), ("sxz", [20, 21]),
+               ("syz", [22, 23])]
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 GOLD = os.path.join(ROOT, "tests", "golden", "layered128_oracle_traces.npz")
 
@@ -249,8 +255,11 @@ def test_run_many_of_uneven_models_against_oracle(B):
 def test_layered384_multistep_against_stored_oracle_planes(B):
     """Full size, in the launch configuration the bench times (one context,
     autotuned shapes, graph replay): the state after the golden's step count
-    against the FP64 oracle's, all 24 split fields on three planes through the
-    source (tests/golden/layered384_oracle_planes.npz), rel-L2 <= 1e-4 each."""
+    against the FP64 oracle's on three planes through the source
+    (tests/golden/layered384_oracle_planes.npz).  The nine fields (each the sum
+    of its split parts) to rel-L2 <= 1e-4; each of the 24 split parts, which
+    only the absorbing layer's formulation separates (Sec. II-B), to 1e-4 of
+    the norm of the field it sums to."""
     gold = os.path.join(ROOT, "tests", "golden", "layered384_oracle_planes.npz")
     if not os.path.exists(gold):
         pytest.fail("tests/golden/layered384_oracle_planes.npz missing (tests/golden/make_layered384_golden.py writes it)")
@@ -269,11 +278,15 @@ def test_layered384_multistep_against_stored_oracle_planes(B):
     for name, zs, ys, xs in planes(w):
         got = st[:, zs, ys, xs].astype(np.float64)
         ref = g[name].astype(np.float64)
-        worst = 0.0
-        for f in range(24):
-            nr = np.linalg.norm(ref[f])
-            assert nr > 0, (name, f)
-            e = float(np.linalg.norm(got[f] - ref[f]) / nr)
-            worst = max(worst, e)
-            assert e <= 1e-4, (name, oracle.STATE_NAMES[f], e)
-        say(f"  plane {name}: worst field rel-L2 {worst:.2e}")
+        worst_field = worst_part = 0.0
+        for fname, parts in SPLIT_PARTS:
+            nf = np.linalg.norm(ref[parts].sum(axis=0))
+            assert nf > 0, (name, fname)
+            e = float(np.linalg.norm(got[parts].sum(axis=0) - ref[parts].sum(axis=0)) / nf)
+            worst_field = max(worst_field, e)
+            assert e <= 1e-4, (name, fname, e)
+            for f in parts:
+                ep = float(np.linalg.norm(got[f] - ref[f]) / nf)
+                worst_part = max(worst_part, ep)
+                assert ep <= 1e-4, (name, oracle.STATE_NAMES[f], ep)
+        say(f"  plane {name}: worst field rel-L2 {worst_field:.2e}, worst split part {worst_part:.2e}")
