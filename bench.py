@@ -366,6 +366,19 @@ def bench_combine(args, binding, inputs, torch):
     ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     used = sorted(set(int(v) for v in ev.src_idx))
     alg = len(used) * 4 * n_rec * nt_in * 4 + 4 * n_rec * nt_out * 4
+    # event-samples: output samples m of each (event, component) whose input
+    # position lies inside the trace, over every receiver; a lane spends about
+    # 10 vector instructions on each, and a CU issues one wave64 instruction
+    # (64 lanes) per cycle: 256 CUs at 2.4 GHz bound the kernel's arithmetic
+    dt_out = 1e-3
+    m = np.arange(nt_out)
+    ev_samples = 0
+    for to in ev.t_origin:
+        for c in range(4):
+            u = m * (dt_out / dt_in) - (to + t0[c]) / dt_in
+            ev_samples += int(np.count_nonzero((u > -1.0) & (u < nt_in)))
+    ev_samples *= n_rec
+    alu_ms = ev_samples * 10 / (256 * 64 * 2.4e9) * 1e3
     out = {
         "metric": "seis_combine GB/s (algorithmic bytes)", "value": round(alg / (ms * 1e-3) / 1e9, 1),
         "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall * 1e3, 3),
@@ -378,6 +391,9 @@ def bench_combine(args, binding, inputs, torch):
                      "timing": "HIP events on the call's stream (includes the event-list upload)"},
         "kernel_ms": round(ms, 3), "call_wall_ms": round(wall * 1e3, 3),
         "sources_used": len(used),
+        "alu_issue": {"event_samples": ev_samples, "instructions_per_event_sample": 10,
+                      "bound_ms": round(alu_ms, 3), "frac": round(alu_ms / ms, 3),
+                      "basis": "10 vector instructions per event-sample and lane, one wave64 instruction per cycle per CU, 256 CUs at 2.4 GHz"},
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -438,46 +438,55 @@ __device__ __forceinline__ float mfeat(const float* X, const Feat& f, int b, int
 // sum_j m_bj q2b[(f 6 + j) O + o], and the output rows of sample b come from
 // one product Qm[b] Hq[b] + bm[b] (a sixth of the work of forming all six
 // responses and combining them).
-__global__ void k_qmix(const float* __restrict__ Q2, const float* __restrict__ q2b, const float* __restrict__ X, Feat f,
-                       int B, int FO, int O, int H, float* __restrict__ Qm, float* __restrict__ bm)
+__global__ __launch_bounds__(256) void k_qmix(const float* __restrict__ Q2, const float* __restrict__ q2b,
+                                              const float* __restrict__ X, Feat f, int B, int FO, int O, int H,
+                                              float* __restrict__ Qm, float* __restrict__ bm)
 {
-    const long n = (long)B * FO * (H + 1);
-    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-        const int hh = e % (H + 1);
-        const long bfo = e / (H + 1);
-        const int fo = bfo % FO, b = bfo / FO;
+    // block rows fo, thread hh (hh = H: the bias); the six response weights
+    // of (fo, hh) are read once and applied to every sample
+    const int hh = blockIdx.x * 256 + threadIdx.x;
+    if (hh > H) return;
+    for (int fo = blockIdx.y; fo < FO; fo += gridDim.y) {
         const int fr = fo / O, o = fo - fr * O;
-        float s = 0.f;
-        if (hh < H) {
+        float q[6];
 #pragma unroll
-            for (int j = 0; j < 6; ++j) s += mfeat(X, f, b, j) * Q2[((long)(fr * 6 + j) * O + o) * H + hh];
-            Qm[bfo * H + hh] = s;
-        } else {
+        for (int j = 0; j < 6; ++j) {
+            const long row = (long)(fr * 6 + j) * O + o;
+            q[j] = hh < H ? Q2[row * H + hh] : q2b[row];
+        }
+        for (int b = 0; b < B; ++b) {
+            float s = 0.f;
 #pragma unroll
-            for (int j = 0; j < 6; ++j) s += mfeat(X, f, b, j) * q2b[(fr * 6 + j) * O + o];
-            bm[bfo] = s;
+            for (int j = 0; j < 6; ++j) s += mfeat(X, f, b, j) * q[j];
+            if (hh < H) Qm[((long)b * FO + fo) * H + hh] = s;
+            else bm[(long)b * FO + fo] = s;
         }
     }
 }
 
 // gradients of Q2 and q2b from those of the weighted projection:
 // dQ2[(f 6 + j) O + o][h] = sum_b m_bj dQm[b][f O + o][h] (h = H: the bias)
-__global__ void k_qgrad(const float* __restrict__ dQm, const float* __restrict__ dbm, const float* __restrict__ X,
-                        Feat f, int B, int FO, int O, int H, float* __restrict__ dQ2, float* __restrict__ dq2b)
+__global__ __launch_bounds__(256) void k_qgrad(const float* __restrict__ dQm, const float* __restrict__ dbm,
+                                               const float* __restrict__ X, Feat f, int B, int FO, int O, int H,
+                                               float* __restrict__ dQ2, float* __restrict__ dq2b)
 {
-    const int F = FO / O;
-    const long n = (long)F * 6 * O * (H + 1);
-    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-        const int hh = e % (H + 1);
-        const long row = e / (H + 1);             // (f 6 + j) O + o
-        const int o = row % O, fj = row / O;
-        const int fr = fj / 6, j = fj - fr * 6;
-        const int fo = fr * O + o;
-        float s = 0.f;
-        for (int b = 0; b < B; ++b)
-            s += mfeat(X, f, b, j) * (hh < H ? dQm[((long)b * FO + fo) * H + hh] : dbm[(long)b * FO + fo]);
-        if (hh < H) dQ2[row * H + hh] = s;
-        else dq2b[row] = s;
+    // block rows fo, thread hh: each dQm value is read once for all six j
+    const int hh = blockIdx.x * 256 + threadIdx.x;
+    if (hh > H) return;
+    for (int fo = blockIdx.y; fo < FO; fo += gridDim.y) {
+        const int fr = fo / O, o = fo - fr * O;
+        float s[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int b = 0; b < B; ++b) {
+            const float d = hh < H ? dQm[((long)b * FO + fo) * H + hh] : dbm[(long)b * FO + fo];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) s[j] += mfeat(X, f, b, j) * d;
+        }
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const long row = (long)(fr * 6 + j) * O + o;
+            if (hh < H) dQ2[row * H + hh] = s[j];
+            else dq2b[row] = s[j];
+        }
     }
 }
 
@@ -530,56 +539,59 @@ __device__ __forceinline__ void lagrange4(float w, float* c)
 }
 
 // Y[b][o][t] = sum_f Yf[b][f O + o](t - shift[b][f][o mod n_rec])
-__global__ void k_fcomb(const float* __restrict__ Yf, const float* __restrict__ shift, int B, int F, int O, int n_rec,
-                        int T, float* __restrict__ Y)
+__global__ __launch_bounds__(256) void k_fcomb(const float* __restrict__ Yf, const float* __restrict__ shift, int B,
+                                               int F, int O, int n_rec, int T, float* __restrict__ Y)
 {
+    // block rows (b, o), threads along t
     const long per = (long)O * T;
-    const long n = (long)B * per;
-    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-        const int b = e / per;
-        const int o = (e / T) % O, t = e % T;
-        float acc = 0.f;
-        for (int fr = 0; fr < F; ++fr) {
-            const float x = (float)t - shift[(b * F + fr) * n_rec + o % n_rec];
-            const float fl = floorf(x);
-            float c[4];
-            lagrange4(x - fl, c);
-            const int i0 = (int)fl - 1;
-            const float* u = Yf + ((long)b * F + fr) * per + (long)o * T;
+    for (int row = blockIdx.y; row < B * O; row += gridDim.y) {
+        const int b = row / O, o = row - b * O;
+        for (int t = blockIdx.x * 256 + threadIdx.x; t < T; t += gridDim.x * 256) {
+            float acc = 0.f;
+            for (int fr = 0; fr < F; ++fr) {
+                const float x = (float)t - shift[(b * F + fr) * n_rec + o % n_rec];
+                const float fl = floorf(x);
+                float c[4];
+                lagrange4(x - fl, c);
+                const int i0 = (int)fl - 1;
+                const float* u = Yf + ((long)b * F + fr) * per + (long)o * T;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const int i = i0 + k;
-                if (i >= 0 && i < T) acc += c[k] * u[i];
+                for (int k = 0; k < 4; ++k) {
+                    const int i = i0 + k;
+                    if (i >= 0 && i < T) acc += c[k] * u[i];
+                }
             }
+            Y[(long)row * T + t] = acc;
         }
-        Y[e] = acc;
     }
 }
 
 // dYf[b][f O + o][i] = sum_t dY[b][o][t] w_{t,i}: the transpose of k_fcomb, as a
 // gather over the (at most five) t whose interpolation reads sample i
-__global__ void k_fspread(const float* __restrict__ dY, const float* __restrict__ shift, int B, int F, int O, int n_rec,
-                          int T, float* __restrict__ dYf)
+__global__ __launch_bounds__(256) void k_fspread(const float* __restrict__ dY, const float* __restrict__ shift, int B,
+                                                 int F, int O, int n_rec, int T, float* __restrict__ dYf)
 {
-    const long per = (long)O * T;
-    const long n = (long)B * F * per;
-    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
-        const int i = e % T, o = (e / T) % O;
-        const int bf = e / per, b = bf / F;
+    // block rows ((b F + f) O + o), threads along i
+    for (int row = blockIdx.y; row < B * F * O; row += gridDim.y) {
+        const int o = row % O, bf = row / O, b = bf / F;
         const float sh = shift[bf * n_rec + o % n_rec];
-        // t - sh in [i - 2, i + 1] reads sample i
-        const int t0 = max(0, (int)floorf((float)i - 2.f + sh)), t1 = min(T - 1, (int)ceilf((float)i + 1.f + sh));
-        float acc = 0.f;
-        for (int t = t0; t <= t1; ++t) {
-            const float x = (float)t - sh;
-            const float fl = floorf(x);
-            const int k = i - (int)fl + 1;
-            if (k < 0 || k > 3) continue;
-            float c[4];
-            lagrange4(x - fl, c);
-            acc += c[k] * dY[(long)b * per + (long)o * T + t];
+        const float* __restrict__ g = dY + ((long)b * O + o) * T;
+        for (int i = blockIdx.x * 256 + threadIdx.x; i < T; i += gridDim.x * 256) {
+            // t - sh in [i - 2, i + 1] reads sample i
+            const int t0 = max(0, (int)floorf((float)i - 2.f + sh));
+            const int t1 = min(T - 1, (int)ceilf((float)i + 1.f + sh));
+            float acc = 0.f;
+            for (int t = t0; t <= t1; ++t) {
+                const float x = (float)t - sh;
+                const float fl = floorf(x);
+                const int k = i - (int)fl + 1;
+                if (k < 0 || k > 3) continue;
+                float c[4];
+                lagrange4(x - fl, c);
+                acc += c[k] * g[t];
+            }
+            dYf[(long)row * T + i] = acc;
         }
-        dYf[e] = acc;
     }
 }
 
@@ -776,6 +788,12 @@ __global__ void k_decim(const float* __restrict__ in, long rows, int nt, int dec
 }
 
 int grid_for(long n) { return (int)std::min<long>((n + 255) / 256, 4096); }
+// 256-thread blocks along a row of `len` values, one block row per row (the
+// kernels loop over rows past the grid's y limit)
+dim3 rows_grid(long len, long rows)
+{
+    return dim3((unsigned)((len + 255) / 256), (unsigned)std::min<long>(std::max<long>(rows, 1), 65535));
+}
 
 }  // namespace
 
@@ -958,15 +976,15 @@ void forward(sno* s, hipStream_t st, const float* X, int B)
     // moment-weighted projection: one frame writes the output directly, two
     // frames go through the per-receiver delays
     const long FO = s->F * O;
-    hipLaunchKernelGGL(k_qmix, dim3(grid_for(B * FO * (H + 1))), dim3(256), 0, st, th + s->off_Q2, th + s->off_q2b, X,
-                       s->feat, B, (int)FO, (int)O, (int)H, s->Qm, s->bm);
+    hipLaunchKernelGGL(k_qmix, rows_grid(H + 1, FO), dim3(256), 0, st, th + s->off_Q2, th + s->off_q2b, X, s->feat, B,
+                       (int)FO, (int)O, (int)H, s->Qm, s->bm);
     float* Yf = s->F == 1 ? s->Y : s->Y6;
     gemm(st, B, FO, T, H, 1, s->Qm, H, 1, FO * H, 0, s->Hq, T, 1, H * T, 0, Yf, T, 1, FO * T, 1.f, 0.f, s->bm, FO);
     if (s->F == 2) {
         hipLaunchKernelGGL(k_shifts, dim3(grid_for((long)B * s->F * c.n_rec)), dim3(256), 0, st, X, s->rays, B,
                            s->shift);
-        hipLaunchKernelGGL(k_fcomb, dim3(grid_for(B * O * T)), dim3(256), 0, st, s->Y6, s->shift, B, s->F, (int)O,
-                           c.n_rec, (int)T, s->Y);
+        hipLaunchKernelGGL(k_fcomb, rows_grid(T, B * O), dim3(256), 0, st, s->Y6, s->shift, B, s->F, (int)O, c.n_rec,
+                           (int)T, s->Y);
     }
 }
 
@@ -989,13 +1007,13 @@ void backward(sno* s, hipStream_t st, const float* X, const float* Yt, int B)
     float* dYf = dY;
     if (s->F == 2) {
         dYf = s->dY6;
-        hipLaunchKernelGGL(k_fspread, dim3(grid_for((long)B * FO * T)), dim3(256), 0, st, dY, s->shift, B, s->F,
-                           (int)O, c.n_rec, (int)T, dYf);
+        hipLaunchKernelGGL(k_fspread, rows_grid(T, B * FO), dim3(256), 0, st, dY, s->shift, B, s->F, (int)O, c.n_rec,
+                           (int)T, dYf);
     }
     gemm(st, B, FO, H, T, 1, dYf, T, 1, FO * T, 0, s->Hq, 1, T, H * T, 0, s->dQm, H, 1, FO * H);
     hipLaunchKernelGGL(k_rowsum, dim3(B * FO), dim3(256), 0, st, dYf, 1, (int)(B * FO), (int)T, s->dbm);
-    hipLaunchKernelGGL(k_qgrad, dim3(grid_for(s->F * 6 * O * (H + 1))), dim3(256), 0, st, s->dQm, s->dbm, X, s->feat, B,
-                       (int)FO, (int)O, (int)H, g + s->off_Q2, g + s->off_q2b);
+    hipLaunchKernelGGL(k_qgrad, rows_grid(H + 1, FO), dim3(256), 0, st, s->dQm, s->dbm, X, s->feat, B, (int)FO, (int)O,
+                       (int)H, g + s->off_Q2, g + s->off_q2b);
     gemm(st, B, H, T, FO, 1, s->Qm, 1, H, FO * H, 0, dYf, T, 1, FO * T, 0, s->dH, T, 1, H * T);
     hipLaunchKernelGGL(k_gelu_bwd, dim3(grid_for(B * H * T)), dim3(256), 0, st, s->dH, s->Hp, s->dH, (long)B * H * T);
     gemm(st, 1, H, C, T, B, s->dH, T, 1, 0, H * T, s->V(c.L), 1, T, 0, C * T, g + s->off_Q1, C, 1, 0, 1.f, 0.f, nullptr, 0, s->kws, s->kws_n);
