@@ -61,13 +61,14 @@ typedef struct {
     /* Travel-time-aligned output (frames = 2): the projection gives two sets
      * of 6 O rows, a P frame and an S frame; row o of frame f is delayed by
      * (tau_f(source, receiver r(o)) - t_ref[f]) / dt samples before the frames
-     * are summed, with tau_f the straight-ray travel time through a medium
-     * whose slowness depends on depth only (tau = |d| / |dz| times the depth
-     * integral of the slowness between the two cell centres; |d| slow[k] for
-     * a horizontal ray) and the fractional delay evaluated by 4-point Lagrange
-     * (cubic) interpolation, zero outside the window.  The direct arrivals then
-     * sit at fixed frame times for every source.  frames = 1: no delay (the
-     * fields below are ignored). */
+     * are summed, with tau_f the first-arrival time of the two-point ray
+     * between the two cell centres through a medium whose slowness depends on
+     * depth only (Snell's law across the cell layers: half a cell at each end,
+     * whole cells between; a path within one layer, a vertical path or one
+     * crossing a zero slowness takes the straight segment) and the fractional
+     * delay evaluated by 4-point Lagrange (cubic) interpolation, zero outside
+     * the window.  The direct arrivals then sit at fixed frame times for every
+     * source.  frames = 1: no delay (the fields below are ignored). */
     int frames;
     const int32_t *rec_ijk;  /* host [n_rec][3] receiver cells (copied by sno_create) */
     int nz_slow;             /* depth cells of the profiles (source and receiver depths below it) */

@@ -329,14 +329,51 @@ def straight_ray_time(src, rec, slow, h):
     return L / abs(d[2]) * integral
 
 
+def ray_layers(src, rec, slow, h):
+    """The cell layers a path between two cell centres crosses: thickness
+    (half a cell at each end, whole cells between, times h[2]) and slowness
+    of each, from the shallower end down."""
+    k0, k1 = int(min(src[2], rec[2])), int(max(src[2], rec[2]))
+    th = [0.5 * h[2]] + [h[2]] * (k1 - k0 - 1) + [0.5 * h[2]]
+    return np.array(th, np.float64), np.array([slow[k] for k in range(k0, k1 + 1)], np.float64)
+
+
+def ray_time(src, rec, slow, h, iters=64):
+    """First-arrival time of the two-point ray between two cell centres
+    through a medium whose slowness depends on depth only (Snell's law across
+    the cell layers of ray_layers).  A ray of horizontal slowness p crosses a
+    layer of thickness t and slowness s (p < s) with horizontal run
+    t p / sqrt(s^2 - p^2) in time t s^2 / sqrt(s^2 - p^2); the run is 0 at
+    p = 0 and grows without bound as p approaches the smallest slowness of
+    the layers, so the p whose total run equals the horizontal distance is
+    found by bisection (iters halvings of [0, min s)).  A path within one
+    layer, a vertical path, and a path through a layer of zero slowness (the
+    fluid in an S profile) take the straight segment."""
+    k0, k1 = int(min(src[2], rec[2])), int(max(src[2], rec[2]))
+    X = float(np.hypot((src[0] - rec[0]) * h[0], (src[1] - rec[1]) * h[1]))
+    if k0 == k1 or X == 0.0 or min(slow[k] for k in range(k0, k1 + 1)) <= 0.0:
+        return straight_ray_time(src, rec, slow, h)
+    th, sl = ray_layers(src, rec, slow, h)
+    lo, hi = 0.0, float(sl.min())
+    for _ in range(iters):
+        p = 0.5 * (lo + hi)
+        run = float(np.sum(th * p / np.sqrt(sl * sl - p * p)))
+        if run < X:
+            lo = p
+        else:
+            hi = p
+    p = 0.5 * (lo + hi)
+    return float(np.sum(th * sl * sl / np.sqrt(sl * sl - p * p)))
+
+
 def frame_shifts(src_ijk, rec_ijk, slows, h, dt, t_ref):
-    """shift[b][f][r] = (straight-ray time of frame f from source b to
-    receiver r - t_ref[f]) / dt, in samples; slows[f] is frame f's slowness
-    profile over depth."""
+    """shift[b][f][r] = (ray time of frame f from source b to receiver r -
+    t_ref[f]) / dt, in samples; slows[f] is frame f's slowness profile over
+    depth."""
     B, F, R = len(src_ijk), len(slows), len(rec_ijk)
     out = np.empty((B, F, R))
     for b in range(B):
         for f in range(F):
             for r in range(R):
-                out[b, f, r] = (straight_ray_time(src_ijk[b], rec_ijk[r], slows[f], h) - t_ref[f]) / dt
+                out[b, f, r] = (ray_time(src_ijk[b], rec_ijk[r], slows[f], h) - t_ref[f]) / dt
     return out

@@ -491,9 +491,12 @@ __global__ __launch_bounds__(256) void k_qgrad(const float* __restrict__ dQm, co
 }
 
 // Travel-time-aligned frames.  shift[b][f][r] = (tau_f - t_ref[f]) / dt with
-// tau_f the straight-ray time from source b's cell (X[b][0..2], whole cell
-// indices) to receiver r's; cum[f][k] = h_z (sum_{i<k} s_i + s_k / 2) is the
-// depth integral of frame f's slowness from the top to the centre of cell k.
+// tau_f the first-arrival time of the two-point ray from source b's cell
+// (X[b][0..2], whole cell indices) to receiver r's through frame f's slowness
+// profile over depth (a straight segment where the path stays in one layer,
+// is vertical, or crosses a zero slowness); cum[f][k] = h_z (sum_{i<k} s_i +
+// s_k / 2) is the depth integral of the slowness from the top to the centre
+// of cell k, which the straight segment uses.
 struct Rays {
     const int* rec;        // [n_rec][3]
     const double* cum;     // [frames][nz]
@@ -504,28 +507,77 @@ struct Rays {
     int nz, n_rec, frames;
 };
 
-__global__ void k_shifts(const float* __restrict__ X, Rays ry, int B, float* __restrict__ shift)
+// sum (all lanes get it) and minimum over the 64 lanes of a wave
+__device__ __forceinline__ double wave_sum(double v)
 {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v = fmin(v, __shfl_xor(v, m, 64));
+    return v;
+}
+
+// bisection steps for the ray's horizontal slowness: to 2^-32 of the
+// smallest slowness, which moves the travel time by at most the horizontal
+// distance times that (6e-11 s over a kilometre where the fastest layer runs
+// at 4 km/s)
+constexpr int RAY_ITERS = 32;
+
+// One wave per (source b, frame f, receiver r); its lanes take the cell
+// layers of the path in turn and the sums over layers are wave reductions.
+__global__ __launch_bounds__(256) void k_shifts(const float* __restrict__ X, Rays ry, int B, float* __restrict__ shift)
+{
+    const int lane = threadIdx.x & 63;
     const int n = B * ry.frames * ry.n_rec;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+    for (int e = blockIdx.x * 4 + (threadIdx.x >> 6); e < n; e += gridDim.x * 4) {
         const int r = e % ry.n_rec, f = (e / ry.n_rec) % ry.frames, b = e / (ry.n_rec * ry.frames);
         int src[3];
         for (int a = 0; a < 3; ++a) src[a] = (int)rintf(X[b * 9 + a]);
-        double d2 = 0.0;
-        for (int a = 0; a < 3; ++a) {
-            const double d = (double)(src[a] - ry.rec[3 * r + a]) * ry.h[a];
-            d2 += d * d;
-        }
-        const double L = sqrt(d2);
+        const double dx = (double)(src[0] - ry.rec[3 * r + 0]) * ry.h[0];
+        const double dy = (double)(src[1] - ry.rec[3 * r + 1]) * ry.h[1];
         const int ks = min(max(src[2], 0), ry.nz - 1), kr = ry.rec[3 * r + 2];
+        const int k0 = min(ks, kr), k1 = max(ks, kr);
+        const double hor = sqrt(dx * dx + dy * dy);
+        const double* __restrict__ sl = ry.slow + f * ry.nz;
+        double smin = 1e300;
+        for (int k = k0 + lane; k <= k1; k += 64) smin = fmin(smin, sl[k]);
+        smin = wave_min(smin);
         double tau;
-        if (ks == kr) {
-            tau = L * ry.slow[f * ry.nz + ks];
+        if (k0 == k1 || hor == 0.0 || !(smin > 0.0)) {
+            // straight segment: |d| / |dz| times the depth integral of the
+            // slowness (one layer: |d| times its slowness)
+            const double dz = (double)(ks - kr) * ry.h[2];
+            const double L = sqrt(hor * hor + dz * dz);
+            tau = k0 == k1 ? L * sl[ks] : L / fabs(dz) * fabs(ry.cum[f * ry.nz + ks] - ry.cum[f * ry.nz + kr]);
         } else {
-            const double dz = fabs((double)(ks - kr) * ry.h[2]);
-            tau = L / dz * fabs(ry.cum[f * ry.nz + ks] - ry.cum[f * ry.nz + kr]);
+            // two-point ray (Snell's law across the cell layers): horizontal
+            // slowness p by bisection so that the layers' horizontal runs
+            // t p / sqrt(s^2 - p^2) add up to the horizontal distance; layer
+            // thickness half a cell at each end, a whole cell between
+            double lo = 0.0, hi = smin;
+            for (int it = 0; it < RAY_ITERS; ++it) {
+                const double p = 0.5 * (lo + hi);
+                double run = 0.0;
+                for (int k = k0 + lane; k <= k1; k += 64) {
+                    const double t = (k == k0 || k == k1 ? 0.5 : 1.0) * ry.h[2];
+                    run += t * p / sqrt(sl[k] * sl[k] - p * p);
+                }
+                if (wave_sum(run) < hor) lo = p;
+                else hi = p;
+            }
+            const double p = 0.5 * (lo + hi);
+            double tt = 0.0;
+            for (int k = k0 + lane; k <= k1; k += 64) {
+                const double t = (k == k0 || k == k1 ? 0.5 : 1.0) * ry.h[2];
+                tt += t * sl[k] * sl[k] / sqrt(sl[k] * sl[k] - p * p);
+            }
+            tau = wave_sum(tt);
         }
-        shift[e] = (float)((tau - ry.t_ref[f]) / ry.dt);
+        if (lane == 0) shift[e] = (float)((tau - ry.t_ref[f]) / ry.dt);
     }
 }
 
@@ -981,7 +1033,8 @@ void forward(sno* s, hipStream_t st, const float* X, int B)
     float* Yf = s->F == 1 ? s->Y : s->Y6;
     gemm(st, B, FO, T, H, 1, s->Qm, H, 1, FO * H, 0, s->Hq, T, 1, H * T, 0, Yf, T, 1, FO * T, 1.f, 0.f, s->bm, FO);
     if (s->F == 2) {
-        hipLaunchKernelGGL(k_shifts, dim3(grid_for((long)B * s->F * c.n_rec)), dim3(256), 0, st, X, s->rays, B,
+        hipLaunchKernelGGL(k_shifts, dim3((unsigned)std::min<long>(((long)B * s->F * c.n_rec + 3) / 4, 4096)),
+                           dim3(256), 0, st, X, s->rays, B,
                            s->shift);
         hipLaunchKernelGGL(k_fcomb, rows_grid(T, B * O), dim3(256), 0, st, s->Y6, s->shift, B, s->F, (int)O, c.n_rec,
                            (int)T, s->Y);

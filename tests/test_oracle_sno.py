@@ -251,6 +251,75 @@ def test_straight_ray_times():
         h[2] * (0.5 * slow[4] + slow[5:9].sum() + 0.5 * slow[9]), rel=1e-14)
 
 
+def test_ray_time_reduces_to_the_straight_segment():
+    """Homogeneous medium: the two-point ray is the straight segment; a
+    vertical path, a path within one layer and a path through a zero
+    slowness (fluid S) are the straight segment by construction."""
+    h = (10.0, 12.5, 8.0)
+    slow = np.full(40, 1 / 2500.0)
+    for a, b in [((3, 4, 30), (10, 2, 5)), ((0, 0, 3), (7, 9, 20)), ((5, 5, 2), (25, 1, 38))]:
+        d = math.sqrt(sum(((a[k] - b[k]) * h[k]) ** 2 for k in range(3)))
+        assert osno.ray_time(a, b, slow, h) == pytest.approx(d / 2500.0, rel=1e-12)
+    rng = np.random.default_rng(4)
+    slow = 1.0 / rng.uniform(1800, 4200, 40)
+    assert osno.ray_time((1, 1, 4), (1, 1, 9), slow, h) == osno.straight_ray_time((1, 1, 4), (1, 1, 9), slow, h)
+    assert osno.ray_time((1, 1, 7), (9, 4, 7), slow, h) == osno.straight_ray_time((1, 1, 7), (9, 4, 7), slow, h)
+    s0 = slow.copy()
+    s0[10] = 0.0
+    assert osno.ray_time((1, 1, 4), (9, 1, 19), s0, h) == osno.straight_ray_time((1, 1, 4), (9, 1, 19), s0, h)
+
+
+def test_ray_time_two_media_against_fermat():
+    """Two homogeneous media: the first-arrival time is the minimum over the
+    crossing point x of s1 sqrt(x^2 + D1^2) + s2 sqrt((X - x)^2 + D2^2)
+    (Fermat), found here by a bounded scalar minimisation."""
+    from scipy.optimize import minimize_scalar
+    h = (10.0, 10.0, 10.0)
+    slow = np.where(np.arange(60) < 25, 1 / 1800.0, 1 / 3600.0)
+    for a, b in [((0, 0, 10), (30, 0, 45)), ((2, 3, 5), (40, 20, 55)), ((0, 0, 24), (12, 5, 26))]:
+        X = math.hypot((a[0] - b[0]) * h[0], (a[1] - b[1]) * h[1])
+        k0, k1 = min(a[2], b[2]), max(a[2], b[2])
+        # thickness in each medium: half a cell at each end, whole cells between
+        th = np.array([0.5] + [1.0] * (k1 - k0 - 1) + [0.5]) * h[2]
+        ks = np.arange(k0, k1 + 1)
+        D1, D2 = th[ks < 25].sum(), th[ks >= 25].sum()
+        f = lambda x: math.sqrt(x * x + D1 * D1) / 1800.0 + math.sqrt((X - x) ** 2 + D2 * D2) / 3600.0
+        best = minimize_scalar(f, bounds=(0.0, X), method="bounded", options={"xatol": 1e-10})
+        t = osno.ray_time(a, b, slow, h)
+        assert t == pytest.approx(best.fun, rel=1e-9)
+        assert t == pytest.approx(osno.ray_time(b, a, slow, h), rel=1e-13)
+        assert t < osno.straight_ray_time(a, b, slow, h)
+
+
+def test_ray_time_is_the_least_time_path_through_many_layers():
+    """Forty layers of random slowness: the ray time equals the least time
+    over all paths straight within each layer (horizontal runs r_i summing to
+    the horizontal distance; time sum s_i sqrt(r_i^2 + t_i^2)), minimised
+    numerically without Snell's law, and is below the straight segment's."""
+    from scipy.optimize import minimize
+    rng = np.random.default_rng(5)
+    h = (10.0, 12.5, 8.0)
+    slow = 1.0 / rng.uniform(1800, 4200, 60)
+    for a, b in [((2, 30, 45), (17, 3, 6)), ((0, 0, 50), (30, 10, 12))]:
+        X = math.hypot((a[0] - b[0]) * h[0], (a[1] - b[1]) * h[1])
+        th, sl = osno.ray_layers(a, b, slow, h)
+        n = th.size
+
+        def T(r):
+            return float(np.sum(sl * np.sqrt(r * r + th * th)))
+
+        def J(r):
+            return sl * r / np.sqrt(r * r + th * th)
+
+        r0 = np.full(n, X / n)
+        res = minimize(T, r0, jac=J, method="SLSQP",
+                       constraints=[{"type": "eq", "fun": lambda r: np.sum(r) - X, "jac": lambda r: np.ones(n)}],
+                       bounds=[(0.0, X)] * n, options={"ftol": 1e-15, "maxiter": 2000})
+        t = osno.ray_time(a, b, slow, h)
+        assert t == pytest.approx(res.fun, rel=1e-8)
+        assert t <= T(r0) and t < osno.straight_ray_time(a, b, slow, h)
+
+
 D_FR = osno.Dims(n_pos=3, n_mt=6, four=(3.0, 7.5), C=4, T=32, K=5, L=2, H=6, O=8, frames=2)
 
 
