@@ -90,6 +90,12 @@ typedef struct {
      * with the epoch index and its mean training loss */
     void (*on_epoch)(int epoch, float loss, void *user);
     void *user;
+    /* 0: the loss is the mean squared error of the per-component normalised
+     * outputs; 1: each (sample, component) term is divided by that target's
+     * mean square, so the loss is the mean squared relative L2 error over
+     * samples and components (the measure the error head predicts) and a
+     * weak seismogram counts as much as a strong one */
+    int rel_loss;
 } sno_train_cfg;
 
 /* Create a model; params (host float, sno_n_params values, order P [C][NA]
@@ -127,6 +133,10 @@ int sno_predict_or_solve(sno *s, pstd3d_ctx *solver, const float *X, const int32
  * normalised) into grad (device, sno_n_params floats). */
 int sno_forward(sno *s, const float *X, int n, float *Y, void *hip_stream);
 int sno_gradient(sno *s, const float *X, const float *Yt, int n, float *grad, float *loss, void *hip_stream);
+/* The same with per-(sample, component) weights w (device float [n][4], NULL:
+ * all 1): the loss is the mean over all outputs of w (Y - Yt)^2. */
+int sno_gradient_weighted(sno *s, const float *X, const float *Yt, const float *w, int n, float *grad, float *loss,
+                          void *hip_stream);
 /* Copy the current FP32 weights to host memory. */
 int sno_get_params(const sno *s, float *params);
 /* Test entries of the optimiser: one Adam step of the weights with the device

@@ -169,18 +169,39 @@ def forward(theta, src, d: Dims, keep=False, shift=None):
     return (Y, cache) if keep else Y
 
 
-def loss(theta, src, y, d: Dims, shift=None):
+def element_weights(w, d: Dims):
+    """Per-element loss weights from per-(sample, component) ones: w [B][4]
+    -> [B][O][1] (output o belongs to component o // n_rec); None -> 1."""
+    if w is None:
+        return 1.0
+    n_rec = d.O // 4
+    w = np.asarray(w, np.float64)
+    return w[:, np.arange(d.O) // n_rec][:, :, None]
+
+
+def relative_weights(y, d: Dims):
+    """w[b][c] = 1 / mean square of target b's component c: with these the
+    weighted mean squared error is the mean over samples and components of
+    the squared relative L2 error (0 for an all-zero component)."""
+    n_rec = d.O // 4
+    ms = np.mean(np.asarray(y, np.float64).reshape(y.shape[0], 4, n_rec * d.T) ** 2, axis=2)
+    return np.where(ms > 0, 1.0 / np.where(ms > 0, ms, 1.0), 0.0)
+
+
+def loss(theta, src, y, d: Dims, shift=None, w=None):
+    """Mean over all outputs of w (Y - y)^2; w [B][4] per sample and
+    component, or None for the plain mean squared error."""
     Y = forward(theta, src, d, shift=shift)
-    return float(np.mean((Y - y) ** 2))
+    return float(np.mean(element_weights(w, d) * (Y - y) ** 2))
 
 
-def grad(theta, src, y, d: Dims, shift=None):
-    """Gradient of the mean squared error with respect to the flat parameters."""
+def grad(theta, src, y, d: Dims, shift=None, w=None):
+    """Gradient of loss() with respect to the flat parameters."""
     p = unflatten(theta, d)
     F, G = dft_bases(d)
     Y, c = forward(theta, src, d, keep=True, shift=shift)
     g = {}
-    dY = 2.0 * (Y - y) / Y.size
+    dY = 2.0 * element_weights(w, d) * (Y - y) / Y.size
     dYf = np.broadcast_to(c["m"][:, None, :, None, None] * dY[:, None, None, :, :],
                           (Y.shape[0], d.frames, d.n_mt, d.O, d.T))
     if shift is not None:

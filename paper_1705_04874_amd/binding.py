@@ -331,7 +331,7 @@ _EPOCH_CB = C.CFUNCTYPE(None, C.c_int, C.c_float, C.c_void_p)
 
 class SnoTrainCfg(C.Structure):
     _fields_ = [("epochs", C.c_int), ("batch", C.c_int), ("lr", C.c_double), ("seed", C.c_uint64),
-                ("n_calib", C.c_int), ("on_epoch", _EPOCH_CB), ("user", C.c_void_p)]
+                ("n_calib", C.c_int), ("on_epoch", _EPOCH_CB), ("user", C.c_void_p), ("rel_loss", C.c_int)]
 
 
 _L.sno_n_params.argtypes = [C.POINTER(SnoCfg)]
@@ -344,6 +344,8 @@ _L.sno_predict_or_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, _ip, _dp
                                     C.c_double, C.c_int, C.c_void_p, C.c_void_p, C.POINTER(C.c_int), C.c_void_p]
 _L.sno_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
 _L.sno_gradient.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, _fp, C.c_void_p]
+_L.sno_gradient_weighted.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, _fp,
+                                     C.c_void_p]
 _L.sno_get_params.argtypes = [C.c_void_p, _fp]
 _L.sno_adam_step.argtypes = [C.c_void_p, C.c_void_p, C.c_long, C.c_double, C.c_void_p]
 _L.sno_get_moments.argtypes = [C.c_void_p, _fp, _fp]
@@ -413,10 +415,12 @@ class Surrogate:
         import torch
         return torch.empty((n, 4, self.cfg.n_rec, self.cfg.T), dtype=torch.float32, device="cuda")
 
-    def train(self, X, Y, epochs, batch, lr, seed=0, n_calib=0, stream=None, on_epoch=None):
-        """Train; on_epoch(epoch, mean_loss), if given, is called after every epoch."""
+    def train(self, X, Y, epochs, batch, lr, seed=0, n_calib=0, stream=None, on_epoch=None, rel_loss=False):
+        """Train; on_epoch(epoch, mean_loss), if given, is called after every
+        epoch; rel_loss: the mean squared relative error per sample and
+        component instead of the mean squared error (include/sno.h)."""
         cb = _EPOCH_CB(lambda ep, loss, _u: on_epoch(int(ep), float(loss))) if on_epoch else _EPOCH_CB()
-        tc = SnoTrainCfg(int(epochs), int(batch), float(lr), int(seed), int(n_calib), cb, None)
+        tc = SnoTrainCfg(int(epochs), int(batch), float(lr), int(seed), int(n_calib), cb, None, int(bool(rel_loss)))
         curve = np.zeros(max(1, int(epochs)), np.float32)
         _scheck(_L.sno_train(self._h, _dev(X), _dev(Y), X.shape[0], C.byref(tc), curve.ctypes.data_as(_fp),
                              _stream_handle(stream)), "sno_train")
@@ -462,12 +466,19 @@ class Surrogate:
         _scheck(_L.sno_forward(self._h, _dev(X), X.shape[0], _dev(Y), _stream_handle(stream)), "sno_forward")
         return Y
 
-    def gradient(self, X, Yt, stream=None):
+    def gradient(self, X, Yt, stream=None, w=None):
+        """Gradient (and loss) of the mean squared error against normalised
+        targets Yt; w: optional device weights [n][4] per sample and component."""
         import torch
         g = torch.empty(self.n_params, dtype=torch.float32, device="cuda")
         loss = C.c_float()
-        _scheck(_L.sno_gradient(self._h, _dev(X), _dev(Yt), X.shape[0], _dev(g), C.byref(loss),
-                                _stream_handle(stream)), "sno_gradient")
+        if w is None:
+            _scheck(_L.sno_gradient(self._h, _dev(X), _dev(Yt), X.shape[0], _dev(g), C.byref(loss),
+                                    _stream_handle(stream)), "sno_gradient")
+        else:
+            assert tuple(w.shape) == (X.shape[0], 4)
+            _scheck(_L.sno_gradient_weighted(self._h, _dev(X), _dev(Yt), _dev(w), X.shape[0], _dev(g), C.byref(loss),
+                                             _stream_handle(stream)), "sno_gradient_weighted")
         return g, loss.value
 
     def params(self):

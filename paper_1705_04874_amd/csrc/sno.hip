@@ -647,6 +647,120 @@ __global__ __launch_bounds__(256) void k_fspread(const float* __restrict__ dY, c
     }
 }
 
+// Per-mode complex channel mixing of the spectral layers (16 modes, width C):
+// U[b][c][k] = sum_c' M_k[c][c'] V[b][c'][k] with M_k = Rr_k + i Ri_k
+// (forward) or its conjugate transpose (the input gradient), real parts at
+// column k and imaginary parts at K + k of each row of 2K.  One block per
+// mode stages M_k (rows padded to C + 1, conflict-free) and chunks of up to
+// MIX_B samples' V in LDS; FP32 products and sums in a fixed order.
+constexpr int MIX_B = 32;
+constexpr size_t MIX_LDS_MAX = 64 * 1024;
+
+size_t mix_lds(long C) { return ((size_t)2 * C * (C + 1) + 2 * (size_t)MIX_B * C) * sizeof(float); }
+
+template <bool HERM>
+__global__ __launch_bounds__(256) void k_cmix(const float* __restrict__ Rr, const float* __restrict__ Ri,
+                                              const float* __restrict__ V, int B, int C, int K,
+                                              float* __restrict__ U)
+{
+    extern __shared__ float sm[];
+    const int k = blockIdx.x;
+    const int C1 = C + 1;
+    float* mr = sm;                     // mr[c][c'] (row stride C + 1)
+    float* mi = sm + C * C1;
+    float* vr = sm + 2 * C * C1;        // vr[b][c'], b < MIX_B
+    float* vi = vr + MIX_B * C;
+    const long K2 = 2L * K;
+    for (int e = threadIdx.x; e < C * C; e += 256) {
+        const int a = e / C, q = e - a * C;
+        const float xr = Rr[(long)k * C * C + e], xi = Ri[(long)k * C * C + e];
+        if (HERM) {
+            mr[q * C1 + a] = xr;
+            mi[q * C1 + a] = -xi;
+        } else {
+            mr[a * C1 + q] = xr;
+            mi[a * C1 + q] = xi;
+        }
+    }
+    for (int b0 = 0; b0 < B; b0 += MIX_B) {
+        const int nb = min(MIX_B, B - b0);
+        __syncthreads();   // M staged / the previous chunk's readers done
+        for (int e = threadIdx.x; e < nb * C; e += 256) {
+            const long row = (long)(b0 + e / C) * C + (e % C);
+            vr[e] = V[row * K2 + k];
+            vi[e] = V[row * K2 + K + k];
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nb * C; e += 256) {
+            const int b = e / C, c = e - b * C;
+            float ur = 0.f, ui = 0.f;
+            for (int q = 0; q < C; ++q) {
+                const float a = mr[c * C1 + q], bb = mi[c * C1 + q];
+                const float xr = vr[b * C + q], xi = vi[b * C + q];
+                ur = fmaf(a, xr, fmaf(-bb, xi, ur));
+                ui = fmaf(bb, xr, fmaf(a, xi, ui));
+            }
+            const long row = (long)(b0 + b) * C + c;
+            U[row * K2 + k] = ur;
+            U[row * K2 + K + k] = ui;
+        }
+    }
+}
+
+// Gradient of the mixing weights, summed over the samples:
+// dRr_k[c][c'] = sum_b dUr[b][c] Vr[b][c'] + dUi[b][c] Vi[b][c'],
+// dRi_k[c][c'] = sum_b dUi[b][c] Vr[b][c'] - dUr[b][c] Vi[b][c'].
+__global__ __launch_bounds__(256) void k_cmix_dw(const float* __restrict__ dU, const float* __restrict__ V, int B,
+                                                 int C, int K, float* __restrict__ dRr, float* __restrict__ dRi)
+{
+    extern __shared__ float sm[];
+    const int k = blockIdx.x;
+    float* ur = sm;                     // [b][c], b < MIX_B
+    float* ui = ur + MIX_B * C;
+    float* vr = ui + MIX_B * C;
+    float* vi = vr + MIX_B * C;
+    const long K2 = 2L * K;
+    constexpr int PER = 16;             // outputs per thread and pass
+    for (int e0 = 0; e0 < C * C; e0 += 256 * PER) {
+        float ar[PER], ai[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) ar[j] = ai[j] = 0.f;
+        for (int b0 = 0; b0 < B; b0 += MIX_B) {
+            const int nb = min(MIX_B, B - b0);
+            __syncthreads();
+            for (int e = threadIdx.x; e < nb * C; e += 256) {
+                const long row = (long)(b0 + e / C) * C + (e % C);
+                ur[e] = dU[row * K2 + k];
+                ui[e] = dU[row * K2 + K + k];
+                vr[e] = V[row * K2 + k];
+                vi[e] = V[row * K2 + K + k];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const int e = e0 + j * 256 + threadIdx.x;
+                if (e < C * C) {
+                    const int c = e / C, q = e - c * C;
+                    for (int b = 0; b < nb; ++b) {
+                        const float xr = ur[b * C + c], xi = ui[b * C + c];
+                        const float yr = vr[b * C + q], yi = vi[b * C + q];
+                        ar[j] = fmaf(xr, yr, fmaf(xi, yi, ar[j]));
+                        ai[j] = fmaf(xi, yr, fmaf(-xr, yi, ai[j]));
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int e = e0 + j * 256 + threadIdx.x;
+            if (e < C * C) {
+                dRr[(long)k * C * C + e] = ar[j];
+                dRi[(long)k * C * C + e] = ai[j];
+            }
+        }
+    }
+}
+
 // out[r] = sum over b, t of X[b][r][t]  (fixed reduction order)
 __global__ __launch_bounds__(256) void k_rowsum(const float* __restrict__ X, int B, int R, int T, float* __restrict__ out)
 {
@@ -665,16 +779,25 @@ __global__ __launch_bounds__(256) void k_rowsum(const float* __restrict__ X, int
 }
 
 // dY = 2 (Y - Yt) / n; block partial sums of (Y - Yt)^2
-__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ Y, const float* __restrict__ Yt, long n,
+// dY = 2 w (Y - Yt) / n and per-block partial sums of w (Y - Yt)^2, with w
+// = wgt[b][o / n_rec] per sample and component (1 without weights); rows
+// (b, o) in a fixed order per block, so the partial sums are reproducible
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ Y, const float* __restrict__ Yt,
+                                             const float* __restrict__ wgt, int B, int O, int T, int n_rec,
                                              float* __restrict__ dY, float* __restrict__ part)
 {
     __shared__ float red[256];
     float s = 0.f;
-    const float g = 2.f / (float)n;
-    for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) {
-        const float d = Y[i] - Yt[i];
-        dY[i] = g * d;
-        s += d * d;
+    const float g = 2.f / ((float)B * O * T);
+    for (int row = blockIdx.x; row < B * O; row += gridDim.x) {
+        const int b = row / O, o = row - b * O;
+        const float w = wgt ? wgt[b * 4 + o / n_rec] : 1.f;
+        const long base = (long)row * T;
+        for (int t = threadIdx.x; t < T; t += 256) {
+            const float d = Y[base + t] - Yt[base + t];
+            dY[base + t] = g * w * d;
+            s += w * d * d;
+        }
     }
     red[threadIdx.x] = s;
     __syncthreads();
@@ -683,6 +806,37 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ Y, const 
         __syncthreads();
     }
     if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// relative-loss weights of n samples: w[i][c] = 1 / mean square of sample i's
+// component c after the output normalisation (0 for an all-zero component)
+__global__ __launch_bounds__(256) void k_relw(const float* __restrict__ Y, int n_rec, int T,
+                                              const float* __restrict__ scale, float* __restrict__ w)
+{
+    __shared__ double red[256];
+    const int i = blockIdx.x, c = blockIdx.y;
+    const long per = (long)n_rec * T;
+    const float* __restrict__ y = Y + ((long)i * 4 + c) * per;
+    const double inv = 1.0 / (double)scale[c];
+    double s = 0.0;
+    for (long e = threadIdx.x; e < per; e += 256) {
+        const double v = y[e] * inv;
+        s += v * v;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) w[i * 4 + c] = red[0] > 0.0 ? (float)((double)per / red[0]) : 0.f;
+}
+
+// the batch's weights: wb[b][c] = w[idx[b]][c]
+__global__ void k_gather_w(const float* __restrict__ w, const int* __restrict__ idx, int B, float* __restrict__ wb)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < B * 4) wb[e] = w[idx[e / 4] * 4 + e % 4];
 }
 
 __global__ void k_sum_parts(const float* __restrict__ part, int np, float* __restrict__ out, float scale)
@@ -879,6 +1033,7 @@ struct sno {
     // partial sums of the split weight-gradient products
     static constexpr long kws_n = 4L << 20;
     float* kws = nullptr;
+    float* wb = nullptr;       // the batch's loss weights [B][4]
 
     float* V(int l) { return l < cfg.L ? Vb + (long)l * bmax * cfg.C * cfg.T : Z + (long)(cfg.L - 1) * bmax * cfg.C * cfg.T; }
     float* Zl(int l) { return Z + (long)l * bmax * cfg.C * cfg.T; }
@@ -887,11 +1042,11 @@ struct sno {
     void free_ws()
     {
         for (float* p : {A, Vb, Vh, Z, Uh, Hp, Hq, Y, X0, X1, X2, dH, dUh, dVh, part, lossd, phi, Xb, Yb, Y6, dY6, shift,
-                         Qm, dQm, bm, dbm, kws})
+                         Qm, dQm, bm, dbm, kws, wb})
             (void)hipFree(p);
         (void)hipFree(idxd);
         A = Vb = Vh = Z = Uh = Hp = Hq = Y = X0 = X1 = X2 = dH = dUh = dVh = part = lossd = phi = Xb = Yb = Y6 = dY6 =
-            shift = Qm = dQm = bm = dbm = kws = nullptr;
+            shift = Qm = dQm = bm = dbm = kws = wb = nullptr;
         idxd = nullptr;
         bmax = 0;
     }
@@ -917,7 +1072,8 @@ struct sno {
             al(&Y, (long)B * O * T) || al(&X0, (long)B * std::max(C, (long)O) * T) || al(&X1, (long)B * C * T) ||
             al(&X2, (long)B * C * T) || al(&dH, (long)B * H * T) || al(&dUh, (long)B * C * K2) ||
             al(&dVh, (long)B * C * K2) || al(&part, 4096) || al(&lossd, 4) || al(&phi, (long)B * (C + 7)) ||
-            al(&Xb, (long)B * 9) || al(&Yb, (long)B * O * T) || al(&kws, kws_n) || hipMalloc(&idxd, B * sizeof(int)))
+            al(&Xb, (long)B * 9) || al(&Yb, (long)B * O * T) || al(&kws, kws_n) || al(&wb, (long)B * 4) ||
+            hipMalloc(&idxd, B * sizeof(int)))
             return sfail(PSTD_ENOMEM, "surrogate workspace");
         bmax = B;
         return PSTD_OK;
@@ -1011,10 +1167,15 @@ void forward(sno* s, hipStream_t st, const float* X, int B)
         // complex mixing per mode: batch over modes, samples as columns
         const float* Rr = th + s->off_Rr[l];
         const float* Ri = th + s->off_Ri[l];
-        gemm(st, K, C, B, C, 1, Rr, C, 1, C * C, 0, Vh, K2, C * K2, 1, 0, s->Uh, K2, C * K2, 1, 1.f, 0.f);
-        gemm(st, K, C, B, C, 1, Ri, C, 1, C * C, 0, Vh + K, K2, C * K2, 1, 0, s->Uh, K2, C * K2, 1, -1.f, 1.f);
-        gemm(st, K, C, B, C, 1, Ri, C, 1, C * C, 0, Vh, K2, C * K2, 1, 0, s->Uh + K, K2, C * K2, 1, 1.f, 0.f);
-        gemm(st, K, C, B, C, 1, Rr, C, 1, C * C, 0, Vh + K, K2, C * K2, 1, 0, s->Uh + K, K2, C * K2, 1, 1.f, 1.f);
+        if (mix_lds(C) <= MIX_LDS_MAX) {
+            hipLaunchKernelGGL(k_cmix<false>, dim3((unsigned)K), dim3(256), mix_lds(C), st, Rr, Ri, Vh, B, (int)C,
+                               (int)K, s->Uh);
+        } else {
+            gemm(st, K, C, B, C, 1, Rr, C, 1, C * C, 0, Vh, K2, C * K2, 1, 0, s->Uh, K2, C * K2, 1, 1.f, 0.f);
+            gemm(st, K, C, B, C, 1, Ri, C, 1, C * C, 0, Vh + K, K2, C * K2, 1, 0, s->Uh, K2, C * K2, 1, -1.f, 1.f);
+            gemm(st, K, C, B, C, 1, Ri, C, 1, C * C, 0, Vh, K2, C * K2, 1, 0, s->Uh + K, K2, C * K2, 1, 1.f, 0.f);
+            gemm(st, K, C, B, C, 1, Rr, C, 1, C * C, 0, Vh + K, K2, C * K2, 1, 0, s->Uh + K, K2, C * K2, 1, 1.f, 1.f);
+        }
         // Z = W V + b + inverse DFT of the mixed modes
         gemm(st, B, C, T, C, 1, th + s->off_W[l], C, 1, 0, 0, V, T, 1, C * T, 0, Z, T, 1, C * T, 1.f, 0.f,
              th + s->off_b[l]);
@@ -1043,7 +1204,7 @@ void forward(sno* s, hipStream_t st, const float* X, int B)
 
 // gradient of the mean squared error of s->Y against Yt (after the forward of
 // the same features X)
-void backward(sno* s, hipStream_t st, const float* X, const float* Yt, int B)
+void backward(sno* s, hipStream_t st, const float* X, const float* Yt, int B, const float* wgt = nullptr)
 {
     const sno_cfg& c = s->cfg;
     const long C = c.C, T = c.T, K = c.K, K2 = 2 * K, H = c.H, O = s->O;
@@ -1051,7 +1212,7 @@ void backward(sno* s, hipStream_t st, const float* X, const float* Yt, int B)
     float* g = s->grad;
     const long nY = (long)B * O * T;
     float* dY = s->X0;
-    hipLaunchKernelGGL(k_mse, dim3(256), dim3(256), 0, st, s->Y, Yt, nY, dY, s->part);
+    hipLaunchKernelGGL(k_mse, dim3(256), dim3(256), 0, st, s->Y, Yt, wgt, B, (int)O, (int)T, c.n_rec, dY, s->part);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, s->part, 256, s->lossd, 1.f / (float)nY);
     // frame delays (transposed), then the moment-weighted projection:
     // dQm[b] = dYf[b] Hq[b]^T, dbm[b] = row sums of dYf[b], dHq[b] = Qm[b]^T dYf[b],
@@ -1093,18 +1254,25 @@ void backward(sno* s, hipStream_t st, const float* X, const float* Yt, int B)
         // dUh = dZ G^T
         gemm(st, B, C, K2, T, 1, dZ, T, 1, C * T, 0, s->G, 1, T, 0, 0, s->dUh, K2, 1, C * K2);
         // spectral weights: dRr = dUr Vr^T + dUi Vi^T ; dRi = dUi Vr^T - dUr Vi^T  (per mode, summed over samples)
-        gemm(st, K, C, C, B, 2, s->dUh, K2, C * K2, 1, K, Vh, C * K2, K2, 1, K, g + s->off_Rr[l], C, 1, C * C);
-        gemm(st, K, C, C, B, 1, s->dUh + K, K2, C * K2, 1, 0, Vh, C * K2, K2, 1, 0, g + s->off_Ri[l], C, 1, C * C,
-             1.f, 0.f);
-        gemm(st, K, C, C, B, 1, s->dUh, K2, C * K2, 1, 0, Vh + K, C * K2, K2, 1, 0, g + s->off_Ri[l], C, 1, C * C,
-             -1.f, 1.f);
         // dVr = Rr^T dUr + Ri^T dUi ; dVi = -Ri^T dUr + Rr^T dUi
         const float* Rr = th + s->off_Rr[l];
         const float* Ri = th + s->off_Ri[l];
-        gemm(st, K, C, B, C, 1, Rr, 1, C, C * C, 0, s->dUh, K2, C * K2, 1, 0, s->dVh, K2, C * K2, 1, 1.f, 0.f);
-        gemm(st, K, C, B, C, 1, Ri, 1, C, C * C, 0, s->dUh + K, K2, C * K2, 1, 0, s->dVh, K2, C * K2, 1, 1.f, 1.f);
-        gemm(st, K, C, B, C, 1, Ri, 1, C, C * C, 0, s->dUh, K2, C * K2, 1, 0, s->dVh + K, K2, C * K2, 1, -1.f, 0.f);
-        gemm(st, K, C, B, C, 1, Rr, 1, C, C * C, 0, s->dUh + K, K2, C * K2, 1, 0, s->dVh + K, K2, C * K2, 1, 1.f, 1.f);
+        if (mix_lds(C) <= MIX_LDS_MAX) {
+            hipLaunchKernelGGL(k_cmix_dw, dim3((unsigned)K), dim3(256), (size_t)4 * MIX_B * C * sizeof(float), st,
+                               s->dUh, Vh, B, (int)C, (int)K, g + s->off_Rr[l], g + s->off_Ri[l]);
+            hipLaunchKernelGGL(k_cmix<true>, dim3((unsigned)K), dim3(256), mix_lds(C), st, Rr, Ri, s->dUh, B, (int)C,
+                               (int)K, s->dVh);
+        } else {
+            gemm(st, K, C, C, B, 2, s->dUh, K2, C * K2, 1, K, Vh, C * K2, K2, 1, K, g + s->off_Rr[l], C, 1, C * C);
+            gemm(st, K, C, C, B, 1, s->dUh + K, K2, C * K2, 1, 0, Vh, C * K2, K2, 1, 0, g + s->off_Ri[l], C, 1, C * C,
+                 1.f, 0.f);
+            gemm(st, K, C, C, B, 1, s->dUh, K2, C * K2, 1, 0, Vh + K, C * K2, K2, 1, 0, g + s->off_Ri[l], C, 1, C * C,
+                 -1.f, 1.f);
+            gemm(st, K, C, B, C, 1, Rr, 1, C, C * C, 0, s->dUh, K2, C * K2, 1, 0, s->dVh, K2, C * K2, 1, 1.f, 0.f);
+            gemm(st, K, C, B, C, 1, Ri, 1, C, C * C, 0, s->dUh + K, K2, C * K2, 1, 0, s->dVh, K2, C * K2, 1, 1.f, 1.f);
+            gemm(st, K, C, B, C, 1, Ri, 1, C, C * C, 0, s->dUh, K2, C * K2, 1, 0, s->dVh + K, K2, C * K2, 1, -1.f, 0.f);
+            gemm(st, K, C, B, C, 1, Rr, 1, C, C * C, 0, s->dUh + K, K2, C * K2, 1, 0, s->dVh + K, K2, C * K2, 1, 1.f, 1.f);
+        }
         // dV = W^T dZ + dVh F^T
         gemm(st, B, C, T, C, 1, th + s->off_W[l], 1, C, 0, 0, dZ, T, 1, C * T, 0, dVn, T, 1, C * T);
         gemm(st, B, C, T, K2, 1, s->dVh, K2, 1, C * K2, 0, s->Fb, 1, K2, 0, 0, dVn, T, 1, C * T, 1.f, 1.f);
@@ -1277,14 +1445,15 @@ int sno_forward(sno* s, const float* X, int n, float* Y, void* hip_stream)
     return PSTD_OK;
 }
 
-int sno_gradient(sno* s, const float* X, const float* Yt, int n, float* grad, float* loss, void* hip_stream)
+int sno_gradient_weighted(sno* s, const float* X, const float* Yt, const float* w, int n, float* grad, float* loss,
+                          void* hip_stream)
 {
     if (!s || !X || !Yt || !grad || n < 1) return sfail(PSTD_EINVAL, "bad arguments");
     hipStream_t st = (hipStream_t)hip_stream;
     int rc = s->ensure(n);
     if (rc) return rc;
     forward(s, st, X, n);
-    backward(s, st, X, Yt, n);
+    backward(s, st, X, Yt, n, w);
     S_TRY(hipMemcpyAsync(grad, s->grad, s->np * 4, hipMemcpyDeviceToDevice, st));
     float l = 0.f;
     S_TRY(hipMemcpyAsync(&l, s->lossd, 4, hipMemcpyDeviceToHost, st));
@@ -1292,6 +1461,11 @@ int sno_gradient(sno* s, const float* X, const float* Yt, int n, float* grad, fl
     S_TRY(hipStreamSynchronize(st));
     if (loss) *loss = l;
     return PSTD_OK;
+}
+
+int sno_gradient(sno* s, const float* X, const float* Yt, int n, float* grad, float* loss, void* hip_stream)
+{
+    return sno_gradient_weighted(s, X, Yt, nullptr, n, grad, loss, hip_stream);
 }
 
 int sno_train(sno* s, const float* X, const float* Y, int n, const sno_train_cfg* tc, float* loss_curve,
@@ -1321,6 +1495,16 @@ int sno_train(sno* s, const float* X, const float* Y, int n, const sno_train_cfg
         s->scale[k] = rms > 0 ? (float)rms : 1.f;
     }
     S_TRY(hipMemcpyAsync(s->dscale, s->scale, 16, hipMemcpyHostToDevice, st));
+    // relative loss: per-(sample, component) weights of the fitting samples
+    float* wfit = nullptr;
+    if (tc->rel_loss) {
+        S_TRY(hipMalloc(&wfit, (size_t)n_fit * 4 * sizeof(float)));
+        hipLaunchKernelGGL(k_relw, dim3(n_fit, 4), dim3(256), 0, st, Y, c.n_rec, c.T, s->dscale, wfit);
+    }
+    struct FreeW {
+        float* p;
+        ~FreeW() { (void)hipFree(p); }
+    } free_w{wfit};
     // Adam with cosine learning-rate decay
     std::mt19937_64 rng(tc->seed);
     std::vector<int> order(n_fit);
@@ -1338,8 +1522,10 @@ int sno_train(sno* s, const float* X, const float* Y, int n, const sno_train_cfg
             S_TRY(hipMemcpyAsync(s->idxd, order.data() + (long)it * B, B * sizeof(int), hipMemcpyHostToDevice, st));
             hipLaunchKernelGGL(k_gather, dim3(grid_for((long)B * s->O * c.T)), dim3(256), 0, st, X, Y, s->idxd, B,
                                s->O, c.T, c.n_rec, s->dscale, s->Xb, s->Yb);
+            if (wfit)
+                hipLaunchKernelGGL(k_gather_w, dim3((B * 4 + 255) / 256), dim3(256), 0, st, wfit, s->idxd, B, s->wb);
             forward(s, st, s->Xb, B);
-            backward(s, st, s->Xb, s->Yb, B);
+            backward(s, st, s->Xb, s->Yb, B, wfit ? s->wb : nullptr);
             ++step;
             const double lr = tc->lr * 0.5 * (1.0 + std::cos(M_PI * (double)(step - 1) / (double)std::max(1L, total)));
             const float c1 = (float)(1.0 - std::pow(0.9, (double)step));

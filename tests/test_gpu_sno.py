@@ -97,6 +97,35 @@ def test_gradient_matches_oracle(B, d):
         o += n
 
 
+def test_weighted_gradient_matches_oracle(B):
+    """The relative loss's per-(sample, component) weights (targets of very
+    different amplitudes, weights 1 / mean square): loss and gradient of every
+    parameter block against the oracle's weighted loss."""
+    import torch
+    d = SMALL
+    rng = np.random.default_rng(4)
+    theta = init(d, 2) + 0.05 * rng.standard_normal(osno.n_params(d))
+    theta = theta.astype(np.float32).astype(np.float64)
+    X = rng.uniform(-1, 1, (4, 9))
+    Yt = rng.standard_normal((4, d.O, d.T)) * rng.uniform(0.05, 20.0, (4, d.O, 1))
+    w = osno.relative_weights(Yt, d)
+    ref = osno.grad(theta, X, Yt, d, w=w)
+    s = make(B, d, theta)
+    g, loss = s.gradient(torch.tensor(X, dtype=torch.float32, device="cuda"),
+                         torch.tensor(Yt, dtype=torch.float32, device="cuda"),
+                         w=torch.tensor(w, dtype=torch.float32, device="cuda"))
+    g = g.cpu().numpy()
+    lref = osno.loss(theta, X, Yt, d, w=w)
+    assert abs(loss - lref) < 2e-2 * lref
+    o = 0
+    for name, sh in osno.param_shapes(d):
+        n = int(np.prod(sh))
+        e = rel(g[o:o + n], ref[o:o + n])
+        say(f"  weighted grad {name}: rel-L2 {e:.2e}")
+        assert e < 2e-2, name
+        o += n
+
+
 def test_training_reduces_loss_on_a_teacher(B):
     """Targets from a fixed random network of the same family: training the
     student must cut the loss by a large factor."""

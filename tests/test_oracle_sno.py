@@ -80,6 +80,50 @@ def test_gradient_matches_finite_differences(D):
     assert o == theta.size
 
 
+D_W = osno.Dims(n_pos=3, n_mt=6, four=(3.0, 7.5), C=4, T=32, K=5, L=2, H=6, O=8)
+
+
+def test_weighted_gradient_matches_finite_differences():
+    """Per-(sample, component) loss weights: the gradient still equals
+    central finite differences of the weighted loss."""
+    rng = np.random.default_rng(6)
+    d = D_W
+    theta = init(d, 3) + 0.05 * rng.standard_normal(osno.n_params(d))
+    src = rng.standard_normal((2, d.n_pos + d.n_mt))
+    y = rng.standard_normal((2, d.O, d.T))
+    w = rng.uniform(0.2, 5.0, (2, 4))
+    g = osno.grad(theta, src, y, d, w=w)
+    h = 1e-6
+    for i in rng.choice(theta.size, 60, replace=False):
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (osno.loss(tp, src, y, d, w=w) - osno.loss(tm, src, y, d, w=w)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (i, fd, g[i])
+    # unit weights are the plain loss
+    assert osno.loss(theta, src, y, d, w=np.ones((2, 4))) == pytest.approx(osno.loss(theta, src, y, d), rel=1e-14)
+
+
+def test_relative_weights_give_the_mean_squared_relative_error():
+    """With w = 1 / mean square of each target component the weighted loss is
+    the mean over samples and components of ||Y - y||^2 / ||y||^2 (receivers
+    of a component are the O / 4 consecutive outputs)."""
+    rng = np.random.default_rng(7)
+    d = D_W
+    theta = init(d, 3) + 0.05 * rng.standard_normal(osno.n_params(d))
+    src = rng.standard_normal((3, d.n_pos + d.n_mt))
+    y = rng.standard_normal((3, d.O, d.T)) * rng.uniform(0.01, 100.0, (3, d.O, 1))
+    w = osno.relative_weights(y, d)
+    Y = osno.forward(theta, src, d)
+    n_rec = d.O // 4
+    rel = [np.linalg.norm(Y[b, c * n_rec:(c + 1) * n_rec] - y[b, c * n_rec:(c + 1) * n_rec]) ** 2 /
+           np.linalg.norm(y[b, c * n_rec:(c + 1) * n_rec]) ** 2 for b in range(3) for c in range(4)]
+    assert osno.loss(theta, src, y, d, w=w) == pytest.approx(np.mean(rel), rel=1e-12)
+    z = y.copy()
+    z[1, 2 * n_rec:3 * n_rec] = 0.0
+    assert osno.relative_weights(z, d)[1, 2] == 0.0
+
+
 def test_adam_first_step():
     theta = np.array([1.0, -2.0, 0.5])
     g = np.array([0.3, -1e-3, 2.0])
