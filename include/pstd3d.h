@@ -259,7 +259,9 @@ const char *pstd3d_last_error(void);
  * event and record segment of up to 6144 samples) go to a device buffer
  * allocated and freed by the call; runs on hip_stream and returns after the
  * stream has finished.  Errors: PSTD_EINVAL (sizes, dt_out / dt_in outside
- * [2^-20, 2^20], source index out of range, non-finite value), PSTD_ENOMEM,
+ * [2^-20, 2^20], source index out of range, non-finite value, more than 2^23
+ * record segments in one call: 4 n_rec rounded up to a multiple of 8, times
+ * ceil(nt_out / 6144)), PSTD_ENOMEM,
  * PSTD_EDEVICE; the message is returned by seis_combine_last_error(). */
 int seis_combine(const float *tr, int n_src, int n_rec, int nt_in, double dt_in, const double t0[4],
                  int n_ev, const int32_t *src_idx, const double *amp, const double *t_origin,

@@ -134,20 +134,40 @@ void make_plan(Plan& p, int n_ev, const int32_t* src_idx, const double* amp, con
     p.bytes = p.off_ev + align256(std::max<size_t>(1, p.ev.size()) * sizeof(Ev));
 }
 
+// Block -> (segment, receiver, component).  The chip hands consecutive
+// blocks to its 8 XCDs in turn, each with its own L2, so the segments of one
+// output row (which stage the same source rows) are given block indices 8
+// apart: the same XCD, one after the other.  Rows are (c, r) with c slowest;
+// blocks past the last row exit.
+constexpr int XCDS = 8;
+
+__device__ __forceinline__ bool block_row(int nseg, int n_rec, int& seg, int& r, int& c)
+{
+    const int L = blockIdx.x;
+    const int g = L / (XCDS * nseg), l = L - g * XCDS * nseg;
+    seg = l / XCDS;
+    const int row = g * XCDS + (l - seg * XCDS);
+    if (row >= 4 * n_rec) return false;
+    c = row / n_rec;
+    r = row - c * n_rec;
+    return true;
+}
+
+inline unsigned row_blocks(int nseg, int n_rec) { return (unsigned)((4 * n_rec + XCDS - 1) / XCDS * XCDS * nseg); }
+
 // values of the staging buffer each thread loads
 constexpr int NPT = (STG + 2 + CT - 1) / CT;
 // samples whose positions, loads and sums go together (the loads of a half
 // are all issued before the first wait)
 constexpr int HALF = SPT / 2;
 
-__global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(8))) void k_combine(const float* __restrict__ tr, int n_rec, int nt_in, double ratio,
+__global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(8))) void k_combine(const float* __restrict__ tr, int nseg, int n_rec, int nt_in, double ratio,
                                                 long long ratio_fx, const char* __restrict__ plan, long off_grp,
                                                 long off_ev, int seg_len, int nt_out, float* __restrict__ out)
 {
     __shared__ float stg[STG + 2];
-    const int seg = blockIdx.x;
-    const int r = blockIdx.y;
-    const int c = blockIdx.z;
+    int seg, r, c;
+    if (!block_row(nseg, n_rec, seg, r, c)) return;
     const int tid = threadIdx.x;
     const int s0 = seg * seg_len;
     const int s1 = min(s0 + seg_len, nt_out);
@@ -253,14 +273,13 @@ __host__ __device__ constexpr int w_slot(int nt_in) { return nt_in + 4; }
 
 template <int VPS>
 __global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(8))) void k_combine_w(
-    const float* __restrict__ tr, int n_rec, int nt_in, double ratio, unsigned long long ratio_fx,
+    const float* __restrict__ tr, int nseg, int n_rec, int nt_in, double ratio, unsigned long long ratio_fx,
     const char* __restrict__ plan, long off_grp, long off_ev, int seg_len, int nt_out, float* __restrict__ out)
 {
     constexpr int NSLOT = WPT / VPS;
     extern __shared__ float stw[];   // NSLOT slots of w_slot(nt_in) floats
-    const int seg = blockIdx.x;
-    const int r = blockIdx.y;
-    const int c = blockIdx.z;
+    int seg, r, c;
+    if (!block_row(nseg, n_rec, seg, r, c)) return;
     const int tid = threadIdx.x;
     const int L = w_slot(nt_in);
     const int s0 = seg * seg_len;
@@ -371,6 +390,13 @@ int check_args(const float* tr, int n_src, int n_rec, int nt_in, double dt_in, c
     if (!(dt_out / dt_in <= 1048576.0) || !(dt_out / dt_in >= 1.0 / 1048576.0))
         return cfail(PSTD_EINVAL, "seis_combine: dt_out / dt_in outside [2^-20, 2^20]");
     if (n_rec == 0 || nt_out == 0) return PSTD_OK;
+    {
+        // one 1-D launch: blocks x threads must stay below 2^32 work-items
+        const long long rows = (4LL * n_rec + XCDS - 1) / XCDS * XCDS;
+        const long long nseg = ((long long)nt_out + SEG_MAX - 1) / SEG_MAX;
+        if (rows * nseg * CT >= (1LL << 32))
+            return cfail(PSTD_EINVAL, "seis_combine: output too large for one call (split the receivers)");
+    }
     if (!tr || !out || (n_ev > 0 && (!src_idx || !amp || !t_origin)))
         return cfail(PSTD_EINVAL, "seis_combine: null pointer");
     for (int e = 0; e < n_ev; ++e) {
@@ -400,20 +426,21 @@ int launch(const Plan& p, char* dplan, const float* tr, int n_rec, int nt_in, do
         const double ratio = dt_out / dt_in;
         const long long ratio_fx = (long long)std::llround(ratio * 4294967296.0);
         const int L = w_slot(nt_in);
-        const dim3 grid(p.nseg, n_rec, 4);
+        const dim3 grid(row_blocks(p.nseg, n_rec));
         const unsigned long long rfx = (unsigned long long)ratio_fx;
         const long og = (long)p.off_grp, oe = (long)p.off_ev;
         if (L <= CT) {
-            hipLaunchKernelGGL(k_combine_w<1>, grid, dim3(CT), (size_t)(WPT / 1) * L * sizeof(float), st, tr, n_rec,
-                               nt_in, ratio, rfx, dplan, og, oe, p.seg_len, nt_out, out);
+            hipLaunchKernelGGL(k_combine_w<1>, grid, dim3(CT), (size_t)(WPT / 1) * L * sizeof(float), st, tr, p.nseg,
+                               n_rec, nt_in, ratio, rfx, dplan, og, oe, p.seg_len, nt_out, out);
         } else if (L <= 2 * CT) {
-            hipLaunchKernelGGL(k_combine_w<2>, grid, dim3(CT), (size_t)(WPT / 2) * L * sizeof(float), st, tr, n_rec,
-                               nt_in, ratio, rfx, dplan, og, oe, p.seg_len, nt_out, out);
+            hipLaunchKernelGGL(k_combine_w<2>, grid, dim3(CT), (size_t)(WPT / 2) * L * sizeof(float), st, tr, p.nseg,
+                               n_rec, nt_in, ratio, rfx, dplan, og, oe, p.seg_len, nt_out, out);
         } else if (L <= 4 * CT) {
-            hipLaunchKernelGGL(k_combine_w<4>, grid, dim3(CT), (size_t)(WPT / 4) * L * sizeof(float), st, tr, n_rec,
-                               nt_in, ratio, rfx, dplan, og, oe, p.seg_len, nt_out, out);
+            hipLaunchKernelGGL(k_combine_w<4>, grid, dim3(CT), (size_t)(WPT / 4) * L * sizeof(float), st, tr, p.nseg,
+                               n_rec, nt_in, ratio, rfx, dplan, og, oe, p.seg_len, nt_out, out);
         } else {
-            hipLaunchKernelGGL(k_combine, dim3(p.nseg, n_rec, 4), dim3(CT), 0, st, tr, n_rec, nt_in, ratio, ratio_fx,
+            hipLaunchKernelGGL(k_combine, dim3(row_blocks(p.nseg, n_rec)), dim3(CT), 0, st, tr, p.nseg, n_rec, nt_in,
+                               ratio, ratio_fx,
                                dplan, (long)p.off_grp, (long)p.off_ev, p.seg_len, nt_out, out);
         }
         ok = hipGetLastError() == hipSuccess;
