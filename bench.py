@@ -47,7 +47,7 @@ MEASURED_TRAFFIC = {
 # the same for seis_combine's kernel (its own source file): bytes per launch on the
 # bench's combine workload
 COMBINE_SOURCES = ["paper_1705_04874_amd/csrc/combine.hip"]
-COMBINE_TRAFFIC = {"source_digest": "e2fd5f9f79465f88", "bytes": 9215.7e6}
+COMBINE_TRAFFIC = {"source_digest": "6aaa4c8f062afc5c", "bytes": 9526.5e6}
 
 
 def kernel_source_digest(files=KERNEL_SOURCES):
@@ -372,9 +372,11 @@ def bench_combine(args, binding, inputs, torch):
     used = sorted(set(int(v) for v in ev.src_idx))
     alg = len(used) * 4 * n_rec * nt_in * 4 + 4 * n_rec * nt_out * 4
     # event-samples: output samples m of each (event, component) whose input
-    # position lies inside the trace, over every receiver; a lane spends about
-    # 10 vector instructions on each, and a CU issues one wave64 instruction
-    # (64 lanes) per cycle: 256 CUs at 2.4 GHz bound the kernel's arithmetic
+    # position lies inside the trace, over every receiver; a lane spends 9
+    # vector instructions on each (position add, clamp, address, fraction
+    # convert and scale, difference, lerp, conversion to double, double fma:
+    # the kernel's inner loop), and a CU issues one wave64 instruction (64
+    # lanes) per cycle: 256 CUs at 2.4 GHz bound the kernel's arithmetic
     dt_out = 1e-3
     m = np.arange(nt_out)
     ev_samples = 0
@@ -383,7 +385,7 @@ def bench_combine(args, binding, inputs, torch):
             u = m * (dt_out / dt_in) - (to + t0[c]) / dt_in
             ev_samples += int(np.count_nonzero((u > -1.0) & (u < nt_in)))
     ev_samples *= n_rec
-    alu_ms = ev_samples * 10 / (256 * 64 * 2.4e9) * 1e3
+    alu_ms = ev_samples * 9 / (256 * 64 * 2.4e9) * 1e3
     traffic = COMBINE_TRAFFIC["bytes"] if COMBINE_TRAFFIC["source_digest"] == kernel_source_digest(COMBINE_SOURCES) else None
     out = {
         "metric": "seis_combine GB/s (algorithmic bytes)", "value": round(alg / (ms * 1e-3) / 1e9, 1),
@@ -398,9 +400,9 @@ def bench_combine(args, binding, inputs, torch):
                      "timing": "HIP events on the call's stream (includes the event-list upload)"},
         "kernel_ms": round(ms, 3), "call_wall_ms": round(wall * 1e3, 3),
         "sources_used": len(used),
-        "alu_issue": {"event_samples": ev_samples, "instructions_per_event_sample": 10,
+        "alu_issue": {"event_samples": ev_samples, "instructions_per_event_sample": 9,
                       "bound_ms": round(alu_ms, 3), "frac": round(alu_ms / ms, 3),
-                      "basis": "10 vector instructions per event-sample and lane, one wave64 instruction per cycle per CU, 256 CUs at 2.4 GHz"},
+                      "basis": "9 vector instructions per event-sample and lane, one wave64 instruction per cycle per CU, 256 CUs at 2.4 GHz"},
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -4,34 +4,36 @@
 // the linear interpolation of trace src_idx[e] (zero outside its samples).
 //
 // One block owns one output row (component c, receiver r) over a segment of
-// the record; each thread owns SPT consecutive output samples and keeps their
-// sums in registers in double precision.  The events that can touch the
-// segment are grouped by source on the host (sources ascending, event order
-// within a source), so the block stages each source's input row in LDS once
-// and applies all of that source's events from there: every input trace is
-// read from HBM once per segment and the record is written once.  A thread
-// skips an event whose sample range (precomputed on the host per event and
-// component) misses its samples, so the per-event cost falls on the few
-// waves an event touches.
+// the record and keeps the segment's sums in registers in double precision.
+// The events that can touch the segment are grouped by source on the host
+// (sources ascending, event order within a source), so the block stages each
+// source's input row in LDS once and applies all of that source's events
+// from there: every input trace is read from HBM once per segment and the
+// record is written once.
 //
 // Two kernels share that scheme.  When a whole input trace fits a slot of the
 // staging buffer (nt_in + 4 values, two zeros on each side; up to 4 CT),
 // k_combine_w stages the rows of several sources between one pair of
 // barriers and clamps each sample's index into its slot (an index outside
 // the trace lands on the two zero pads at either end, so no sample needs a
-// range test).  Longer traces go through k_combine, which stages one source
-// at a time in chunks of STG samples and tests every sample against the
-// chunk.  Blocks of 512 threads (segments of 6144 samples) measured faster
-// than 1024: fewer waves wait at each item's barriers for the busiest one.
+// range test).  Its threads own output samples in groups of GQ spread over
+// the segment (below), and the host marks per event and component the
+// windows of samples it touches, so a wave spends lanes only where an event
+// is.  Longer traces go through k_combine, whose threads own SPT consecutive
+// samples and which stages one source at a time in chunks of STG samples and
+// tests every sample against the chunk.  Blocks of 512 threads (segments of
+// 6144 samples) measured faster than 1024: fewer waves wait at each item's
+// barriers for the busiest one.
 //
-// The input position of a sample is u = m (dt_out / dt_in) - (t_origin + t0)/dt_in:
-// for a thread's first sample one fused multiply-add in double from the
-// per-event offset computed on the host, then in 32.32 fixed point, each next
-// sample adding the ratio in integers (its rounding, 2^-33 of a sample, grows
-// by that much per sample).  The integer part picks the two input samples, the
-// fraction f is the interpolation weight, the lerp x0 + f (x1 - x0) is formed
-// in float (the inputs are float) and added to the double sum.  The lerp is
-// continuous in u, so the rounding of u moves the result by as little.
+// The input position of a sample is u = m (dt_out / dt_in) - (t_origin + t0)/dt_in,
+// kept in 32.32 fixed point: the host converts each event's offset
+// -(t_origin + t0)/dt_in, a thread converts m (dt_out / dt_in) of its first
+// sample once (in double), and each next sample adds the ratio in integers
+// (its rounding, 2^-33 of a sample, grows by that much per sample).  The
+// integer part picks the two input samples, the fraction f is the
+// interpolation weight, the lerp x0 + f (x1 - x0) is formed in float (the
+// inputs are float) and added to the double sum.  The lerp is continuous in
+// u, so the rounding of u moves the result by as little.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -48,21 +50,42 @@ constexpr int CT = 512;            // threads per block
 constexpr int SPT = 12;            // output samples per thread
 constexpr int SEG_MAX = CT * SPT;  // output samples per segment
 constexpr int STG = 4096;          // input samples staged per chunk (plus one before and one after)
+// Output samples of k_combine_w go to threads in groups of GQ: group j of
+// thread t holds samples s0 + j GSPAN + t GQ + q, q < GQ, so one wave's group
+// j covers WSPAN consecutive samples (a window) and its groups lie GSPAN apart.
+constexpr int GQ = 4;
+constexpr int NGRP = SPT / GQ;
+constexpr int GSPAN = CT * GQ;
+constexpr int WSPAN = 64 * GQ;
+constexpr int NWAVE = CT / 64;
+static_assert(NWAVE * NGRP <= 32, "one bit per window of a segment");
 
 // per-segment work list: groups of events sharing a source
 struct Grp {
-    int src;
-    int e0, e1;    // events [e0, e1) of the plan's event array
-    int pad;
+    long long src_off;   // offset of the source's traces in tr: src 4 n_rec nt_in floats
+    int e0, e1;          // events [e0, e1) of the plan's event array
 };
 // one event of a segment: amplitude, and per component the input offset
 // (t_origin + t0[c]) / dt_in and the output samples [rng[c][0], rng[c][1])
 // it can touch
 struct Ev {
     double amp;
-    double be[4];
+    unsigned long long u0[4];   // -(t_origin + t0[c]) / dt_in, 32.32 fixed point
     int rng[4][2];
+    unsigned win[4];            // windows of the segment the event touches, bit w NGRP + j
 };
+
+// x in 32.32 fixed point modulo 2^64 (two's complement): the integer part in
+// the high word, the fraction truncated to 32 bits in the low word.  |x| is
+// clamped to 2^52 (a position that far out is never inside a trace, and the
+// event ranges keep such positions away from the kernels).
+__host__ __device__ inline unsigned long long to_fx(double x)
+{
+    x = fmin(fmax(x, -4503599627370496.0), 4503599627370496.0);
+    const double fl = floor(x);
+    const double fr = fmin(floor((x - fl) * 4294967296.0), 4294967295.0);
+    return ((unsigned long long)(long long)fl << 32) + (unsigned long long)fr;
+}
 
 // Host-side lists of one call: per segment the source groups, per group its
 // events.  The arrays go to the device back to back (offsets in bytes).
@@ -76,11 +99,25 @@ struct Plan {
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
+// bit w NGRP + j set where window j of wave w, [s0 + j GSPAN + w WSPAN, +
+// WSPAN), meets the samples [lo, min(hi, s1)) of the segment [s0, s1)
+unsigned window_mask(int lo, int hi, int s0, int s1)
+{
+    hi = std::min(hi, s1);
+    unsigned m = 0;
+    for (int w = 0; w < NWAVE; ++w)
+        for (int j = 0; j < NGRP; ++j) {
+            const int a = s0 + j * GSPAN + w * WSPAN;
+            if (lo < a + WSPAN && hi > a) m |= 1u << (w * NGRP + j);
+        }
+    return m;
+}
+
 // Build the work lists.  An event can touch output sample m of component c
 // only if u(m) lies in (-1, nt_in); that sample range is widened by one
 // sample on each side (the kernel decides each sample exactly, a superset
 // only costs a skipped iteration).
-void make_plan(Plan& p, int n_ev, const int32_t* src_idx, const double* amp, const double* t_origin,
+void make_plan(Plan& p, int n_rec, int n_ev, const int32_t* src_idx, const double* amp, const double* t_origin,
                const double t0[4], int nt_in, double dt_in, int nt_out, double dt_out)
 {
     p.nseg = (nt_out + SEG_MAX - 1) / SEG_MAX;
@@ -93,10 +130,11 @@ void make_plan(Plan& p, int n_ev, const int32_t* src_idx, const double* amp, con
         E.amp = amp[e];
         double lo_all = 1e300, hi_all = -1e300;
         for (int c = 0; c < 4; ++c) {
-            E.be[c] = (t_origin[e] + t0[c]) / dt_in;
+            const double be = (t_origin[e] + t0[c]) / dt_in;
+            E.u0[c] = to_fx(-be);
             // clamped in double first: the offset may be far outside the record
-            const double lo = std::max(0.0, std::floor((E.be[c] - 1.0) / ratio) - 1.0);
-            const double hi = std::min((double)nt_out, std::ceil(((double)nt_in + E.be[c]) / ratio) + 2.0);
+            const double lo = std::max(0.0, std::floor((be - 1.0) / ratio) - 1.0);
+            const double hi = std::min((double)nt_out, std::ceil(((double)nt_in + be) / ratio) + 2.0);
             E.rng[c][0] = (int)std::min(lo, (double)nt_out);
             E.rng[c][1] = hi > lo ? (int)hi : E.rng[c][0];
             if (E.rng[c][1] > E.rng[c][0]) {
@@ -120,8 +158,13 @@ void make_plan(Plan& p, int n_ev, const int32_t* src_idx, const double* amp, con
         for (size_t i = 0; i < L.size();) {
             size_t j = i;
             while (j < L.size() && src_idx[L[j]] == src_idx[L[i]]) ++j;
-            Grp g{src_idx[L[i]], (int)p.ev.size(), 0, 0};
-            for (size_t k = i; k < j; ++k) p.ev.push_back(all[L[k]]);
+            Grp g{(long long)src_idx[L[i]] * 4 * n_rec * nt_in, (int)p.ev.size(), 0};
+            for (size_t k = i; k < j; ++k) {
+                Ev E = all[L[k]];
+                const int s0 = s * p.seg_len, s1 = std::min(s0 + p.seg_len, nt_out);
+                for (int c = 0; c < 4; ++c) E.win[c] = window_mask(E.rng[c][0], E.rng[c][1], s0, s1);
+                p.ev.push_back(E);
+            }
             g.e1 = (int)p.ev.size();
             p.grp.push_back(g);
             i = j;
@@ -176,6 +219,8 @@ __global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(8))) void k_
     const int* __restrict__ seg_ptr = reinterpret_cast<const int*>(plan);
     const Grp* __restrict__ grp = reinterpret_cast<const Grp*>(plan + off_grp);
     const Ev* __restrict__ ev = reinterpret_cast<const Ev*>(plan + off_ev);
+    // this block's row (c, r) of source 0; a group adds its source's offset
+    const float* __restrict__ rowp = tr + ((long)c * n_rec + r) * nt_in;
     double acc[SPT];
 #pragma unroll
     for (int k = 0; k < SPT; ++k) acc[k] = 0.0;
@@ -193,7 +238,7 @@ __global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(8))) void k_
         const int g = g0 + item / nchunk, q = item % nchunk;
         const int a = q * STG - 1;
         const int b = q == nchunk - 1 ? nt_in : a + STG;
-        const float* __restrict__ x = tr + (((long)grp[g].src * 4 + c) * n_rec + r) * nt_in;
+        const float* __restrict__ x = rowp + grp[g].src_off;
 #pragma unroll
         for (int j = 0; j < NPT; ++j) {
             const int i = tid + j * CT, k = a + i;
@@ -220,9 +265,10 @@ __global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(8))) void k_
             if (!active || hi <= m0 || lo >= m0 + SPT) continue;
             const double amp = E.amp;
             // position of this thread's first sample in 32.32 fixed point
-            // (from double; each later sample adds ratio exactly in integers,
-            // 2^-32 of a sample per step), integer part = left neighbour
-            const double u0 = fma(md, ratio, -E.be[c]);
+            // (from double: m0 (dt_out / dt_in) plus the event's offset; each
+            // later sample adds the ratio in integers, 2^-32 of a sample per
+            // step), integer part = left neighbour
+            const double u0 = fma(md, ratio, (double)(long long)E.u0[c] * 2.3283064365386963e-10);
             const double fl0 = floor(u0);
             long long u = ((long long)fl0 << 32) + (long long)((u0 - fl0) * 4294967296.0);
 #pragma unroll
@@ -261,55 +307,86 @@ __global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(8))) void k_
 }
 
 // Whole-trace staging: a slot holds a source row x[-2 .. nt_in + 1] (zeros
-// outside the trace), nt_in + 4 values, of which each thread loads VPS (so a
-// slot is at most VPS * CT values, VPS = 1, 2 or 4); an item is
-// NSLOT(VPS) = WPT / VPS slots, staged from WPT registers per thread (32 KB
-// of LDS).
+// outside the trace), nt_in + 4 values, in VPS CT floats of which each thread
+// writes VPS (VPS = 1, 2 or 4: the smallest with nt_in + 4 <= VPS CT); an item
+// is NSLOT(VPS) = WPT / VPS slots, staged from WPT registers per thread
+// (16 KB of LDS).  The loads are buffer loads whose range is the trace, so
+// the positions outside it read zero and staging needs no branch, clamp or
+// select.
+//
+// Output samples go to threads in the groups of GQ described above; the
+// host marks per event and component the windows it touches (one bit each),
+// and a wave computes only its marked windows.  An event then spends lanes
+// on at most one partly covered window of WSPAN samples at either end, where
+// runs of SPT samples per thread would waste up to a wave's 64 SPT, and a
+// wave that the event misses pays one scalar test for it.
 constexpr int WPT = 8;
-// samples whose loads are issued together
-constexpr int QTR = SPT / 3;
+// buffer resource word 3 for raw 32-bit loads on this chip family
+constexpr int BUF_DW3 = 0x00020000;
+
+// fixed-point position of group j's first sample relative to the thread's
+// first, plus the slot's two leading pads: to_fx(j GSPAN ratio + 2)
+struct GroupPos {
+    unsigned long long d[NGRP];
+};
 
 __host__ __device__ constexpr int w_slot(int nt_in) { return nt_in + 4; }
 
 template <int VPS>
 __global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(8))) void k_combine_w(
     const float* __restrict__ tr, int nseg, int n_rec, int nt_in, double ratio, unsigned long long ratio_fx,
-    const char* __restrict__ plan, long off_grp, long off_ev, int seg_len, int nt_out, float* __restrict__ out)
+    GroupPos gp, const char* __restrict__ plan, long off_grp, long off_ev, int seg_len, int nt_out,
+    float* __restrict__ out)
 {
     constexpr int NSLOT = WPT / VPS;
-    extern __shared__ float stw[];   // NSLOT slots of w_slot(nt_in) floats
+    constexpr int S = VPS * CT;      // floats per slot
+    extern __shared__ float stw[];   // NSLOT slots of S floats
     int seg, r, c;
     if (!block_row(nseg, n_rec, seg, r, c)) return;
     const int tid = threadIdx.x;
     const int L = w_slot(nt_in);
     const int s0 = seg * seg_len;
     const int s1 = min(s0 + seg_len, nt_out);
-    const int m0 = s0 + tid * SPT;
-    const bool active = m0 < s1;
+    // this wave's bits in the events' window masks (uniform across the wave)
+    const int wsh = (__builtin_amdgcn_readfirstlane(tid) / 64) * NGRP;
     const int* __restrict__ seg_ptr = reinterpret_cast<const int*>(plan);
     const Grp* __restrict__ grp = reinterpret_cast<const Grp*>(plan + off_grp);
     const Ev* __restrict__ ev = reinterpret_cast<const Ev*>(plan + off_ev);
+    // this block's row (c, r) of source 0; a group adds its source's offset
+    const float* __restrict__ rowp = tr + ((long)c * n_rec + r) * nt_in;
     double acc[SPT];
 #pragma unroll
     for (int k = 0; k < SPT; ++k) acc[k] = 0.0;
     const int g0 = seg_ptr[seg], g1 = seg_ptr[seg + 1];
+    // (s0 + t GQ) (dt_out / dt_in) in fixed point; an event adds its offset
+    const unsigned long long T = to_fx((double)(s0 + tid * GQ) * ratio);
     // Item q stages the rows of groups [g0 + q NSLOT, g0 + (q + 1) NSLOT); the
     // next item's values are loaded into registers while this one is computed.
     const int nitems = (g1 - g0 + NSLOT - 1) / NSLOT;
-    const double md = (double)m0;
+    // slot position tid + v CT holds x[tid + v CT - 2]: buffer loads with the
+    // trace as the buffer's range return zero outside it (a negative offset
+    // is out of range as an unsigned value)
     float pre[WPT];
+    // byte offsets of x[tid - 2] and x[tid + 2 CT - 2]; the other loads add
+    // constants that fit the instructions' offset field
+    const int o0 = (tid - 2) * 4, o2 = o0 + 2 * CT * 4;
     auto fetch = [&](int item) {
+        // opaque copies, so the per-load constants stay in the loads'
+        // offset fields rather than in registers set up outside the loop
+        int b0 = o0, b2 = o2;
+        asm volatile("" : "+v"(b0), "+v"(b2));
         const int gb = g0 + item * NSLOT;
 #pragma unroll
         for (int sl = 0; sl < NSLOT; ++sl) {
-            const int g = gb + sl;
-            const float* __restrict__ x =
-                g < g1 ? tr + (((long)grp[g].src * 4 + c) * n_rec + r) * nt_in : tr;
+            // a slot past the item's last group is loaded from that group
+            // and never read
+            const int g = min(gb + sl, g1 - 1);
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc((void*)(rowp + grp[g].src_off), (short)0, nt_in * 4, BUF_DW3);
 #pragma unroll
-            for (int v = 0; v < VPS; ++v) {
-                const int xi = tid + v * CT - 2;   // slot position tid + v CT holds x[xi]
-                pre[sl * VPS + v] = (g < g1 && xi >= 0 && xi < nt_in) ? x[xi] : 0.0f;
-            }
+            for (int v = 0; v < VPS; ++v)
+                pre[sl * VPS + v] = __uint_as_float(
+                    __builtin_amdgcn_raw_buffer_load_b32(rs, (v < 2 ? b0 : b2) + (v & 1) * CT * 4, 0, 0));
         }
     };
     if (nitems > 0) fetch(0);
@@ -318,58 +395,57 @@ __global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(8))) void k_
 #pragma unroll
         for (int sl = 0; sl < NSLOT; ++sl)
 #pragma unroll
-            for (int v = 0; v < VPS; ++v) {
-                const int k = tid + v * CT;
-                if (k < L) stw[sl * L + k] = pre[sl * VPS + v];
-            }
+            for (int v = 0; v < VPS; ++v) stw[sl * S + tid + v * CT] = pre[sl * VPS + v];
         __syncthreads();
         if (item + 1 < nitems) fetch(item + 1);
         const int gb = g0 + item * NSLOT;
         const int ng = min(NSLOT, g1 - gb);
         for (int gi = 0; gi < ng; ++gi) {
             const Grp G = grp[gb + gi];
-            const float* __restrict__ x = stw + gi * L;
+            const float* __restrict__ x = stw + gi * S;
             for (int e = G.e0; e < G.e1; ++e) {
                 const Ev& E = ev[e];
-                const int lo = E.rng[c][0], hi = E.rng[c][1];
-                if (!active || hi <= m0 || lo >= m0 + SPT) continue;
+                // this wave's windows that the event touches
+                const unsigned wm = (E.win[c] >> wsh) & ((1u << NGRP) - 1);
+                if (!wm) continue;
                 const double amp = E.amp;
-                // slot index of this thread's first sample (x[i] sits at i + 2)
-                // in 32.32 fixed point
-                const double u0 = fma(md, ratio, 2.0 - E.be[c]);
-                const double fl0 = floor(u0);
-                unsigned long long u = ((unsigned long long)(unsigned)(int)fl0 << 32) |
-                                       (unsigned long long)(unsigned)((u0 - fl0) * 4294967296.0);
+                const unsigned long long ue = T + E.u0[c];
 #pragma unroll
-                for (int h = 0; h < SPT; h += QTR) {
-                    int idx[QTR];
-                    float fr[QTR];
+                for (int j = 0; j < NGRP; ++j) {
+                    if (!(wm >> j & 1)) continue;
+                    unsigned long long u = ue + gp.d[j];
+                    int idx[GQ];
+                    float fr[GQ];
 #pragma unroll
-                    for (int k = 0; k < QTR; ++k) {
+                    for (int q = 0; q < GQ; ++q) {
                         // clamped into [0, L - 2] as unsigned (a negative index
                         // becomes L - 2): an index outside the trace reads two
                         // of the zero pads
-                        idx[k] = (int)min((unsigned)(u >> 32), (unsigned)(L - 2));
-                        fr[k] = (float)(unsigned)u * 2.3283064365386963e-10f;
+                        idx[q] = (int)min((unsigned)(u >> 32), (unsigned)(L - 2));
+                        fr[q] = (float)(unsigned)u * 2.3283064365386963e-10f;
                         u += ratio_fx;
                     }
-                    float x0[QTR], x1[QTR];
+                    float x0[GQ], x1[GQ];
 #pragma unroll
-                    for (int k = 0; k < QTR; ++k) {
-                        x0[k] = x[idx[k]];
-                        x1[k] = x[idx[k] + 1];
+                    for (int q = 0; q < GQ; ++q) {
+                        x0[q] = x[idx[q]];
+                        x1[q] = x[idx[q] + 1];
                     }
 #pragma unroll
-                    for (int k = 0; k < QTR; ++k)
-                        acc[h + k] = fma(amp, (double)fmaf(fr[k], x1[k] - x0[k], x0[k]), acc[h + k]);
+                    for (int q = 0; q < GQ; ++q)
+                        acc[j * GQ + q] = fma(amp, (double)fmaf(fr[q], x1[q] - x0[q], x0[q]), acc[j * GQ + q]);
                 }
             }
         }
     }
     float* __restrict__ o = out + ((long)c * n_rec + r) * nt_out;
 #pragma unroll
-    for (int k = 0; k < SPT; ++k)
-        if (m0 + k < s1) o[m0 + k] = (float)acc[k];
+    for (int j = 0; j < NGRP; ++j)
+#pragma unroll
+        for (int q = 0; q < GQ; ++q) {
+            const int m = s0 + j * GSPAN + tid * GQ + q;
+            if (m < s1) o[m] = (float)acc[j * GQ + q];
+        }
 }
 
 thread_local std::string g_cerr;
@@ -429,15 +505,17 @@ int launch(const Plan& p, char* dplan, const float* tr, int n_rec, int nt_in, do
         const dim3 grid(row_blocks(p.nseg, n_rec));
         const unsigned long long rfx = (unsigned long long)ratio_fx;
         const long og = (long)p.off_grp, oe = (long)p.off_ev;
+        GroupPos gp;
+        for (int j = 0; j < NGRP; ++j) gp.d[j] = to_fx((double)j * GSPAN * ratio + 2.0);
         if (L <= CT) {
-            hipLaunchKernelGGL(k_combine_w<1>, grid, dim3(CT), (size_t)(WPT / 1) * L * sizeof(float), st, tr, p.nseg,
-                               n_rec, nt_in, ratio, rfx, dplan, og, oe, p.seg_len, nt_out, out);
+            hipLaunchKernelGGL(k_combine_w<1>, grid, dim3(CT), (size_t)WPT * CT * sizeof(float), st, tr, p.nseg,
+                               n_rec, nt_in, ratio, rfx, gp, dplan, og, oe, p.seg_len, nt_out, out);
         } else if (L <= 2 * CT) {
-            hipLaunchKernelGGL(k_combine_w<2>, grid, dim3(CT), (size_t)(WPT / 2) * L * sizeof(float), st, tr, p.nseg,
-                               n_rec, nt_in, ratio, rfx, dplan, og, oe, p.seg_len, nt_out, out);
+            hipLaunchKernelGGL(k_combine_w<2>, grid, dim3(CT), (size_t)WPT * CT * sizeof(float), st, tr, p.nseg,
+                               n_rec, nt_in, ratio, rfx, gp, dplan, og, oe, p.seg_len, nt_out, out);
         } else if (L <= 4 * CT) {
-            hipLaunchKernelGGL(k_combine_w<4>, grid, dim3(CT), (size_t)(WPT / 4) * L * sizeof(float), st, tr, p.nseg,
-                               n_rec, nt_in, ratio, rfx, dplan, og, oe, p.seg_len, nt_out, out);
+            hipLaunchKernelGGL(k_combine_w<4>, grid, dim3(CT), (size_t)WPT * CT * sizeof(float), st, tr, p.nseg,
+                               n_rec, nt_in, ratio, rfx, gp, dplan, og, oe, p.seg_len, nt_out, out);
         } else {
             hipLaunchKernelGGL(k_combine, dim3(row_blocks(p.nseg, n_rec)), dim3(CT), 0, st, tr, p.nseg, n_rec, nt_in,
                                ratio, ratio_fx,
@@ -488,7 +566,7 @@ extern "C" int seis_combine(const float* tr, int n_src, int n_rec, int nt_in, do
     int rc = check_args(tr, n_src, n_rec, nt_in, dt_in, t0, n_ev, src_idx, amp, t_origin, nt_out, dt_out, out);
     if (rc || n_rec == 0 || nt_out == 0) return rc;
     Plan p;
-    make_plan(p, n_ev, src_idx, amp, t_origin, t0, nt_in, dt_in, nt_out, dt_out);
+    make_plan(p, n_rec, n_ev, src_idx, amp, t_origin, t0, nt_in, dt_in, nt_out, dt_out);
     char* dplan = nullptr;
     if (hipMalloc(&dplan, p.bytes) != hipSuccess) return cfail(PSTD_ENOMEM, "seis_combine: hipMalloc failed");
     rc = launch(p, dplan, tr, n_rec, nt_in, dt_in, t0, nt_out, dt_out, out, (hipStream_t)hip_stream);
@@ -505,7 +583,7 @@ extern "C" int seis_combine_noalloc(const float* tr, int n_src, int n_rec, int n
     int rc = check_args(tr, n_src, n_rec, nt_in, dt_in, t0, n_ev, src_idx, amp, t_origin, nt_out, dt_out, out);
     if (rc || n_rec == 0 || nt_out == 0) return rc;
     Plan p;
-    make_plan(p, n_ev, src_idx, amp, t_origin, t0, nt_in, dt_in, nt_out, dt_out);
+    make_plan(p, n_rec, n_ev, src_idx, amp, t_origin, t0, nt_in, dt_in, nt_out, dt_out);
     if (p.bytes > NOALLOC_BYTES)
         return cfail(PSTD_EINVAL, "seis_combine_noalloc: the event lists need " + std::to_string(p.bytes) +
                                       " bytes, more than the " + std::to_string(NOALLOC_BYTES) +
