@@ -258,8 +258,9 @@ const char *pstd3d_last_error(void);
  * src_idx, amp, t_origin: host arrays [n_ev].  The event lists (88 bytes per
  * event and record segment of up to 6144 samples) go to a device buffer
  * allocated and freed by the call; runs on hip_stream and returns after the
- * stream has finished.  Errors: PSTD_EINVAL (sizes, dt_out / dt_in outside
- * [2^-20, 2^20], source index out of range, non-finite value, more than 2^23
+ * stream has finished.  Errors: PSTD_EINVAL (sizes, nt_in above 2^30,
+ * dt_out / dt_in outside [2^-20, 2^20], source index out of range,
+ * non-finite value, more than 2^23
  * record segments in one call: 4 n_rec rounded up to a multiple of 8, times
  * ceil(nt_out / 6144)), PSTD_ENOMEM,
  * PSTD_EDEVICE; the message is returned by seis_combine_last_error(). */

@@ -465,6 +465,8 @@ int check_args(const float* tr, int n_src, int n_rec, int nt_in, double dt_in, c
         return cfail(PSTD_EINVAL, "seis_combine: bad sizes or sampling intervals");
     if (!(dt_out / dt_in <= 1048576.0) || !(dt_out / dt_in >= 1.0 / 1048576.0))
         return cfail(PSTD_EINVAL, "seis_combine: dt_out / dt_in outside [2^-20, 2^20]");
+    // input positions near an event stay within nt_in + 2^25 samples, in int range
+    if (nt_in > (1 << 30)) return cfail(PSTD_EINVAL, "seis_combine: nt_in above 2^30");
     if (n_rec == 0 || nt_out == 0) return PSTD_OK;
     {
         // one 1-D launch: blocks x threads must stay below 2^32 work-items

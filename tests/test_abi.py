@@ -77,12 +77,12 @@ def test_combine_validation_without_device(lib):
     t0 = (ctypes.c_double * 4)(0, 0, 0, 0)
     fake = ctypes.c_void_p(0x1000)
 
-    def call(src, amp, to, n_src=2, nt_in=10, dt_in=1e-3):
+    def call(src, amp, to, n_src=2, nt_in=10, dt_in=1e-3, n_rec=3, nt_out=20):
         s = np.ascontiguousarray(src, np.int32)
         a = np.ascontiguousarray(amp, np.float64)
         t = np.ascontiguousarray(to, np.float64)
-        return lib.seis_combine(fake, n_src, 3, nt_in, dt_in, t0, s.size, s.ctypes.data_as(ip),
-                                a.ctypes.data_as(dp), t.ctypes.data_as(dp), 20, 1e-3, fake, None)
+        return lib.seis_combine(fake, n_src, n_rec, nt_in, dt_in, t0, s.size, s.ctypes.data_as(ip),
+                                a.ctypes.data_as(dp), t.ctypes.data_as(dp), nt_out, 1e-3, fake, None)
 
     assert call([2], [1.0], [0.0]) == -1
     assert b"source index" in lib.seis_combine_last_error()
@@ -92,3 +92,8 @@ def test_combine_validation_without_device(lib):
     assert call([0], [1.0], [0.0], nt_in=0) == -1
     assert call([0], [1.0], [0.0], dt_in=0.0) == -1
     assert call([0], [1.0], [0.0], n_src=0) == -1
+    assert call([0], [1.0], [0.0], nt_in=(1 << 30) + 1) == -1
+    assert b"nt_in" in lib.seis_combine_last_error()
+    # 2^22 output rows in 2 segments of 512-thread blocks: 2^32 work-items
+    assert call([0], [1.0], [0.0], n_rec=1 << 20, nt_out=12000) == -1
+    assert b"too large" in lib.seis_combine_last_error()

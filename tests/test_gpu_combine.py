@@ -156,6 +156,35 @@ def test_staging_slot_boundaries(B, nt_in):
     check(got, ref)
 
 
+@pytest.mark.parametrize("nt_in,nt_out,ratio", [
+    (300, 1, 1.0), (300, 255, 1.0), (300, 257, 0.37), (1500, 2049, 1.0), (1500, 6144, 1.3),
+    (1500, 6145, 1.3), (300, 12289, 7.3), (1500, 3000, 0.05)])
+def test_window_and_segment_edges(B, nt_in, nt_out, ratio):
+    """Records ending inside, at and just past a wave's 256-sample window, a
+    segment (6144 samples) and two; output rates from 20 times finer to 7.3
+    times coarser than the input; dense events of few sources so that every
+    window meets event edges."""
+    import torch
+    rng = np.random.default_rng(nt_out)
+    n_src, n_rec = 3, 2
+    dt_in = 1e-3
+    dt_out = ratio * dt_in
+    tr = rng.standard_normal((n_src, 4, n_rec, nt_in)).astype(np.float32)
+    t0 = [1e-3, 0.5e-3, 0.5e-3, 0.5e-3]
+    n_ev = 40
+    src = rng.integers(0, n_src, n_ev).astype(np.int32)
+    amp = rng.lognormal(0, 1, n_ev)
+    span = nt_out * dt_out
+    to = rng.uniform(-nt_in * dt_in, span, n_ev)
+    say("combine edges", nt_in, nt_out, ratio)
+    got = B.seis_combine(torch.from_numpy(tr).cuda(), t0, src, amp, to, nt_out, dt_in, dt_out).cpu().numpy()
+    ref = oracle.combine(tr, t0, src, amp, to, nt_out, dt_in, dt_out)
+    if np.abs(ref).max() == 0:
+        assert not got.any()
+    else:
+        check(got, ref)
+
+
 def test_one_sample_traces_and_far_events(B):
     """nt_in = 1 (a trace that is one spike), events far outside the record
     (no sample touched), and repeated events of one source."""
