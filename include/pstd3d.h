@@ -255,8 +255,9 @@ const char *pstd3d_last_error(void);
  * source) and rounded once to float.
  * tr: device float [n_src][4][n_rec][nt_in]; out: device float
  * [4][n_rec][nt_out]; t0: host double[4] (time of sample 0 per component);
- * src_idx, amp, t_origin: host arrays [n_ev].  The event lists (88 bytes per
- * event and record segment of up to 6144 samples) go to a device buffer
+ * src_idx, amp, t_origin: host arrays [n_ev].  The event lists (128 bytes per
+ * event and record segment of up to 6144 samples for traces of up to 2044
+ * samples, 88 for longer ones) go to a device buffer
  * allocated and freed by the call; runs on hip_stream and returns after the
  * stream has finished.  Errors: PSTD_EINVAL (sizes, nt_in above 2^30,
  * dt_out / dt_in outside [2^-20, 2^20], source index out of range,
@@ -275,9 +276,10 @@ const char *seis_combine_last_error(void);
  * the same arguments, kernels and results, but the event lists go to a
  * static device array of seis_combine_noalloc_max_bytes() bytes (4 MiB) that
  * the library holds on each device it runs on until the process ends; the
- * call makes no device allocation.  It needs 88 bytes per (event, record
- * segment of up to 6144 samples) plus 16 per (source, segment) and a few
- * hundred bytes: about 47 000 event-segments.  Larger event lists return
+ * call makes no device allocation.  It needs 128 bytes per (event, record
+ * segment of up to 6144 samples; 88 for traces longer than 2044 samples) plus
+ * 16 per (source, segment) and a few hundred bytes: about 32 000
+ * event-segments.  Larger event lists return
  * PSTD_EINVAL before any device work (use seis_combine).  Every call on one
  * device shares its array, so calls that overlap on one device (on other
  * streams or threads) race; each call returns after its stream has finished.

@@ -66,13 +66,24 @@ struct Grp {
     int e0, e1;          // events [e0, e1) of the plan's event array
 };
 // one event of a segment: amplitude, and per component the input offset
-// (t_origin + t0[c]) / dt_in and the output samples [rng[c][0], rng[c][1])
-// it can touch
+// (t_origin + t0[c]) / dt_in, the output samples [rng[c][0], rng[c][1]) it can
+// touch and the windows of the segment they meet (the chunked kernel reads
+// these records)
 struct Ev {
     double amp;
     unsigned long long u0[4];   // -(t_origin + t0[c]) / dt_in, 32.32 fixed point
     int rng[4][2];
-    unsigned win[4];            // windows of the segment the event touches, bit w NGRP + j
+    unsigned win[4];            // bit w NGRP + j: window j of wave w
+};
+// the same for one component, as the whole-trace kernel reads it (one
+// 32-byte scalar load per event); its plan holds these component-major,
+// [4][events]
+struct EvC {
+    unsigned long long u0;
+    double amp;
+    unsigned win;
+    int lo, hi;
+    int pad;
 };
 
 // x in 32.32 fixed point modulo 2^64 (two's complement): the integer part in
@@ -94,6 +105,7 @@ struct Plan {
     std::vector<int> seg_ptr;    // [nseg + 1] into grp
     std::vector<Grp> grp;
     std::vector<Ev> ev;
+    std::vector<EvC> evc;        // [4][ev.size()]
     size_t off_ptr = 0, off_grp = 0, off_ev = 0, bytes = 0;
 };
 
@@ -174,7 +186,21 @@ void make_plan(Plan& p, int n_rec, int n_ev, const int32_t* src_idx, const doubl
     p.off_ptr = 0;
     p.off_grp = align256(p.seg_ptr.size() * sizeof(int));
     p.off_ev = p.off_grp + align256(std::max<size_t>(1, p.grp.size()) * sizeof(Grp));
-    p.bytes = p.off_ev + align256(std::max<size_t>(1, p.ev.size()) * sizeof(Ev));
+    // the whole-trace kernel reads the component-major records, the chunked
+    // kernel the per-event ones
+    const size_t n = p.ev.size();
+    p.evc.clear();
+    if (nt_in + 4 <= 4 * CT) {
+        p.evc.resize(4 * n);
+        for (int c = 0; c < 4; ++c)
+            for (size_t i = 0; i < n; ++i) {
+                const Ev& E = p.ev[i];
+                p.evc[c * n + i] = EvC{E.u0[c], E.amp, E.win[c], E.rng[c][0], E.rng[c][1], 0};
+            }
+        p.bytes = p.off_ev + align256(std::max<size_t>(1, p.evc.size()) * sizeof(EvC));
+    } else {
+        p.bytes = p.off_ev + align256(std::max<size_t>(1, n) * sizeof(Ev));
+    }
 }
 
 // Block -> (segment, receiver, component).  The chip hands consecutive
@@ -310,7 +336,7 @@ __global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(8))) void k_
 // outside the trace), nt_in + 4 values, in VPS CT floats of which each thread
 // writes VPS (VPS = 1, 2 or 4: the smallest with nt_in + 4 <= VPS CT); an item
 // is NSLOT(VPS) = WPT / VPS slots, staged from WPT registers per thread
-// (16 KB of LDS).  The loads are buffer loads whose range is the trace, so
+// (32 KB of LDS).  The loads are buffer loads whose range is the trace, so
 // the positions outside it read zero and staging needs no branch, clamp or
 // select.
 //
@@ -320,7 +346,7 @@ __global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(8))) void k_
 // on at most one partly covered window of WSPAN samples at either end, where
 // runs of SPT samples per thread would waste up to a wave's 64 SPT, and a
 // wave that the event misses pays one scalar test for it.
-constexpr int WPT = 8;
+constexpr int WPT = 16;
 // buffer resource word 3 for raw 32-bit loads on this chip family
 constexpr int BUF_DW3 = 0x00020000;
 
@@ -335,7 +361,7 @@ __host__ __device__ constexpr int w_slot(int nt_in) { return nt_in + 4; }
 template <int VPS>
 __global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(8))) void k_combine_w(
     const float* __restrict__ tr, int nseg, int n_rec, int nt_in, double ratio, unsigned long long ratio_fx,
-    GroupPos gp, const char* __restrict__ plan, long off_grp, long off_ev, int seg_len, int nt_out,
+    GroupPos gp, const char* __restrict__ plan, long off_grp, long off_ev, int n_evp, int seg_len, int nt_out,
     float* __restrict__ out)
 {
     constexpr int NSLOT = WPT / VPS;
@@ -351,7 +377,7 @@ __global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(8))) void k_
     const int wsh = (__builtin_amdgcn_readfirstlane(tid) / 64) * NGRP;
     const int* __restrict__ seg_ptr = reinterpret_cast<const int*>(plan);
     const Grp* __restrict__ grp = reinterpret_cast<const Grp*>(plan + off_grp);
-    const Ev* __restrict__ ev = reinterpret_cast<const Ev*>(plan + off_ev);
+    const EvC* __restrict__ ev = reinterpret_cast<const EvC*>(plan + off_ev) + (long)c * n_evp;
     // this block's row (c, r) of source 0; a group adds its source's offset
     const float* __restrict__ rowp = tr + ((long)c * n_rec + r) * nt_in;
     double acc[SPT];
@@ -404,12 +430,15 @@ __global__ __launch_bounds__(CT) __attribute__((amdgpu_waves_per_eu(8))) void k_
             const Grp G = grp[gb + gi];
             const float* __restrict__ x = stw + gi * S;
             for (int e = G.e0; e < G.e1; ++e) {
-                const Ev& E = ev[e];
+                const EvC E = ev[e];
+                // one round trip for the whole record: make its fields live
+                // before the test below uses the mask
+                asm volatile("" ::"s"(E.u0), "s"(E.amp), "s"(E.win));
                 // this wave's windows that the event touches
-                const unsigned wm = (E.win[c] >> wsh) & ((1u << NGRP) - 1);
+                const unsigned wm = (E.win >> wsh) & ((1u << NGRP) - 1);
                 if (!wm) continue;
                 const double amp = E.amp;
-                const unsigned long long ue = T + E.u0[c];
+                const unsigned long long ue = T + E.u0;
 #pragma unroll
                 for (int j = 0; j < NGRP; ++j) {
                     if (!(wm >> j & 1)) continue;
@@ -497,7 +526,10 @@ int launch(const Plan& p, char* dplan, const float* tr, int n_rec, int nt_in, do
     if (ok && !p.grp.empty())
         ok = hipMemcpyAsync(dplan + p.off_grp, p.grp.data(), p.grp.size() * sizeof(Grp), hipMemcpyHostToDevice,
                             st) == hipSuccess;
-    if (ok && !p.ev.empty())
+    if (ok && !p.evc.empty())
+        ok = hipMemcpyAsync(dplan + p.off_ev, p.evc.data(), p.evc.size() * sizeof(EvC), hipMemcpyHostToDevice, st) ==
+             hipSuccess;
+    else if (ok && !p.ev.empty())
         ok = hipMemcpyAsync(dplan + p.off_ev, p.ev.data(), p.ev.size() * sizeof(Ev), hipMemcpyHostToDevice, st) ==
              hipSuccess;
     if (ok) {
@@ -507,17 +539,18 @@ int launch(const Plan& p, char* dplan, const float* tr, int n_rec, int nt_in, do
         const dim3 grid(row_blocks(p.nseg, n_rec));
         const unsigned long long rfx = (unsigned long long)ratio_fx;
         const long og = (long)p.off_grp, oe = (long)p.off_ev;
+        const int nev = (int)p.ev.size();
         GroupPos gp;
         for (int j = 0; j < NGRP; ++j) gp.d[j] = to_fx((double)j * GSPAN * ratio + 2.0);
         if (L <= CT) {
             hipLaunchKernelGGL(k_combine_w<1>, grid, dim3(CT), (size_t)WPT * CT * sizeof(float), st, tr, p.nseg,
-                               n_rec, nt_in, ratio, rfx, gp, dplan, og, oe, p.seg_len, nt_out, out);
+                               n_rec, nt_in, ratio, rfx, gp, dplan, og, oe, nev, p.seg_len, nt_out, out);
         } else if (L <= 2 * CT) {
             hipLaunchKernelGGL(k_combine_w<2>, grid, dim3(CT), (size_t)WPT * CT * sizeof(float), st, tr, p.nseg,
-                               n_rec, nt_in, ratio, rfx, gp, dplan, og, oe, p.seg_len, nt_out, out);
+                               n_rec, nt_in, ratio, rfx, gp, dplan, og, oe, nev, p.seg_len, nt_out, out);
         } else if (L <= 4 * CT) {
             hipLaunchKernelGGL(k_combine_w<4>, grid, dim3(CT), (size_t)WPT * CT * sizeof(float), st, tr, p.nseg,
-                               n_rec, nt_in, ratio, rfx, gp, dplan, og, oe, p.seg_len, nt_out, out);
+                               n_rec, nt_in, ratio, rfx, gp, dplan, og, oe, nev, p.seg_len, nt_out, out);
         } else {
             hipLaunchKernelGGL(k_combine, dim3(row_blocks(p.nseg, n_rec)), dim3(CT), 0, st, tr, p.nseg, n_rec, nt_in,
                                ratio, ratio_fx,
