@@ -144,13 +144,22 @@ int pstd3d_run_many(pstd3d_ctx *const *ctxs, int n, int nt, float *const *traces
  * F = pstd3d_state_fields: the 24 split fields in the order vx(x,y,z)
  * vy(x,y,z) vz(x,y,z) sxx(x,y,z) syy(x,y,z) szz(x,y,z) sxy(x,y) sxz(x,z)
  * syz(y,z), then with viscosity the previous step's D-x vx, D-y vy, D-z vz,
- * Dx+ vy, Dy+ vx, Dx+ vz, Dz+ vx, Dy+ vz, Dz+ vy) to host memory. */
+ * Dx+ vy, Dy+ vx, Dx+ vz, Dz+ vx, Dy+ vz, Dz+ vy) to host memory.
+ * The split into parts only matters where the absorbing layer damps (Sec.
+ * II-B): in the undamped cells (pstd3d_undamped_range) each field's whole
+ * value sits in its first part and the other parts are zero. */
 int pstd3d_get_state(pstd3d_ctx *c, int shot, float *fields_host);
 /* Restore shot `shot`'s split fields from host memory and set the step index
- * of the context (the wavelet sample used by the next step). */
+ * of the context (the wavelet sample used by the next step).  In the
+ * undamped cells the parts of each field are summed into its first part. */
 int pstd3d_set_state(pstd3d_ctx *c, int shot, const float *fields_host, long step);
 /* Step index of the next step. */
 long pstd3d_step(const pstd3d_ctx *c);
+/* The undamped cells: those with lo[d] <= index <= hi[d] on every axis d
+ * (x, y, z), where every absorbing-layer factor of the split update is
+ * exactly 1 (hi[d] < lo[d]: none).  The update kernels read and write only
+ * the first split part of each field there.  PSTD_EINVAL for NULL. */
+int pstd3d_undamped_range(const pstd3d_ctx *c, int lo[3], int hi[3]);
 
 /* Debug / test entry: the nine staggered spectral derivatives of one phase,
  * computed with the same kernels as a time step.  phase 0: in = 6 device

@@ -46,6 +46,8 @@ _L.pstd3d_get_state.argtypes = [C.c_void_p, C.c_int, _fp]
 _L.pstd3d_set_state.argtypes = [C.c_void_p, C.c_int, _fp, C.c_long]
 _L.pstd3d_step.argtypes = [C.c_void_p]
 _L.pstd3d_step.restype = C.c_long
+_L.pstd3d_undamped_range.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+_L.pstd3d_undamped_range.restype = C.c_int
 _L.pstd3d_derivs.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p]
 _L.pstd3d_reset.argtypes = [C.c_void_p, C.c_void_p]
 _L.pstd3d_profile.argtypes = [C.c_void_p, C.c_int]
@@ -229,6 +231,13 @@ class Solver:
     @property
     def step(self):
         return _L.pstd3d_step(self._h)
+
+    def undamped_range(self):
+        """(lo, hi): per axis (x, y, z) the index range of the undamped cells,
+        where each field's value sits in its first split part."""
+        lo, hi = (C.c_int * 3)(), (C.c_int * 3)()
+        _check(_L.pstd3d_undamped_range(self._h, lo, hi), "pstd3d_undamped_range")
+        return tuple(lo), tuple(hi)
 
     def derivs(self, phase, fields, stream=None):
         """Nine staggered spectral derivatives of one phase (see include/pstd3d.h)."""

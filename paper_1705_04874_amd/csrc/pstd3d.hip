@@ -565,6 +565,21 @@ int build_model(pstd3d_ctx* c, const pstd3d_model* m)
         c->P.ah[d] = c->pmlb + off[d][1];
         c->P.bi[d] = c->pmlb + off[d][2];
         c->P.bh[d] = c->pmlb + off[d][3];
+        // the undamped index range of this axis: all four factors exactly 1
+        // (one interval, the axis minus its two absorbing layers; empty if
+        // the flags do not form one)
+        auto flat = [&](int i) {
+            for (int kind = 0; kind < 4; ++kind)
+                if (hp[off[d][kind] + i] != 1.0f) return false;
+            return true;
+        };
+        int lo = 0, hi = N[d] - 1;
+        while (lo < N[d] && !flat(lo)) ++lo;
+        while (hi >= lo && !flat(hi)) --hi;
+        bool one = true;
+        for (int i = lo; i <= hi; ++i) one = one && flat(i);
+        c->P.flo[d] = one ? lo : 0;
+        c->P.fhi[d] = one ? hi : -1;
     }
 
     // twiddles exp(-2 pi i e / N) per axis
@@ -862,6 +877,28 @@ int autotune(pstd3d_ctx* c)
     c->apply();
     c->tuned = true;
     return PSTD_OK;
+}
+
+// In the undamped cells (inside P.flo .. P.fhi on every axis) sum each
+// field's split parts into its first part and zero the others: the form the
+// update kernels keep there.  fields: one shot's host state [24 + ...][n].
+void collapse_undamped(const pstd3d_ctx* c, float* fields)
+{
+    const long n = (long)c->nx * c->ny * c->nz;
+    // first part and part count of the nine fields: vx vy vz sxx syy szz sxy sxz syz
+    const int first[9] = {0, 3, 6, 9, 12, 15, 18, 20, 22};
+    const int cnt[9] = {3, 3, 3, 3, 3, 3, 2, 2, 2};
+    for (int z = c->P.flo[2]; z <= c->P.fhi[2]; ++z)
+        for (int y = c->P.flo[1]; y <= c->P.fhi[1]; ++y)
+            for (int x = c->P.flo[0]; x <= c->P.fhi[0]; ++x) {
+                const long cell = ((long)z * c->ny + y) * c->nx + x;
+                for (int f = 0; f < 9; ++f) {
+                    float sum = 0.f;
+                    for (int k = 0; k < cnt[f]; ++k) sum += fields[(first[f] + k) * n + cell];
+                    fields[first[f] * n + cell] = sum;
+                    for (int k = 1; k < cnt[f]; ++k) fields[(first[f] + k) * n + cell] = 0.f;
+                }
+            }
 }
 
 // Recompute the x-transformed stress sums from the split fields.
@@ -1312,7 +1349,10 @@ int pstd3d_set_state(pstd3d_ctx* c, int shot, const float* fields_host, long ste
         return fail(PSTD_EINVAL, "bad arguments");
     HIP_TRY(hipSetDevice(c->device));
     HIP_TRY(hipDeviceSynchronize());
-    HIP_TRY(hipMemcpy(c->fields + (size_t)shot * c->g.fstride, fields_host, c->g.fstride * sizeof(float),
+    // undamped cells keep each field's whole value in its first split part
+    std::vector<float> st(fields_host, fields_host + c->g.fstride);
+    collapse_undamped(c, st.data());
+    HIP_TRY(hipMemcpy(c->fields + (size_t)shot * c->g.fstride, st.data(), c->g.fstride * sizeof(float),
                       hipMemcpyHostToDevice));
     enqueue_restore_spectra(c, nullptr);
     const int s32 = (int)step;
@@ -1323,6 +1363,16 @@ int pstd3d_set_state(pstd3d_ctx* c, int shot, const float* fields_host, long ste
 }
 
 long pstd3d_step(const pstd3d_ctx* c) { return c ? c->step : -1; }
+
+int pstd3d_undamped_range(const pstd3d_ctx* c, int lo[3], int hi[3])
+{
+    if (!c || !lo || !hi) return fail(PSTD_EINVAL, "bad arguments");
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = c->P.flo[d];
+        hi[d] = c->P.fhi[d];
+    }
+    return PSTD_OK;
+}
 
 int pstd3d_derivs(pstd3d_ctx* c, int phase, const float* in_dev, float* out_dev, void* hip_stream)
 {

@@ -52,7 +52,17 @@ struct Pml {
     const float* ah[3];
     const float* bi[3];
     const float* bh[3];
+    // per axis, the indices [flo, fhi] whose four factors are all exactly 1:
+    // a cell inside all three ranges is undamped, and there each field keeps
+    // its whole value in its first split part (the others stay zero)
+    int flo[3] = {0, 0, 0}, fhi[3] = {-1, -1, -1};
 };
+
+__device__ __forceinline__ bool undamped(const Pml& pm, int x, int y, int z)
+{
+    return x >= pm.flo[0] && x <= pm.fhi[0] && y >= pm.flo[1] && y <= pm.fhi[1] && z >= pm.flo[2] &&
+           z <= pm.fhi[2];
+}
 
 struct Rec {
     const int* ptr;     // [nrows + 1] receivers sorted by row
@@ -274,7 +284,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vel_waves<NX
     // all loads of the update before any store: the split parts share one
     // base pointer, so interleaved stores would serialise later loads
     float vp[CPT][9], dtr[CPT][3], a[CPT][3][3];
-    bool ok[CPT];
+    bool ok[CPT], in[CPT];
     long cell[CPT];
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
@@ -285,6 +295,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vel_waves<NX
         const int rr = ok[i] ? row : row0;
         const int y = rr % g.ny, z = rr / g.ny;
         cell[i] = (long)rr * NX + x;
+        in[i] = undamped(pm, x, y, z);
         const float axi = pm.ai[0][x], axh = pm.ah[0][x];
         const float ayi = pm.ai[1][y], ayh = pm.ah[1][y];
         const float azi = pm.ai[2][z], azh = pm.ah[2][z];
@@ -296,8 +307,9 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vel_waves<NX
         a[i][0][0] = axh * byi * bzi; a[i][0][1] = ayi * bxh * bzi; a[i][0][2] = azi * bxh * byi;
         a[i][1][0] = axi * byh * bzi; a[i][1][1] = ayh * bxi * bzi; a[i][1][2] = azi * bxi * byh;
         a[i][2][0] = axi * byi * bzh; a[i][2][1] = ayi * bxi * bzh; a[i][2][2] = azh * bxi * byi;
+        // an undamped cell reads only the first part of each component
 #pragma unroll
-        for (int q = 0; q < 9; ++q) vp[i][q] = ok[i] ? F[(long)q * g.n + cell[i]] : 0.f;
+        for (int q = 0; q < 9; ++q) vp[i][q] = ok[i] && (q % 3 == 0 || !in[i]) ? F[(long)q * g.n + cell[i]] : 0.f;
 #pragma unroll
         for (int comp = 0; comp < 3; ++comp) dtr[i][comp] = ok[i] ? m.dtr[comp][cell[i]] : 0.f;
     }
@@ -319,10 +331,13 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vel_waves<NX
                 acc += vp[i][q];
             }
             vsum[i][comp] = acc;
+            // undamped: the parts' factors are 1, their sum is the component
+            if (in[i]) vp[i][3 * comp] = acc;
         }
         if (ok[i]) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q) F[(long)q * g.n + cell[i]] = vp[i][q];
+            for (int q = 0; q < 9; ++q)
+                if (q % 3 == 0 || !in[i]) F[(long)q * g.n + cell[i]] = vp[i][q];
         }
     }
     __syncthreads();
@@ -357,6 +372,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(vel_waves<NX
 // S phase tail: inverse x FFT of the 9 velocity derivatives, stress split-PML
 // update (eq. 2 first line), source injection, receiver p (eq. 3), x FFT of
 // the 6 summed stresses.
+// the first split part of a stress component (parts 0-8: three per normal
+// component, 9-14: two per shear component)
+__host__ __device__ constexpr bool first_part(int q) { return q < 9 ? q % 3 == 0 : (q - 9) % 2 == 0; }
+
 // slot of velocity derivative q (order of e[] in k_str) among the nine stored ones
 __host__ __device__ constexpr int ep_slot(int q) { return q < 3 ? q : ((q - 3) ^ 1) + 3; }
 
@@ -395,7 +414,7 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
     float sp[CPT][15], mt[CPT][5], fa[CPT][9];
     float ep[VISC ? CPT : 1][9], vm[VISC ? CPT : 1][5];
     int jr[CPT][2];
-    bool ok[CPT];
+    bool ok[CPT], in[CPT];
 #pragma unroll
     for (int i = 0; i < CPT; ++i) {
         const int c = threadIdx.x + i * NT;
@@ -405,8 +424,10 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
         const int rr = ok[i] ? row : row0;
         const int y = rr % g.ny, z = rr / g.ny;
         const long cell = (long)rr * NX + x;
+        in[i] = undamped(pm, x, y, z);
+        // an undamped cell reads only the first part of each component
 #pragma unroll
-        for (int q = 0; q < 15; ++q) sp[i][q] = F[(long)q * g.n + cell];
+        for (int q = 0; q < 15; ++q) sp[i][q] = first_part(q) || !in[i] ? F[(long)q * g.n + cell] : 0.f;
         mt[i][0] = m.dlam[cell];
         mt[i][1] = m.dmu2[cell];
         mt[i][2] = m.dmus[0][cell];
@@ -510,14 +531,24 @@ __global__ __launch_bounds__(NT) void k_str(Geo g, Mat m, Pml pm, const float2* 
                     if (q.y == f) sp[i][f] += val;
             }
         }
-#pragma unroll
-        for (int q = 0; q < 15; ++q) F[(long)q * g.n + cell] = sp[i][q];
         ssum[i][0] = sp[i][0] + sp[i][1] + sp[i][2];
         ssum[i][1] = sp[i][3] + sp[i][4] + sp[i][5];
         ssum[i][2] = sp[i][6] + sp[i][7] + sp[i][8];
         ssum[i][3] = sp[i][9] + sp[i][10];
         ssum[i][4] = sp[i][11] + sp[i][12];
         ssum[i][5] = sp[i][13] + sp[i][14];
+        if (in[i]) {
+            // undamped: the parts' factors are 1, their sum is the component
+            sp[i][0] = ssum[i][0];
+            sp[i][3] = ssum[i][1];
+            sp[i][6] = ssum[i][2];
+            sp[i][9] = ssum[i][3];
+            sp[i][11] = ssum[i][4];
+            sp[i][13] = ssum[i][5];
+        }
+#pragma unroll
+        for (int q = 0; q < 15; ++q)
+            if (first_part(q) || !in[i]) F[(long)q * g.n + cell] = sp[i][q];
     }
     __syncthreads();
 #pragma unroll

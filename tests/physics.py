@@ -88,6 +88,48 @@ def summed(state):
     return v + s + sh
 
 
+# first split part and part count of vx vy vz sxx syy szz sxy sxz syz
+FIELD_PARTS = [("vx", 0, 3), ("vy", 3, 3), ("vz", 6, 3), ("sxx", 9, 3), ("syy", 12, 3), ("szz", 15, 3),
+               ("sxy", 18, 2), ("sxz", 20, 2), ("syz", 22, 2)]
+
+
+def undamped_mask(shape, lo, hi):
+    """Boolean [nz][ny][nx]: the cells with lo[d] <= index <= hi[d] on every
+    axis d = (x, y, z), where the absorbing layer leaves the split update
+    undamped."""
+    nz, ny, nx = shape
+    mx = (np.arange(nx) >= lo[0]) & (np.arange(nx) <= hi[0])
+    my = (np.arange(ny) >= lo[1]) & (np.arange(ny) <= hi[1])
+    mz = (np.arange(nz) >= lo[2]) & (np.arange(nz) <= hi[2])
+    return mz[:, None, None] & my[None, :, None] & mx[None, None, :]
+
+
+def collapse_undamped(state, mask):
+    """The split state as the GPU keeps it: in the cells of `mask` each field's
+    parts summed into its first part and the others zero (state [F][...] with
+    the 24 split parts first; mask of the trailing shape)."""
+    st = np.array(state, dtype=np.float64, copy=True)
+    for _, f0, n in FIELD_PARTS:
+        tot = st[f0:f0 + n][:, mask].sum(axis=0)
+        st[f0][mask] = tot
+        for k in range(1, n):
+            st[f0 + k][mask] = 0.0
+    return st
+
+
+def split_errors(got, ref):
+    """Per field: (name, rel-L2 of the field (sum of its parts), largest
+    rel-L2 of one part on the scale of the field's norm) of got against ref."""
+    out = []
+    for name, f0, n in FIELD_PARTS:
+        fr = ref[f0:f0 + n].sum(axis=0)
+        nf = float(np.linalg.norm(fr))
+        ef = float(np.linalg.norm(got[f0:f0 + n].astype(np.float64).sum(axis=0) - fr)) / nf
+        ep = max(float(np.linalg.norm(got[f0 + k].astype(np.float64) - ref[f0 + k])) / nf for k in range(n))
+        out.append((name, ef, ep))
+    return out
+
+
 def staggered_materials(vp, vs, rho):
     """rho at velocity nodes, lam/mu at centres and mu at shear nodes, with the
     same averaging reading the solvers take (arithmetic rho, harmonic mu)."""

@@ -386,7 +386,11 @@ def test_kelvin_voigt_state_matches_oracle_and_checkpoints(B):
     o.run(40)
     ref = o.get_state()
     o.close()
-    for f in range(33):
+    # the undamped cells keep each field in its first split part
+    ref = physics.collapse_undamped(ref, physics.undamped_mask(ref.shape[1:], *s.undamped_range()))
+    for name, ef, ep in physics.split_errors(st, ref):
+        assert ef <= TOL and ep <= TOL, (name, ef, ep)
+    for f in range(24, 33):
         e = rel(st[f], ref[f])
         assert e <= TOL, (f, e)
     s2 = B.Solver.from_workload(w)
