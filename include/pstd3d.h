@@ -151,7 +151,8 @@ int pstd3d_run_many(pstd3d_ctx *const *ctxs, int n, int nt, float *const *traces
 int pstd3d_get_state(pstd3d_ctx *c, int shot, float *fields_host);
 /* Restore shot `shot`'s split fields from host memory and set the step index
  * of the context (the wavelet sample used by the next step).  In the
- * undamped cells the parts of each field are summed into its first part. */
+ * undamped cells the parts of each field are summed into its first part
+ * (in a host copy of the state: PSTD_ENOMEM if that allocation fails). */
 int pstd3d_set_state(pstd3d_ctx *c, int shot, const float *fields_host, long step);
 /* Step index of the next step. */
 long pstd3d_step(const pstd3d_ctx *c);

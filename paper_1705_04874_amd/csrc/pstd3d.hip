@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <string>
+#include <new>
 #include <vector>
 
 #include "pstd3d.h"
@@ -1350,7 +1351,13 @@ int pstd3d_set_state(pstd3d_ctx* c, int shot, const float* fields_host, long ste
     HIP_TRY(hipSetDevice(c->device));
     HIP_TRY(hipDeviceSynchronize());
     // undamped cells keep each field's whole value in its first split part
-    std::vector<float> st(fields_host, fields_host + c->g.fstride);
+    // (summed in a host copy: the caller's buffer is const)
+    std::vector<float> st;
+    try {
+        st.assign(fields_host, fields_host + c->g.fstride);
+    } catch (const std::bad_alloc&) {
+        return fail(PSTD_ENOMEM, "pstd3d_set_state: host copy of the state");
+    }
     collapse_undamped(c, st.data());
     HIP_TRY(hipMemcpy(c->fields + (size_t)shot * c->g.fstride, st.data(), c->g.fstride * sizeof(float),
                       hipMemcpyHostToDevice));
