@@ -154,6 +154,38 @@ def test_run_is_stateful_and_checkpoint_is_exact(B):
     np.testing.assert_array_equal(c, b)
 
 
+def test_undamped_cells_hold_each_field_in_its_first_part(B):
+    """The cells the absorbing layer leaves undamped (every factor of the split
+    update exactly 1) are those with every index in [pml, n - 2 - pml] (at
+    pml - 1 and n - 1 - pml a half node is damped), all cells without a layer.
+    After a run they hold each field in its first split part, the other parts
+    exactly zero; set_state sums a given state's parts there and leaves the
+    damped cells as given."""
+    w = small_workload(nt=60, shots=1)
+    nz, ny, nx = w.model.shape
+    L = w.pml
+    s = B.Solver.from_workload(w)
+    lo, hi = s.undamped_range()
+    assert lo == (L, L, L) and hi == (nx - 2 - L, ny - 2 - L, nz - 2 - L), (lo, hi)
+    mask = physics.undamped_mask(w.model.shape, lo, hi)
+    s.set_workload_sources(w)
+    s.run(w.nt)
+    st = s.get_state()
+    for _, f0, n in physics.FIELD_PARTS:
+        assert np.abs(st[f0][mask]).max() > 0
+        for k in range(1, n):
+            assert not st[f0 + k][mask].any()
+    given = np.random.default_rng(5).standard_normal(st.shape).astype(np.float32)
+    s.set_state(given, 0)
+    back = s.get_state()
+    np.testing.assert_allclose(back, physics.collapse_undamped(given, mask), rtol=0, atol=1e-6)
+    np.testing.assert_array_equal(back[:, ~mask], given[:, ~mask])
+    s.close()
+    n0 = B.Solver(w.model.vp, w.model.vs, w.model.rho, w.d, w.dt, pml=0)
+    assert n0.undamped_range() == ((0, 0, 0), (nx - 1, ny - 1, nz - 1))
+    n0.close()
+
+
 @pytest.mark.parametrize("wave", ["P", "S"])
 def test_plane_wave(B, wave):
     shape = (24, 20, 32)
