@@ -114,3 +114,51 @@ def test_pml_reflection_is_below_minus_40_db():
     weak = reflection_db(0.5)
     assert max(weak) > -30.0, weak
     assert all(w > x + 15.0 for w, x in zip(weak, db)), (weak, db)
+
+
+def test_undamped_cells_need_only_the_sum_of_their_split_parts():
+    """Where every factor of the split update is exactly 1 the parts of a field
+    evolve without damping and only their sum enters the physics: summing them
+    into the first part there (the form the GPU keeps) and zeroing the others
+    leaves every field of the oracle's run unchanged to FP64 rounding over
+    further steps, and those cells are exactly the box [L, n - 2 - L] on every
+    axis of the profile above (at L - 1 and n - 1 - L a half node is damped)."""
+    from tests import physics
+    nz, ny, nx = 22, 20, 26
+    L, A, dt = 5, 2.0, 0.8e-3
+    N = (nx, ny, nz)
+    rng = np.random.default_rng(9)
+    vp = 2500.0 + 300.0 * rng.random((nz, ny, nx))
+    vs = vp / 1.8
+    rho = 2000.0 + 100.0 * rng.random((nz, ny, nx))
+    c_ref = float(vp.max())
+    # undamped along an axis: the integer and the half node of the index both have alpha = 0
+    flat = [np.array([alpha(i, n, L, A, c_ref, 10.0) == 0.0 and alpha(i + 0.5, n, L, A, c_ref, 10.0) == 0.0
+                      for i in range(n)]) for n in N]
+    lo = tuple(int(np.argmax(f)) for f in flat)
+    hi = tuple(int(len(f) - 1 - np.argmax(f[::-1])) for f in flat)
+    assert lo == (L, L, L) and hi == (nx - 2 - L, ny - 2 - L, nz - 2 - L)
+    assert all(f[l:h + 1].all() and not f[:l].any() and not f[h + 1:].any() for f, l, h in zip(flat, lo, hi))
+    mask = physics.undamped_mask((nz, ny, nx), lo, hi)
+    m6 = inputs.random_dc(rng, 1000.0)[None]
+
+    def solver():
+        s = oracle.Solver(vp, vs, rho, (10.0, 10.0, 10.0), dt, pml=L, pml_A=A, pml_p=0.1, kspace=1, c_ref=c_ref,
+                          rec=np.array([[nx // 2, ny // 2, 3], [L + 1, ny // 2, nz // 2]], np.int32))
+        s.set_sources(np.array([[nx // 2 + 2, ny // 2 - 1, nz // 2]]), m6, inputs.ricker(40.0, dt, 120)[None])
+        return s
+
+    a = solver()
+    a.run(40)
+    st = a.get_state()
+    b = solver()
+    b.set_state(physics.collapse_undamped(st, mask))
+    b.step = 40
+    assert np.abs(st[1][mask]).max() > 0           # the uncollapsed state does split the interior
+    tra, trb = a.run(60), b.run(60)
+    sa, sb = physics.summed(a.get_state()), physics.summed(b.get_state())
+    for fa, fb in zip(sa, sb):
+        assert np.abs(fa - fb).max() <= 1e-12 * np.abs(fa).max()
+    assert np.abs(tra - trb).max() <= 1e-12 * np.abs(tra).max()
+    a.close()
+    b.close()
